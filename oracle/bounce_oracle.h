@@ -1,0 +1,138 @@
+/*
+ * bounce_oracle.h -- plain FP64 CPU oracle of the BOUNCE velocity-jump process.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the reference the GPU path is
+ * checked against; it is called by the test-suite, by the entry module's smoke
+ * check and by the benchmark's CPU-baseline leg, and by nothing else.  It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * Everything is written for clarity, not speed: brute-force pair searches,
+ * double precision throughout, one obvious loop per formula.  Each function
+ * names the passage of Monmarche, Weisman, Lagardere & Piquemal,
+ * "Velocity jump processes: an alternative to multi-timestep methods for faster
+ * and accurate molecular dynamics simulations" (arXiv:2002.07109) it follows.
+ *
+ * Units: Angstrom, fs, amu, kcal/mol, e.  "Gradient" means nabla E (the paper's
+ * F_i are gradients, so the force is minus what is returned here).
+ */
+#ifndef BOUNCE_ORACLE_H
+#define BOUNCE_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXT 8
+
+/* physical constants (proposed readings: the paper does not state units) */
+#define ORC_KE 332.0637          /* Coulomb constant, kcal A / (mol e^2) */
+#define ORC_KB 0.0019872041      /* Boltzmann constant, kcal / (mol K)   */
+#define ORC_ACC 4.184e-4         /* (kcal/mol/A)/amu -> A/fs^2            */
+
+enum { ORC_BOUNCE = 0, ORC_BAOAB = 1 };
+enum { ORC_COUL_BARE = 0, ORC_COUL_EWALD = 1 };
+/* random-stream phases (counter word 1 = phase << 32 | atom) */
+enum { ORC_PH_JA = 0, ORC_PH_O = 1, ORC_PH_JB = 2 };
+/* gradient components */
+enum { ORC_G_BONDED = 1, ORC_G_SHORT = 2, ORC_G_LONG = 4, ORC_G_FULL = 8 };
+/* status codes (same meaning as the GPU library's) */
+enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_SKIN = -4, ORC_E_BOUND = -5,
+       ORC_E_POISSON_CAP = -6, ORC_E_NONFINITE = -7, ORC_E_GRID = -9 };
+
+typedef struct {
+    int32_t integrator;        /* ORC_BOUNCE (B J A O A J B) or ORC_BAOAB           */
+    int32_t coulomb;           /* ORC_COUL_BARE (1/r) or ORC_COUL_EWALD (erfc(a r)/r) */
+    int32_t periodic;          /* 1: orthorhombic box, minimum image                */
+    int32_t n_types;
+    int32_t rebuild_interval;  /* lists rebuilt at q_n when n % K == 0              */
+    int32_t max_proposals;     /* Poisson cap per atom per half step                */
+    double dt, gamma, temperature;          /* fs, 1/fs, K                          */
+    double r_on, r_off, r_cut, skin;        /* r', r'', cutoff, Verlet skin (A)     */
+    double ewald_alpha;                     /* 1/A                                  */
+    double bound_scale;                     /* rate bound used = bound_scale * L    */
+    double box[3];
+    double cell_size;                       /* canonical-order cell grid            */
+    double grid_origin[3];                  /* droplet grid                         */
+    int32_t grid_dims[3];
+    int32_t pad0;
+    uint64_t seed, replica;                 /* Philox key                           */
+    double charge[ORC_MAXT], eps[ORC_MAXT], sigma[ORC_MAXT];
+} orc_params;
+
+typedef struct {
+    int32_t n_atoms;
+    int32_t n_bonds, n_angles, n_excl;
+    const int32_t *type;       /* [n]       */
+    const double *mass;        /* [n]       */
+    const int32_t *bonds;      /* [nb][2]   */
+    const double *bond_k, *bond_r0;
+    const int32_t *angles;     /* [na][3], vertex in the middle */
+    const double *angle_k, *angle_t0;
+    const int32_t *excl;       /* [ne][2] excluded nonbonded pairs */
+} orc_topology;
+
+typedef struct {
+    int64_t proposals, accepted, bound_violations, rebuilds, pair_evals, steps;
+} orc_counters;
+
+typedef struct {
+    int64_t step;
+    int32_t phase, atom, k, partner, accepted, pad;
+} orc_event;
+
+/* Philox4x64-10 block (Salmon et al., SC'11). */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double orc_u01(uint64_t w);
+uint64_t orc_umulh(uint64_t a, uint64_t b);
+
+/* pair potential u, shifted-force W_sf and switch chi */
+void orc_pair_u(const orc_params *p, int a, int b, double r, double *u, double *du);
+void orc_pair_wsf(const orc_params *p, int a, int b, double r, double *w, double *dw);
+double orc_chi(const orc_params *p, double r);
+/* L_ab >= sup |chi W'_sf| per type pair (n_types x n_types) and L_a = max_b L_ab */
+void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a);
+/* reflection of v on F (scalar mass) */
+void orc_reflect(const double v[3], const double F[3], double out[3]);
+
+/* canonical atom order: ascending (cell, atom id); returns ORC_E_GRID if an atom
+   is outside a droplet grid.  order[k] = atom at sorted position k. */
+int orc_sort_order(const orc_params *p, int32_t n, const double *q, int32_t *order, int64_t *cell);
+/* per-atom lists: j != i, not excluded, rmin <= |d| < rmax (no lower bound if
+   rmin <= 0), rows in canonical order.  Returns total entries or -1 if > cap. */
+int64_t orc_build_list(const orc_params *p, const orc_topology *t, const double *q,
+                       double rmin, double rmax, const int32_t *order,
+                       int64_t *row_ptr, int32_t *col, int64_t cap);
+/* one row of the same list, for sampled checks at large N */
+int32_t orc_list_row(const orc_params *p, const orc_topology *t, const double *q,
+                     double rmin, double rmax, const int32_t *order, int32_t i,
+                     int32_t *col, int32_t cap);
+
+/* gradient components (sum of the ORC_G_* bits in which), brute force */
+void orc_gradient(const orc_params *p, const orc_topology *t, const double *q, int which, double *g);
+void orc_gradient_atom(const orc_params *p, const orc_topology *t, const double *q, int which,
+                       int32_t i, double g[3]);
+/* E_bond, E_angle, E_coul, E_lj, E_pair, E_kin, T_kin */
+void orc_energies(const orc_params *p, const orc_topology *t, const double *q, const double *v,
+                  double out[7]);
+
+/* one J half-step (velocities only) over all atoms at fixed q with given
+   candidate lists; step/phase select the random stream. */
+int orc_jump_halfstep(const orc_params *p, const orc_topology *t, const double *q, double *v,
+                      const int64_t *row_ptr, const int32_t *col, int64_t step, int32_t phase,
+                      orc_event *ev, int64_t ev_cap, int64_t *n_ev, orc_counters *cnt);
+
+/* nsteps of BOUNCE or BAOAB from (q,v) at step0, lists built at the first step
+   and whenever n % K == 0.  q, v updated in place. */
+int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, int64_t step0,
+            int32_t nsteps, orc_event *ev, int64_t ev_cap, int64_t *n_ev, orc_counters *cnt);
+
+/* direct-space energy sum_{i<j, not excluded, r<rc} W_sf and its gradients with
+   respect to positions and per-type charge, epsilon, sigma (NULL = skip). */
+double orc_direct_energy(const orc_params *p, const orc_topology *t, const double *q,
+                         double *grad_q, double *grad_charge, double *grad_eps, double *grad_sigma);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
