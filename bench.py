@@ -1,0 +1,218 @@
+#!/usr/bin/env python
+"""Throughput of BOUNCE against BAOAB (both at 1 fs) on one MI355X.
+
+Workload: the periodic 24,000-atom water box (8,000 flexible 3-site waters in a
+62 A cube, 1 g/cm^3), real-space Ewald erfc Coulomb (alpha = 0.45/A) + LJ with
+a 9 A shifted-force cutoff and a 2 A Verlet skin, FP32 pair arithmetic with FP64
+accumulation and FP64 state, BOUNCE split r'/r'' = 6/7 A.  Inputs are synthetic (seeded lattice
+waters, Maxwell velocities) and resident in HBM before the timed region; the
+state is first relaxed on the GPU (BAOAB with strong friction, untimed).
+
+One JSON line: ns/day of BOUNCE (value) with BAOAB's ns/day, pair evaluations
+per second for both, the roofline position of the dominant kernel (the F_0 pair
+kernel) and the FP64 CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FP32 operations per evaluated pair (adds, multiplies, each half of
+# an FMA, and each transcendental counted once): see the design doc
+FLOPS_SHORT = 46     # (1 - chi) W'_sf d/r: distance, rsqrt, erfc + exp Coulomb, LJ, switch, accumulate
+FLOPS_FULL = 36      # W'_sf d/r without the switch
+PEAK_FP32 = 157.3    # TFLOP/s, MI355X vector FP32 (published)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pair_count(pos, box, r, n_excl_within):
+    """Unordered non-excluded pairs with |d| < r (minimum image)."""
+    from scipy.spatial import cKDTree
+    wrapped = np.mod(pos, box)
+    wrapped[wrapped >= box] = 0.0
+    t = cKDTree(wrapped, boxsize=box)
+    return int(t.count_neighbors(t, r) - pos.shape[0]) // 2 - n_excl_within
+
+
+def run_gpu(args, system, ff, integrator, state):
+    import torch
+    import paper_2002_07109_amd as B
+    p = B.make_params(integrator=integrator, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
+                      periodic=1, dt=1.0, gamma=1e-3, temperature=300.0, r_on=args.r_on,
+                      r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
+                      rebuild_interval=args.rebuild, seed=0, cell_size=system.cell_size,
+                      use_graph=0 if args.no_graph else 1)
+    sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
+    sim.set_state(pos=state[0], vel=state[1], step=0)
+    sim.step(args.warmup)
+    sim.sync()
+    c0 = sim.counters()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(args.steps)
+    ev1.record(sim.stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    c1 = sim.counters()
+    pair_ms = sim.profile_kernel(0, 50)
+    build_ms = sim.profile_kernel(1, 10)
+    e = sim.energies()[0]
+    out = dict(wall_s=wall, gpu_ms=gpu_ms, ms_per_step=1e3 * wall / args.steps,
+               proposals_per_step=(c1["proposals"] - c0["proposals"]) / args.steps,
+               accepted_per_step=(c1["accepted"] - c0["accepted"]) / args.steps,
+               pair_kernel_ms=pair_ms, build_ms=build_ms, t_kin=e["tkin"],
+               e_pot=e["pair"] + e["bond"] + e["angle"],
+               pos=sim.pos.cpu().numpy())
+    sim.close()
+    return out
+
+
+def equilibrate(args, system, ff):
+    import paper_2002_07109_amd as B
+    p = B.make_params(integrator=B.BAOAB, pair_precision=B.PAIR_FP32, periodic=1, dt=1.0,
+                      gamma=0.05, temperature=300.0, r_cut=9.0, skin=2.0, rebuild_interval=10,
+                      ewald_alpha=args.alpha,
+                      seed=12345, cell_size=system.cell_size, use_graph=1)
+    sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
+    done = 0
+    while done < args.equil:
+        k = min(500, args.equil - done)
+        sim.step(k)
+        sim.sync()
+        done += k
+        log(f"equilibration {done}/{args.equil} steps: T_kin = {sim.energies()[0]['tkin']:.1f} K")
+    state = (sim.pos.cpu().numpy(), sim.vel.cpu().numpy())
+    sim.close()
+    return state
+
+
+def cpu_baseline(args, system):
+    """The FP64 oracle on a bounded sample of the same workload (its seeded
+    input state), on all host cores."""
+    from oracle import oracle as orc
+    orc.build(force=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p = orc.make_params(system, integrator=orc.BOUNCE, r_on=args.r_on, r_off=args.r_off,
+                        r_cut=9.0, skin=args.skin, rebuild_interval=args.rebuild,
+                        ewald_alpha=args.alpha)
+    topo = orc.Topology.from_system(system)
+    t0 = time.perf_counter()
+    o = orc.run(p, topo, system.pos, system.vel, 0, args.cpu_steps)
+    wall = time.perf_counter() - t0
+    ns_day = args.cpu_steps * 1.0 * 1e-6 / wall * 86400.0
+    return dict(value=ns_day, unit="ns/day", cores=cores, kind="oracle",
+                sample=f"{args.cpu_steps} BOUNCE steps of the 24,000-atom box from its seeded "
+                       f"input, including the O(N^2) list build ({wall:.1f} s wall)",
+                status=o["status_name"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--equil", type=int, default=1000)
+    ap.add_argument("--skin", type=float, default=2.0)
+    ap.add_argument("--r-on", type=float, default=6.0)
+    ap.add_argument("--r-off", type=float, default=7.0)
+    ap.add_argument("--rebuild", type=int, default=10)
+    ap.add_argument("--alpha", type=float, default=0.45)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    from workloads import tip3p_params, water_box
+    ff = tip3p_params()
+    log("building the 24,000-atom water box")
+    system = water_box(n_side=20, box_len=62.0, seed=0)
+    n_excl = system.excl.shape[0]
+    state = equilibrate(args, system, ff)
+
+    import paper_2002_07109_amd as B
+    res = {}
+    for name, integ in (("baoab", B.BAOAB), ("bounce", B.BJAOAJB)):
+        log(f"timing {name}: {args.warmup} warmup + {args.steps} steps")
+        res[name] = run_gpu(args, system, ff, integ, state)
+        log(f"{name}: {res[name]['ms_per_step']:.4f} ms/step, pair kernel "
+            f"{res[name]['pair_kernel_ms']*1e3:.1f} us, T_kin {res[name]['t_kin']:.1f} K")
+
+    box = system.box
+    bo, ba = res["bounce"], res["baoab"]
+    short_pairs = pair_count(bo["pos"], box, args.r_off, n_excl)
+    full_pairs_bo = pair_count(bo["pos"], box, 9.0, n_excl)
+    full_pairs_ba = pair_count(ba["pos"], box, 9.0, n_excl)
+    ns_day = lambda ms: 1.0 * 1e-6 / (ms * 1e-3) * 86400.0
+    steps_s_bo = 1e3 / bo["ms_per_step"]
+    steps_s_ba = 1e3 / ba["ms_per_step"]
+    achieved = short_pairs * FLOPS_SHORT / (bo["pair_kernel_ms"] * 1e-3) / 1e12
+    achieved_ba = full_pairs_ba * FLOPS_FULL / (ba["pair_kernel_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "ns/day & pair-evals/s, BOUNCE vs BAOAB 1fs on same GPU, 24k-atom box",
+        "value": round(ns_day(bo["ms_per_step"]), 3),
+        "unit": "ns/day",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(bo["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 accumulation and state",
+        "data": "synthetic",
+        "config": {"workload": "periodic 24,000-atom flexible water box, 62 A cube, Ewald erfc "
+                               "(alpha %g/A) + LJ, rc 9 A, skin 2 A, BOUNCE r'/r'' = %g/%g A, "
+                               "dt 1 fs" % (args.alpha, args.r_on, args.r_off),
+                   "n_atoms": system.n_atoms, "rebuild_interval": args.rebuild,
+                   "skin": args.skin, "hip_graph": not args.no_graph},
+        "bounce": {"ns_per_day": round(ns_day(bo["ms_per_step"]), 3),
+                   "ms_per_step": round(bo["ms_per_step"], 5),
+                   "pair_evals_per_s": (short_pairs + bo["proposals_per_step"]) * steps_s_bo,
+                   "baoab_equivalent_pair_evals_per_s": full_pairs_bo * steps_s_bo,
+                   "short_pairs_per_step": short_pairs,
+                   "proposals_per_step": bo["proposals_per_step"],
+                   "accepted_per_step": bo["accepted_per_step"],
+                   "pair_kernel_us": round(bo["pair_kernel_ms"] * 1e3, 3),
+                   "list_build_us": round(bo["build_ms"] * 1e3, 3),
+                   "t_kin_K": round(bo["t_kin"], 2), "e_pot": round(bo["e_pot"], 2)},
+        "baoab": {"ns_per_day": round(ns_day(ba["ms_per_step"]), 3),
+                  "ms_per_step": round(ba["ms_per_step"], 5),
+                  "pair_evals_per_s": full_pairs_ba * steps_s_ba,
+                  "pairs_per_step": full_pairs_ba,
+                  "pair_kernel_us": round(ba["pair_kernel_ms"] * 1e3, 3),
+                  "list_build_us": round(ba["build_ms"] * 1e3, 3),
+                  "pair_kernel_tflops": round(achieved_ba, 3),
+                  "t_kin_K": round(ba["t_kin"], 2), "e_pot": round(ba["e_pot"], 2)},
+        "speedup_vs_baoab": round(ba["ms_per_step"] / bo["ms_per_step"], 4),
+        "roofline": {"kernel": "F_0 pair kernel (BOUNCE short range)", "bound": "alu",
+                     "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
+                     "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs},
+    }
+    if not args.skip_cpu:
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(args, system)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * bounce.h -- C ABI of the MI355X BOUNCE direct-space library.
+ *
+ * BOUNCE (Monmarche, Weisman, Lagardere, Piquemal, arXiv:2002.07109) samples
+ * the canonical measure of a molecular system (Sec. II.A) with a Langevin
+ * dynamics driven by the short-range forces F_0 (Eq. SDE-Langevin-F0) plus
+ * velocity jumps that carry the bounded long-range pair forces (Sec. II.B,
+ * Eq. Lambda_i, Eq. R_i), discretised by the Strang splitting
+ * B J A O A J B (Sec. III.C, algorithm of Sec. IV.B).  The long-range part of
+ * every direct-space pair (Coulomb + Lennard-Jones, gradient-level switch chi,
+ * Sec. IV.A and Sec. V) is sampled by per-atom Poisson thinning with the rate
+ * bound beta |v_i| L (Sec. IV.A, Sec. III.D).  BAOAB is the same scheme without
+ * J and with the full pair force in F_0.
+ *
+ * Conventions
+ *  - Units: Angstrom, fs, amu, kcal/mol, elementary charge.
+ *  - Atom arrays are in caller order ("global" ids), row-major [N][3] float64.
+ *  - Several independent systems ("replicas") may share one context; replica r
+ *    owns atoms [replica_offset[r], replica_offset[r+1]) and draws from the
+ *    Philox4x64-10 key (seed, r); atom ids in random counters and event logs
+ *    are replica-local, so a replica's trajectory does not depend on the batch.
+ *  - Device pointers are HIP device addresses (e.g. torch tensors' data_ptr());
+ *    host pointers are ordinary memory.  The library never allocates device
+ *    memory: the caller allocates the workspace it asks for and keeps it, the
+ *    position and the velocity buffers alive until bounce_destroy or the next
+ *    bounce_bind.  All device work is enqueued on the bound stream.
+ *  - Every call returns a bounce_status (0 = success).  Argument errors are
+ *    returned at once.  Conditions detected on the device (list capacity,
+ *    Verlet-skin overrun, rate-bound violation, Poisson cap, non-finite state,
+ *    atom outside a droplet grid) are latched in a device word and returned by
+ *    the next bounce_sync or getter; bounce_last_error gives a message.
+ *  - Not thread-safe per context; different contexts are independent.
+ */
+#ifndef BOUNCE_H
+#define BOUNCE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BOUNCE_MAX_TYPES 8
+
+typedef enum {
+    BOUNCE_OK = 0,
+    BOUNCE_E_ARG = -1,          /* invalid argument or call order            */
+    BOUNCE_E_HIP = -2,          /* HIP runtime error                         */
+    BOUNCE_E_CAPACITY = -3,     /* a pair-list row or cell overflowed        */
+    BOUNCE_E_SKIN = -4,         /* an atom moved >= skin/2 since the build   */
+    BOUNCE_E_BOUND = -5,        /* a proposal exceeded the rate bound        */
+    BOUNCE_E_POISSON_CAP = -6,  /* more proposals than max_proposals         */
+    BOUNCE_E_NONFINITE = -7,    /* NaN/Inf in positions or velocities        */
+    BOUNCE_E_STATE = -8,        /* context not bound / system not set        */
+    BOUNCE_E_GRID = -9,         /* droplet atom left its cell grid           */
+    BOUNCE_E_WORKSPACE = -10    /* workspace too small                       */
+} bounce_status;
+
+enum { BOUNCE_BJAOAJB = 0, BOUNCE_BAOAB = 1 };          /* integrator          */
+enum { BOUNCE_PAIR_FP32 = 0, BOUNCE_PAIR_FP64 = 1 };    /* pair arithmetic     */
+enum { BOUNCE_COUL_BARE = 0, BOUNCE_COUL_EWALD = 1 };   /* 1/r or erfc(a r)/r  */
+enum { BOUNCE_PH_JA = 0, BOUNCE_PH_O = 1, BOUNCE_PH_JB = 2 };  /* random-stream phases */
+/* gradient parts for bounce_compute_gradient (bit mask) */
+enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8 };
+/* lists for bounce_get_list */
+enum { BOUNCE_LIST_FORCE = 0, BOUNCE_LIST_CAND = 1 };
+
+typedef struct {
+    int32_t integrator;        /* BOUNCE_BJAOAJB or BOUNCE_BAOAB                          */
+    int32_t pair_precision;    /* BOUNCE_PAIR_FP32 (FP64 accumulation) or BOUNCE_PAIR_FP64 */
+    int32_t coulomb;           /* BOUNCE_COUL_BARE or BOUNCE_COUL_EWALD                    */
+    int32_t periodic;          /* 1: orthorhombic boxes, minimum image; 0: droplets        */
+    int32_t rebuild_interval;  /* K: lists rebuilt at q_n when n % K == 0                  */
+    int32_t max_proposals;     /* Poisson cap per atom per half step                       */
+    int32_t log_events;        /* 1: record every jump proposal                            */
+    int32_t use_graph;         /* 1: replay captured HIP graphs of K steps in bounce_step  */
+    double dt;                 /* time step delta (fs)                                     */
+    double gamma;              /* friction (1/fs), velocity space, all atoms               */
+    double temperature;        /* K                                                        */
+    double r_on, r_off;        /* switch chi: 0 below r', 1 above r'' (Angstrom)           */
+    double r_cut;              /* shifted-force cutoff rc (Angstrom)                       */
+    double skin;               /* Verlet skin s (Angstrom)                                 */
+    double ewald_alpha;        /* 1/Angstrom (BOUNCE_COUL_EWALD)                           */
+    double bound_scale;        /* rate bound used = bound_scale * L (1 = tight)            */
+    double cell_size;          /* target cell edge of the list grid (Angstrom)             */
+    uint64_t seed;             /* Philox key word 0                                        */
+    int64_t event_capacity;    /* events kept when log_events = 1                          */
+} bounce_params;
+
+typedef struct {
+    int32_t n_replicas;
+    int32_t n_atoms;                 /* total over replicas                               */
+    const int64_t *replica_offset;   /* [n_replicas + 1], offset[0] = 0                   */
+    const double *box;               /* [n_replicas][3] box edges (periodic) or NULL      */
+    const double *grid_origin;       /* [n_replicas][3] droplet cell-grid origin or NULL  */
+    const int32_t *grid_dims;        /* [n_replicas][3] droplet cell-grid dims or NULL    */
+    const int32_t *type;             /* [n_atoms] in [0, n_types)                         */
+    const double *mass;              /* [n_atoms] amu                                     */
+    int32_t n_types;                 /* <= BOUNCE_MAX_TYPES                               */
+    const double *charge, *eps, *sigma;  /* [n_types] e, kcal/mol, Angstrom; Lorentz-Berthelot mixing */
+    int32_t n_bonds;   const int32_t *bonds;  const double *bond_k, *bond_r0;   /* E = k (r - r0)^2       */
+    int32_t n_angles;  const int32_t *angles; const double *angle_k, *angle_t0; /* [na][3], vertex middle */
+    int32_t n_excl;    const int32_t *excl;   /* [n_excl][2] pairs with no nonbonded term        */
+} bounce_system;
+
+typedef struct {
+    int64_t proposals;         /* jump proposals (pair fields evaluated by J)  */
+    int64_t accepted;          /* accepted jumps (reflections)                 */
+    int64_t bound_violations;  /* v.F > |v| L seen (must stay 0)               */
+    int64_t rebuilds;          /* list builds                                  */
+    int64_t steps;             /* completed steps                              */
+} bounce_counters;
+
+typedef struct {
+    int64_t step;
+    int32_t phase, atom, k, partner, accepted, replica;   /* atom/partner replica-local */
+} bounce_event;
+
+typedef struct bounce_ctx bounce_ctx;
+
+/* Create a context from parameters (copied).  *out receives the handle. */
+bounce_status bounce_create(const bounce_params *params, bounce_ctx **out);
+/* Release the context (not the caller's buffers).  NULL is ignored. */
+void bounce_destroy(bounce_ctx *ctx);
+/* Replace dt, gamma, temperature and bound_scale of a bound context (other fields ignored). */
+bounce_status bounce_update_params(bounce_ctx *ctx, const bounce_params *params);
+
+/* Topology and force field of all replicas (host arrays, copied).  Computes the
+   rate bounds L_ab = (1 + 1e-3) max over a 1e-4 A grid of [r', rc] of |chi W'_sf|
+   (Sec. IV.A).  Must precede bounce_workspace_size. */
+bounce_status bounce_set_system(bounce_ctx *ctx, const bounce_system *sys);
+/* Device workspace bytes the context needs. */
+bounce_status bounce_workspace_size(const bounce_ctx *ctx, uint64_t *bytes);
+/* Bind caller-owned device memory: workspace (>= bounce_workspace_size bytes),
+   positions and velocities ([N][3] float64, updated in place), and the HIP
+   stream (hipStream_t, NULL = default).  Uploads the topology; step = 0. */
+bounce_status bounce_bind(bounce_ctx *ctx, void *workspace, uint64_t workspace_bytes,
+                          double *pos_dev, double *vel_dev, void *stream);
+/* Set the step counter n (random-stream counter base); the next bounce_step
+   rebuilds the lists.  Use after writing new positions or velocities. */
+bounce_status bounce_set_step(bounce_ctx *ctx, int64_t step);
+bounce_status bounce_get_step(const bounce_ctx *ctx, int64_t *step);
+/* Enqueue n_steps full steps (B J A O A J B, or B A O A B), leaving positions
+   and velocities at a step boundary.  Asynchronous. */
+bounce_status bounce_step(bounce_ctx *ctx, int32_t n_steps);
+/* Wait for the bound stream and return the first latched device condition. */
+bounce_status bounce_sync(bounce_ctx *ctx);
+
+/* Gradient dE/dq of the selected parts at the current positions into grad_dev
+   ([N][3] float64, caller order): BONDED, SHORT = sum_j (1-chi) W'_sf d/r (r<r''),
+   LONG = sum_j chi W'_sf d/r (r'<r<rc), FULL = sum_j W'_sf d/r (r<rc).  Synchronous. */
+bounce_status bounce_compute_gradient(bounce_ctx *ctx, int32_t which, double *grad_dev);
+/* Energies of every replica into out_host[n_replicas][7]:
+   E_bond, E_angle, E_coul, E_lj, E_pair (= coul + lj, shifted force, r < rc),
+   E_kin, T_kin.  Synchronous. */
+bounce_status bounce_compute_energies(bounce_ctx *ctx, double *out_host);
+bounce_status bounce_get_counters(bounce_ctx *ctx, int32_t replica, bounce_counters *out);
+/* Copy up to cap logged events (in no particular order) and their total count. */
+bounce_status bounce_get_events(bounce_ctx *ctx, bounce_event *host, int64_t cap, int64_t *n_total);
+/* The list built last (FORCE: r < r''+s for BOUNCE, r < rc+s for BAOAB; CAND:
+   candidate partners r'-s <= r < rc+s) as CSR in caller ids: row_ptr_host[N+1],
+   col_host[cap], rows in the library's canonical order (ascending list-grid cell,
+   then id).  Synchronous. */
+bounce_status bounce_get_list(bounce_ctx *ctx, int32_t which, int64_t *row_ptr_host,
+                              int32_t *col_host, int64_t cap);
+/* Rate bounds: L_ab_host[n_types^2] and L_a_host[n_types] (before bound_scale). */
+bounce_status bounce_rate_bounds(const bounce_ctx *ctx, double *L_ab_host, double *L_a_host);
+/* Apply one J half-step alone (Sec. IV.B step J) at the current positions with
+   the current candidate lists, random stream (step, phase).  Synchronous. */
+bounce_status bounce_jump_halfstep(bounce_ctx *ctx, int64_t step, int32_t phase);
+
+/* Direct-space energy E = sum_{i<j, not excluded, r<rc} W_sf,ij of replica 0's
+   topology at positions pos_dev ([N][3]) with per-type parameters
+   params_dev = [charge[nt], eps[nt], sigma[nt]] (device); writes the scalar to
+   energy_dev.  Enqueued on the bound stream. */
+bounce_status bounce_direct_energy(bounce_ctx *ctx, const double *pos_dev,
+                                   const double *params_dev, double *energy_dev);
+/* Backward of bounce_direct_energy: grad_pos_dev[N][3] = g dE/dq and
+   grad_params_dev[3 nt] = g dE/d(charge, eps, sigma), with g = *grad_out_dev. */
+bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
+                                       const double *params_dev, const double *grad_out_dev,
+                                       double *grad_pos_dev, double *grad_params_dev);
+
+/* Kernel timing for measurement: enqueue reps back-to-back launches of one
+   kernel of the step exactly as bounce_step launches it (which = 0: the F_0
+   pair kernel at the current positions; which = 1: the list build) between two
+   HIP events on the bound stream and return the mean duration in ms.  Leaves
+   the trajectory unchanged.  Synchronous. */
+bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);
+
+const char *bounce_status_string(int32_t status);
+const char *bounce_last_error(const bounce_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,996 @@
+// C-ABI host side of the BOUNCE library: context, workspace binding, rate
+// bounds, list-build schedule, step orchestration (direct launches or replayed
+// HIP graphs), diagnostics and the differentiable direct energy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bounce.h"
+#include "bounce_kernels.hpp"
+
+using namespace bnc;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// host-side pair potential, used only for the rate bounds (Sec. IV.A: the bound
+// L >= |chi W'|_inf is computed numerically once from the 1-D function)
+// ---------------------------------------------------------------------------
+struct HostFF {
+    int nt;
+    double q[MAXT], eps[MAXT], sig[MAXT];
+    int coulomb;
+    double alpha, r_on, r_off, r_cut;
+
+    void du(int a, int b, double r, double &d) const
+    {
+        double qq = KE * q[a] * q[b];
+        double e = std::sqrt(eps[a] * eps[b]);
+        double s = 0.5 * (sig[a] + sig[b]);
+        double dg;
+        if (coulomb) {
+            double ar = alpha * r;
+            dg = -std::erfc(ar) / (r * r) - TWO_OVER_SQRTPI * alpha * std::exp(-ar * ar) / r;
+        } else {
+            dg = -1.0 / (r * r);
+        }
+        double dl = 0.0;
+        if (e != 0.0) {
+            double x = s / r, x6 = x * x * x * x * x * x;
+            dl = 4.0 * e * (6.0 * x6 - 12.0 * x6 * x6) / r;
+        }
+        d = qq * dg + dl;
+    }
+    double chi(double r) const
+    {
+        double x = (r - r_on) / (r_off - r_on);
+        x = std::min(1.0, std::max(0.0, x));
+        return x * x * x * (10.0 + x * (6.0 * x - 15.0));
+    }
+    // (1 + 1e-3) * max over the grid r' + k 1e-4 < rc of |chi(r) (u'(r) - u'(rc))|
+    double bound(int a, int b) const
+    {
+        double drc;
+        du(a, b, r_cut, drc);
+        double m = 0.0;
+        for (long k = 0;; ++k) {
+            double r = r_on + (double)k * 1e-4;
+            if (r >= r_cut) break;
+            double d;
+            du(a, b, r, d);
+            m = std::max(m, std::fabs(chi(r) * (d - drc)));
+        }
+        return m * (1.0 + 1e-3);
+    }
+};
+
+struct Region {
+    size_t off, bytes;
+};
+
+}  // namespace
+
+struct bounce_ctx {
+    bounce_params p{};
+    bool have_system = false, bound = false;
+    std::string err;
+    // system (host copies)
+    int32_t n = 0, R = 0, nt = 0;
+    std::vector<int64_t> rep_off;
+    std::vector<RepInfo> reps;
+    std::vector<int32_t> type, rep_of, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, angle_ijk;
+    std::vector<double> mass, acc_m, inv_mass, ou_c2, bond_kr, angle_kt, tparams;
+    std::vector<double> L_ab, L_a;
+    int32_t n_cells = 0, fcap = 0, ccap = 0, acap = 0, xcap = 0;
+    // workspace
+    char *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    double *pos = nullptr, *vel = nullptr;
+    hipStream_t stream = nullptr;
+    Topo tp{};
+    ListSet main{}, aux{};
+    RepInfo *d_reps = nullptr;
+    DevState *d_st = nullptr;
+    RepCounters *d_cnt = nullptr;
+    Event *d_events = nullptr;
+    double *d_La = nullptr, *d_tparams = nullptr, *d_fpair = nullptr, *d_atom = nullptr,
+           *d_seg = nullptr, *d_ou_c2 = nullptr;
+    int64_t *d_rep_off = nullptr, *d_one_seg = nullptr;
+    int32_t *d_cell_rep = nullptr;
+    std::vector<int32_t> cell_rep;
+    int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
+    // schedule
+    int64_t step = 0;
+    int64_t built_step = -1;
+    int64_t host_steps = 0, host_rebuilds = 0;
+    // graphs of K steps
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+static bounce_status fail(bounce_ctx *c, bounce_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, BOUNCE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// API functions: C linkage comes from their declarations in bounce.h
+
+const char *bounce_status_string(int32_t s)
+{
+    switch (s) {
+        case BOUNCE_OK: return "ok";
+        case BOUNCE_E_ARG: return "invalid argument";
+        case BOUNCE_E_HIP: return "HIP runtime error";
+        case BOUNCE_E_CAPACITY: return "pair-list or cell capacity exceeded";
+        case BOUNCE_E_SKIN: return "an atom moved half the Verlet skin since the list build";
+        case BOUNCE_E_BOUND: return "a jump proposal exceeded the rate bound";
+        case BOUNCE_E_POISSON_CAP: return "Poisson proposal count above max_proposals";
+        case BOUNCE_E_NONFINITE: return "non-finite position or velocity";
+        case BOUNCE_E_STATE: return "context not ready (system not set or not bound)";
+        case BOUNCE_E_GRID: return "a droplet atom left its cell grid";
+        case BOUNCE_E_WORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+const char *bounce_last_error(const bounce_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
+{
+    if (!p || !out) return BOUNCE_E_ARG;
+    *out = nullptr;
+    if (p->integrator != BOUNCE_BJAOAJB && p->integrator != BOUNCE_BAOAB) return BOUNCE_E_ARG;
+    if (!(p->dt > 0) || !(p->gamma >= 0) || !(p->temperature > 0)) return BOUNCE_E_ARG;
+    if (!(p->r_cut > 0) || !(p->skin >= 0) || !(p->cell_size > 0)) return BOUNCE_E_ARG;
+    if (p->integrator == BOUNCE_BJAOAJB && !(p->r_on > 0 && p->r_off > p->r_on)) return BOUNCE_E_ARG;
+    if (p->rebuild_interval < 1 || p->max_proposals < 1) return BOUNCE_E_ARG;
+    if (!(p->bound_scale > 0)) return BOUNCE_E_ARG;
+    bounce_ctx *c = new bounce_ctx();
+    c->p = *p;
+    *out = c;
+    return BOUNCE_OK;
+}
+
+void bounce_destroy(bounce_ctx *c)
+{
+    if (!c) return;
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    delete c;
+}
+
+static void make_ou(bounce_ctx *c)
+{
+    double c1 = std::exp(-c->p.gamma * c->p.dt);
+    double kt = KB * c->p.temperature;
+    c->ou_c2.resize(c->n);
+    for (int32_t g = 0; g < c->n; ++g) c->ou_c2[g] = std::sqrt(kt * (1.0 - c1 * c1) * ACC / c->mass[g]);
+}
+
+static void make_bounds(bounce_ctx *c)
+{
+    HostFF ff{};
+    ff.nt = c->nt;
+    for (int a = 0; a < c->nt; ++a) {
+        ff.q[a] = c->tparams[a]; ff.eps[a] = c->tparams[c->nt + a]; ff.sig[a] = c->tparams[2 * c->nt + a];
+    }
+    ff.coulomb = c->p.coulomb;
+    ff.alpha = c->p.ewald_alpha;
+    ff.r_on = c->p.r_on; ff.r_off = c->p.r_off; ff.r_cut = c->p.r_cut;
+    c->L_ab.assign(c->nt * c->nt, 0.0);
+    c->L_a.assign(c->nt, 0.0);
+    if (c->p.integrator != BOUNCE_BJAOAJB) return;
+    for (int a = 0; a < c->nt; ++a)
+        for (int b = a; b < c->nt; ++b) c->L_ab[a * c->nt + b] = c->L_ab[b * c->nt + a] = ff.bound(a, b);
+    for (int a = 0; a < c->nt; ++a)
+        for (int b = 0; b < c->nt; ++b) c->L_a[a] = std::max(c->L_a[a], c->L_ab[a * c->nt + b]);
+}
+
+bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
+{
+    if (!c || !s) return BOUNCE_E_ARG;
+    if (s->n_replicas < 1 || s->n_atoms < 1 || !s->replica_offset || !s->type || !s->mass)
+        return fail(c, BOUNCE_E_ARG, "missing replicas, atoms, types or masses");
+    if (s->n_types < 1 || s->n_types > MAXT || !s->charge || !s->eps || !s->sigma)
+        return fail(c, BOUNCE_E_ARG, "n_types must be in [1, 8] with charge/eps/sigma");
+    if (s->replica_offset[0] != 0 || s->replica_offset[s->n_replicas] != s->n_atoms)
+        return fail(c, BOUNCE_E_ARG, "replica_offset must run from 0 to n_atoms");
+    if (c->p.periodic && !s->box) return fail(c, BOUNCE_E_ARG, "periodic system needs box");
+    if (!c->p.periodic && (!s->grid_origin || !s->grid_dims))
+        return fail(c, BOUNCE_E_ARG, "droplet system needs grid_origin and grid_dims");
+    const int32_t n = s->n_atoms, R = s->n_replicas, nt = s->n_types;
+    c->n = n; c->R = R; c->nt = nt;
+    c->rep_off.assign(s->replica_offset, s->replica_offset + R + 1);
+    c->type.assign(s->type, s->type + n);
+    c->mass.assign(s->mass, s->mass + n);
+    for (int32_t g = 0; g < n; ++g) {
+        if (c->type[g] < 0 || c->type[g] >= nt) return fail(c, BOUNCE_E_ARG, "atom type out of range");
+        if (!(c->mass[g] > 0)) return fail(c, BOUNCE_E_ARG, "masses must be positive");
+    }
+    c->tparams.resize(3 * nt);
+    for (int a = 0; a < nt; ++a) {
+        c->tparams[a] = s->charge[a]; c->tparams[nt + a] = s->eps[a]; c->tparams[2 * nt + a] = s->sigma[a];
+    }
+    c->rep_of.assign(n, 0);
+    c->reps.assign(R, RepInfo{});
+    int32_t cell_off = 0;
+    double max_rho = 0.0;
+    const double rsearch = std::max(c->p.r_cut, c->p.r_off) + c->p.skin;
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t b = c->rep_off[r], e = c->rep_off[r + 1];
+        if (e <= b) return fail(c, BOUNCE_E_ARG, "empty replica");
+        for (int64_t g = b; g < e; ++g) c->rep_of[g] = r;
+        RepInfo &ri = c->reps[r];
+        ri.periodic = c->p.periodic;
+        ri.atom_off = b;
+        ri.n_atoms = (int32_t)(e - b);
+        ri.cell_off = cell_off;
+        ri.key0 = c->p.seed;
+        ri.key1 = (uint64_t)r;
+        double vol = 1.0;
+        for (int k = 0; k < 3; ++k) {
+            if (c->p.periodic) {
+                double L = s->box[3 * r + k];
+                if (!(L > 2.0 * rsearch))
+                    return fail(c, BOUNCE_E_ARG, "box edge must exceed 2 (max(rc, r'') + skin)");
+                ri.box[k] = L;
+                ri.inv_box[k] = 1.0 / L;
+                int32_t nc = (int32_t)std::floor(L / c->p.cell_size);
+                if (nc < 1) nc = 1;
+                ri.ncell[k] = nc;
+                ri.cinv[k] = (double)nc * ri.inv_box[k];
+                ri.cw[k] = L / nc;
+                vol *= L;
+            } else {
+                ri.box[k] = 0.0; ri.inv_box[k] = 0.0;
+                ri.origin[k] = s->grid_origin[3 * r + k];
+                ri.ncell[k] = s->grid_dims[3 * r + k];
+                if (ri.ncell[k] < 1) return fail(c, BOUNCE_E_ARG, "grid_dims must be >= 1");
+                ri.cw[k] = c->p.cell_size;
+                vol *= ri.ncell[k] * c->p.cell_size;
+            }
+        }
+        ri.inv_cell = 1.0 / c->p.cell_size;
+        int64_t nc3 = (int64_t)ri.ncell[0] * ri.ncell[1] * ri.ncell[2];
+        if (nc3 > (int64_t)1 << 28) return fail(c, BOUNCE_E_ARG, "cell grid too large");
+        cell_off += (int32_t)nc3;
+        double rho = c->p.periodic ? (double)(e - b) / vol : 0.12;
+        max_rho = std::max(max_rho, rho);
+    }
+    c->n_cells = cell_off;
+    c->cell_rep.assign(cell_off, 0);
+    for (int32_t r = 0; r < R; ++r) {
+        int32_t e = r + 1 < R ? c->reps[r + 1].cell_off : cell_off;
+        for (int32_t k = c->reps[r].cell_off; k < e; ++k) c->cell_rep[k] = r;
+    }
+    // row capacities: 1.5 x the mean count in the list sphere at the densest replica
+    auto cap = [&](double r) {
+        double m = 1.5 * max_rho * 4.18879020478639 * r * r * r + 64.0;
+        return (int32_t)(std::ceil(m / 32.0) * 32.0);
+    };
+    int64_t max_rep = 0;
+    for (int32_t r = 0; r < R; ++r) max_rep = std::max<int64_t>(max_rep, c->rep_off[r + 1] - c->rep_off[r]);
+    auto clampcap = [&](int32_t k) { return (int32_t)std::min<int64_t>(k, std::max<int64_t>(32, ((max_rep + 31) / 32) * 32)); };
+    bool bounce = c->p.integrator == BOUNCE_BJAOAJB;
+    c->fcap = clampcap(cap((bounce ? c->p.r_off : c->p.r_cut) + c->p.skin));
+    c->ccap = bounce ? clampcap(cap(c->p.r_cut + c->p.skin)) : 0;
+    c->acap = clampcap(cap(c->p.r_cut + 0.01));
+    c->xcap = std::max(c->fcap, std::max(c->ccap, c->acap));
+    // exclusions (both directions) and bonded terms per atom
+    std::vector<std::vector<int32_t>> ex(n), bt(n);
+    for (int32_t k = 0; k < s->n_excl; ++k) {
+        int32_t a = s->excl[2 * k], b = s->excl[2 * k + 1];
+        if (a < 0 || b < 0 || a >= n || b >= n) return fail(c, BOUNCE_E_ARG, "exclusion index");
+        ex[a].push_back(b);
+        ex[b].push_back(a);
+    }
+    c->bond_ij.assign(s->bonds, s->bonds + 2 * s->n_bonds);
+    c->bond_kr.resize(2 * s->n_bonds);
+    for (int32_t k = 0; k < s->n_bonds; ++k) {
+        c->bond_kr[2 * k] = s->bond_k[k];
+        c->bond_kr[2 * k + 1] = s->bond_r0[k];
+        for (int j = 0; j < 2; ++j) {
+            int32_t a = s->bonds[2 * k + j];
+            if (a < 0 || a >= n) return fail(c, BOUNCE_E_ARG, "bond index");
+            bt[a].push_back(k);
+        }
+    }
+    c->angle_ijk.assign(s->angles, s->angles + 3 * s->n_angles);
+    c->angle_kt.resize(2 * s->n_angles);
+    for (int32_t k = 0; k < s->n_angles; ++k) {
+        c->angle_kt[2 * k] = s->angle_k[k];
+        c->angle_kt[2 * k + 1] = s->angle_t0[k];
+        for (int j = 0; j < 3; ++j) {
+            int32_t a = s->angles[3 * k + j];
+            if (a < 0 || a >= n) return fail(c, BOUNCE_E_ARG, "angle index");
+            bt[a].push_back((1 << 28) | k);
+        }
+    }
+    c->excl_ptr.assign(n + 1, 0);
+    c->bt_ptr.assign(n + 1, 0);
+    c->excl_idx.clear();
+    c->bt.clear();
+    for (int32_t g = 0; g < n; ++g) {
+        c->excl_idx.insert(c->excl_idx.end(), ex[g].begin(), ex[g].end());
+        c->bt.insert(c->bt.end(), bt[g].begin(), bt[g].end());
+        c->excl_ptr[g + 1] = (int32_t)c->excl_idx.size();
+        c->bt_ptr[g + 1] = (int32_t)c->bt.size();
+    }
+    c->acc_m.resize(n);
+    c->inv_mass.resize(n);
+    for (int32_t g = 0; g < n; ++g) {
+        c->acc_m[g] = ACC / c->mass[g];
+        c->inv_mass[g] = 1.0 / c->mass[g];
+    }
+    make_ou(c);
+    make_bounds(c);
+    c->have_system = true;
+    c->bound = false;
+    return BOUNCE_OK;
+}
+
+// workspace layout
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes)
+    {
+        size_t off = (total + 255) & ~(size_t)255;
+        total = off + bytes;
+        return off;
+    }
+};
+
+template <typename T>
+static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
+
+struct Offsets {
+    size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
+        angle_ijk, angle_kt, reps, La, tparams, rep_off, one_seg, st, cnt, events, fpair, atom,
+        seg, xcnt, xcol, cell_rep;
+    size_t ls[2][12];
+};
+
+static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
+{
+    const size_t n = c->n, R = c->R;
+    o.type = L.take(4 * n);
+    o.rep_of = L.take(4 * n);
+    o.acc_m = L.take(8 * n);
+    o.inv_mass = L.take(8 * n);
+    o.ou_c2 = L.take(8 * n);
+    o.excl_ptr = L.take(4 * (n + 1));
+    o.excl_idx = L.take(4 * std::max<size_t>(1, c->excl_idx.size()));
+    o.bt_ptr = L.take(4 * (n + 1));
+    o.bt = L.take(4 * std::max<size_t>(1, c->bt.size()));
+    o.bond_ij = L.take(4 * std::max<size_t>(1, c->bond_ij.size()));
+    o.bond_kr = L.take(8 * std::max<size_t>(1, c->bond_kr.size()));
+    o.angle_ijk = L.take(4 * std::max<size_t>(1, c->angle_ijk.size()));
+    o.angle_kt = L.take(8 * std::max<size_t>(1, c->angle_kt.size()));
+    o.reps = L.take(sizeof(RepInfo) * R);
+    o.La = L.take(8 * MAXT);
+    o.tparams = L.take(8 * 3 * MAXT);
+    o.rep_off = L.take(8 * (R + 1));
+    o.cell_rep = L.take(4 * (size_t)c->n_cells);
+    o.one_seg = L.take(16);
+    o.st = L.take(sizeof(DevState));
+    o.cnt = L.take(sizeof(RepCounters) * R);
+    o.events = L.take(sizeof(Event) * std::max<int64_t>(1, c->p.log_events ? c->p.event_capacity : 1));
+    o.fpair = L.take(24 * n);
+    o.atom = L.take(8 * n * std::max(5, 3 * MAXT));
+    o.seg = L.take(8 * 8 * R);
+    o.xcnt = L.take(4 * n);
+    o.xcol = L.take(4 * n * (size_t)c->xcap);
+    for (int k = 0; k < 2; ++k) {
+        const size_t fcap = k == 0 ? c->fcap : c->acap, ccap = k == 0 ? c->ccap : 0;
+        size_t *q = o.ls[k];
+        q[0] = L.take(4 * n);                      // perm
+        q[1] = L.take(4 * n);                      // inv_perm
+        q[2] = L.take(4 * n);                      // cell_of
+        q[3] = L.take(4 * n);                      // slot
+        q[4] = L.take(4 * (size_t)c->n_cells);     // cell_count
+        q[5] = L.take(4 * ((size_t)c->n_cells + 1));  // cell_start
+        q[6] = L.take(32 * n);                     // x[0]
+        q[7] = L.take(32 * n);                     // x[1]
+        q[8] = L.take(24 * n);                     // q_build
+        q[9] = L.take(4 * n);                      // fcnt
+        q[10] = L.take(4 * n * fcap);              // flist
+        q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
+    }
+}
+
+bounce_status bounce_workspace_size(const bounce_ctx *c, uint64_t *bytes)
+{
+    if (!c || !bytes) return BOUNCE_E_ARG;
+    if (!c->have_system) return BOUNCE_E_STATE;
+    Layout L;
+    Offsets o;
+    plan(c, L, o);
+    *bytes = L.total + 256;
+    return BOUNCE_OK;
+}
+
+template <typename T>
+static hipError_t up(hipStream_t sm, char *ws, size_t off, const std::vector<T> &v)
+{
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, sm);
+}
+
+bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double *pos, double *vel,
+                          void *stream)
+{
+    if (!c || !workspace || !pos || !vel) return BOUNCE_E_ARG;
+    if (!c->have_system) return fail(c, BOUNCE_E_STATE, "bounce_set_system first");
+    Layout L;
+    Offsets o;
+    plan(c, L, o);
+    char *ws = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    if ((uint64_t)(ws - (char *)workspace) + L.total > bytes)
+        return fail(c, BOUNCE_E_WORKSPACE, "workspace smaller than bounce_workspace_size");
+    c->ws = ws;
+    c->ws_bytes = bytes;
+    c->pos = pos;
+    c->vel = vel;
+    c->stream = (hipStream_t)stream;
+    hipStream_t sm = c->stream;
+    HIPCHK(c, up(sm, ws, o.type, c->type));
+    HIPCHK(c, up(sm, ws, o.rep_of, c->rep_of));
+    HIPCHK(c, up(sm, ws, o.acc_m, c->acc_m));
+    HIPCHK(c, up(sm, ws, o.inv_mass, c->inv_mass));
+    HIPCHK(c, up(sm, ws, o.ou_c2, c->ou_c2));
+    HIPCHK(c, up(sm, ws, o.excl_ptr, c->excl_ptr));
+    HIPCHK(c, up(sm, ws, o.excl_idx, c->excl_idx));
+    HIPCHK(c, up(sm, ws, o.bt_ptr, c->bt_ptr));
+    HIPCHK(c, up(sm, ws, o.bt, c->bt));
+    HIPCHK(c, up(sm, ws, o.bond_ij, c->bond_ij));
+    HIPCHK(c, up(sm, ws, o.bond_kr, c->bond_kr));
+    HIPCHK(c, up(sm, ws, o.angle_ijk, c->angle_ijk));
+    HIPCHK(c, up(sm, ws, o.angle_kt, c->angle_kt));
+    HIPCHK(c, up(sm, ws, o.reps, c->reps));
+    std::vector<double> La(MAXT, 0.0);
+    for (int a = 0; a < c->nt; ++a) La[a] = c->L_a[a] * c->p.bound_scale;
+    HIPCHK(c, up(sm, ws, o.La, La));
+    HIPCHK(c, up(sm, ws, o.tparams, c->tparams));
+    HIPCHK(c, up(sm, ws, o.rep_off, c->rep_off));
+    HIPCHK(c, up(sm, ws, o.cell_rep, c->cell_rep));
+    std::vector<int64_t> one = {0, c->n};
+    HIPCHK(c, up(sm, ws, o.one_seg, one));
+    HIPCHK(c, hipMemsetAsync(ws + o.st, 0, sizeof(DevState), sm));
+    HIPCHK(c, hipMemsetAsync(ws + o.cnt, 0, sizeof(RepCounters) * c->R, sm));
+    Topo &t = c->tp;
+    t.type = at<int32_t>(ws, o.type);
+    t.rep_of = at<int32_t>(ws, o.rep_of);
+    t.acc_m = at<double>(ws, o.acc_m);
+    t.inv_mass = at<double>(ws, o.inv_mass);
+    t.excl_ptr = at<int32_t>(ws, o.excl_ptr);
+    t.excl_idx = at<int32_t>(ws, o.excl_idx);
+    t.bt_ptr = at<int32_t>(ws, o.bt_ptr);
+    t.bt = at<int32_t>(ws, o.bt);
+    t.bond_ij = at<int32_t>(ws, o.bond_ij);
+    t.bond_kr = at<double>(ws, o.bond_kr);
+    t.angle_ijk = at<int32_t>(ws, o.angle_ijk);
+    t.angle_kt = at<double>(ws, o.angle_kt);
+    c->d_reps = at<RepInfo>(ws, o.reps);
+    c->d_La = at<double>(ws, o.La);
+    c->d_tparams = at<double>(ws, o.tparams);
+    c->d_rep_off = at<int64_t>(ws, o.rep_off);
+    c->d_cell_rep = at<int32_t>(ws, o.cell_rep);
+    c->d_one_seg = at<int64_t>(ws, o.one_seg);
+    c->d_st = at<DevState>(ws, o.st);
+    c->d_cnt = at<RepCounters>(ws, o.cnt);
+    c->d_events = at<Event>(ws, o.events);
+    c->d_fpair = at<double>(ws, o.fpair);
+    c->d_atom = at<double>(ws, o.atom);
+    c->d_seg = at<double>(ws, o.seg);
+    c->d_ou_c2 = at<double>(ws, o.ou_c2);
+    c->d_xcnt = at<int32_t>(ws, o.xcnt);
+    c->d_xcol = at<int32_t>(ws, o.xcol);
+    for (int k = 0; k < 2; ++k) {
+        ListSet &ls = k == 0 ? c->main : c->aux;
+        size_t *q = o.ls[k];
+        ls.perm = at<int32_t>(ws, q[0]);
+        ls.inv_perm = at<int32_t>(ws, q[1]);
+        ls.cell_of = at<int32_t>(ws, q[2]);
+        ls.slot = at<int32_t>(ws, q[3]);
+        ls.cell_count = at<int32_t>(ws, q[4]);
+        ls.cell_start = at<int32_t>(ws, q[5]);
+        ls.x[0] = at<double4>(ws, q[6]);
+        ls.x[1] = at<double4>(ws, q[7]);
+        ls.q_build = at<double>(ws, q[8]);
+        ls.fcnt = at<int32_t>(ws, q[9]);
+        ls.flist = at<int32_t>(ws, q[10]);
+        ls.ccnt = at<int32_t>(ws, q[11]);
+        ls.clist = at<int32_t>(ws, q[11]) + c->n;
+        ls.fcap = k == 0 ? c->fcap : c->acap;
+        ls.ccap = k == 0 ? c->ccap : 0;
+        ls.n_cells = c->n_cells;
+        HIPCHK(c, hipMemsetAsync(ls.cell_count, 0, 4 * (size_t)c->n_cells, sm));
+    }
+    HIPCHK(c, hipStreamSynchronize(sm));
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    c->step = 0;
+    c->built_step = -1;
+    c->host_steps = 0;
+    c->host_rebuilds = 0;
+    c->bound = true;
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_update_params(bounce_ctx *c, const bounce_params *p)
+{
+    if (!c || !p) return BOUNCE_E_ARG;
+    if (!(p->dt > 0) || !(p->gamma >= 0) || !(p->temperature > 0) || !(p->bound_scale > 0))
+        return fail(c, BOUNCE_E_ARG, "dt, gamma, temperature, bound_scale");
+    c->p.dt = p->dt;
+    c->p.gamma = p->gamma;
+    c->p.temperature = p->temperature;
+    c->p.bound_scale = p->bound_scale;
+    if (!c->have_system) return BOUNCE_OK;
+    make_ou(c);
+    if (c->bound) {
+        Layout L;
+        Offsets o;
+        plan(c, L, o);
+        HIPCHK(c, up(c->stream, c->ws, o.ou_c2, c->ou_c2));
+        std::vector<double> La(MAXT, 0.0);
+        for (int a = 0; a < c->nt; ++a) La[a] = c->L_a[a] * c->p.bound_scale;
+        HIPCHK(c, up(c->stream, c->ws, o.La, La));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    }
+    return BOUNCE_OK;
+}
+
+static bounce_status ready(bounce_ctx *c)
+{
+    if (!c) return BOUNCE_E_ARG;
+    if (!c->have_system || !c->bound) return fail(c, BOUNCE_E_STATE, "set_system and bind first");
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_set_step(bounce_ctx *c, int64_t step)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (step < 0) return BOUNCE_E_ARG;
+    DevState st{};
+    st.step = step;
+    HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->step = step;
+    c->built_step = -1;
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_get_step(const bounce_ctx *c, int64_t *step)
+{
+    if (!c || !step) return BOUNCE_E_ARG;
+    *step = c->step;
+    return BOUNCE_OK;
+}
+
+static PairGlobals pair_globals(const bounce_ctx *c)
+{
+    PairGlobals g{};
+    g.alpha = c->p.ewald_alpha;
+    g.r_on = c->p.r_on;
+    g.r_off = c->p.r_off;
+    g.inv_w = c->p.r_off > c->p.r_on ? 1.0 / (c->p.r_off - c->p.r_on) : 0.0;
+    g.r_cut = c->p.r_cut;
+    g.coulomb = c->p.coulomb;
+    g.n_types = c->nt;
+    return g;
+}
+
+static BuildSpec main_spec(const bounce_ctx *c)
+{
+    BuildSpec b{};
+    const bounce_params &p = c->p;
+    if (p.integrator == BOUNCE_BJAOAJB) {
+        double rf = p.r_off + p.skin;
+        double rmin = p.r_on - p.skin, rmax = p.r_cut + p.skin;
+        b.rf2 = rf * rf;
+        b.rcmin2 = rmin > 0.0 ? rmin * rmin : 0.0;
+        b.rcmax2 = rmax * rmax;
+        b.rsearch = std::max(rf, rmax);
+        b.want_force = 1;
+        b.want_cand = 1;
+    } else {
+        double rf = p.r_cut + p.skin;
+        b.rf2 = rf * rf;
+        b.rsearch = rf;
+        b.want_force = 1;
+        b.want_cand = 0;
+    }
+    b.mirror_sel = -1;
+    return b;
+}
+
+static void enqueue_build(bounce_ctx *c)
+{
+    launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, main_spec(c), c->d_st);
+}
+
+static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
+{
+    PairArgs a{};
+    a.n = c->n;
+    a.mirror_sel = mirror_sel;
+    a.reps = c->d_reps;
+    a.tp = c->tp;
+    a.ls = ls;
+    a.st = c->d_st;
+    a.type_params = c->d_tparams;
+    a.pg = pair_globals(c);
+    return a;
+}
+
+static void enqueue_force(bounce_ctx *c)
+{
+    PairArgs a = pair_args(c, c->main, -1);
+    a.out = c->d_fpair;
+    a.out_global = 0;
+    a.accumulate = 0;
+    launch_pair(c->stream, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
+                c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+}
+
+static StepArgs step_args(bounce_ctx *c, int close, int open)
+{
+    StepArgs a{};
+    a.n = c->n;
+    a.do_close = close;
+    a.do_open = open;
+    a.bounce = c->p.integrator == BOUNCE_BJAOAJB;
+    a.pair_fp64 = c->p.pair_precision == BOUNCE_PAIR_FP64;
+    a.log_events = c->p.log_events;
+    a.max_proposals = c->p.max_proposals;
+    a.reps = c->d_reps;
+    a.tp = c->tp;
+    a.ls = c->main;
+    a.st = c->d_st;
+    a.cnt = c->d_cnt;
+    a.events = c->d_events;
+    a.event_cap = c->p.log_events ? c->p.event_capacity : 0;
+    a.fpair = c->d_fpair;
+    a.pos = c->pos;
+    a.vel = c->vel;
+    a.ou_c2 = c->d_ou_c2;
+    a.L_a = c->d_La;
+    a.type_params = c->d_tparams;
+    a.pg = pair_globals(c);
+    a.dt = c->p.dt;
+    a.half_dt = 0.5 * c->p.dt;
+    a.c1 = std::exp(-c->p.gamma * c->p.dt);
+    a.beta = 1.0 / (KB * c->p.temperature);
+    a.skin_half2 = 0.25 * c->p.skin * c->p.skin;
+    return a;
+}
+
+// one substep of the fused schedule at the current step index c->step
+static void enqueue_substep(bounce_ctx *c, int close, int open)
+{
+    if (c->built_step < 0 || (c->step % c->p.rebuild_interval == 0 && c->built_step != c->step)) {
+        enqueue_build(c);
+        c->built_step = c->step;
+        c->host_rebuilds++;
+    }
+    enqueue_force(c);
+    launch_step(c->stream, step_args(c, close, open));
+    if (open) c->step++;
+}
+
+// a graph of K fused steps starting at a multiple of K (rebuild at its head)
+static bounce_status make_graph(bounce_ctx *c)
+{
+    if (c->graph_exec) return BOUNCE_OK;
+    hipStream_t cap;
+    HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        c->stream = saved;
+        (void)hipStreamDestroy(cap);
+        return fail(c, BOUNCE_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < c->p.rebuild_interval; ++k) {
+        if (k == 0) enqueue_build(c);
+        enqueue_force(c);
+        launch_step(c->stream, step_args(c, 1, 1));
+    }
+    e = hipStreamEndCapture(cap, &c->graph);
+    c->stream = saved;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(c, BOUNCE_E_HIP, std::string("end capture: ") + hipGetErrorString(e));
+    HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_step(bounce_ctx *c, int32_t n_steps)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (n_steps < 0) return BOUNCE_E_ARG;
+    if (n_steps == 0) return BOUNCE_OK;
+    const int64_t K = c->p.rebuild_interval;
+    const int64_t end = c->step + n_steps;
+    // open the first step (F_0 at q_n)
+    enqueue_substep(c, 0, 1);
+    while (c->step < end) {
+        if (c->p.use_graph && c->step % K == 0 && c->step + K <= end) {
+            s = make_graph(c);
+            if (s) return s;
+            HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            c->step += K;
+            c->built_step = c->step - K;
+            c->host_rebuilds++;
+            continue;
+        }
+        enqueue_substep(c, 1, 1);
+    }
+    // close the last step: J(n-1, JB), B(dt/2) with F_0 at q_n
+    enqueue_substep(c, 1, 0);
+    c->host_steps += n_steps;
+    HIPCHK(c, hipGetLastError());
+    return BOUNCE_OK;
+}
+
+static bounce_status status_from_bits(bounce_ctx *c, uint32_t bits)
+{
+    if (!bits) return BOUNCE_OK;
+    if (bits & ST_NONFINITE) return fail(c, BOUNCE_E_NONFINITE, bounce_status_string(BOUNCE_E_NONFINITE));
+    if (bits & ST_GRID) return fail(c, BOUNCE_E_GRID, bounce_status_string(BOUNCE_E_GRID));
+    if (bits & ST_CAPACITY) return fail(c, BOUNCE_E_CAPACITY, bounce_status_string(BOUNCE_E_CAPACITY));
+    if (bits & ST_SKIN) return fail(c, BOUNCE_E_SKIN, bounce_status_string(BOUNCE_E_SKIN));
+    if (bits & ST_POISSON) return fail(c, BOUNCE_E_POISSON_CAP, bounce_status_string(BOUNCE_E_POISSON_CAP));
+    if (bits & ST_BOUND) return fail(c, BOUNCE_E_BOUND, bounce_status_string(BOUNCE_E_BOUND));
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_sync(bounce_ctx *c)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DevState st;
+    HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof st, hipMemcpyDeviceToHost));
+    if (st.step != c->step)
+        return fail(c, BOUNCE_E_STATE, "device step counter out of step with the host");
+    return status_from_bits(c, st.status);
+}
+
+static BuildSpec aux_spec(const bounce_ctx *c)
+{
+    BuildSpec b{};
+    double r = c->p.r_cut + 0.01;
+    b.rf2 = r * r;
+    b.rsearch = r;
+    b.want_force = 1;
+    b.want_cand = 0;
+    b.mirror_sel = 0;
+    return b;
+}
+
+bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!grad || (which & ~15) || !which) return BOUNCE_E_ARG;
+    hipStream_t sm = c->stream;
+    const int pairs[3] = {BOUNCE_G_SHORT, BOUNCE_G_LONG, BOUNCE_G_FULL};
+    const int modes[3] = {MODE_SHORT, MODE_LONG, MODE_FULL};
+    int first = 1;
+    if (which & (BOUNCE_G_SHORT | BOUNCE_G_LONG | BOUNCE_G_FULL))
+        launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    for (int k = 0; k < 3; ++k) {
+        if (!(which & pairs[k])) continue;
+        PairArgs a = pair_args(c, c->aux, 0);
+        a.out = grad;
+        a.out_global = 1;
+        a.accumulate = !first;
+        launch_pair(sm, modes[k], c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+        first = 0;
+    }
+    if (which & BOUNCE_G_BONDED) {
+        if (first) HIPCHK(c, hipMemsetAsync(grad, 0, 24 * (size_t)c->n, sm));
+        launch_bonded_grad(sm, c->n, c->pos, c->d_reps, c->tp, grad);
+    }
+    return bounce_sync(c);
+}
+
+bounce_status bounce_compute_energies(bounce_ctx *c, double *out)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!out) return BOUNCE_E_ARG;
+    hipStream_t sm = c->stream;
+    launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    PairArgs a = pair_args(c, c->aux, 0);
+    a.atom_out = c->d_atom;
+    a.energy_total = 0;
+    a.atom_stride = 5;
+    a.atom_col = 2;
+    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_atom_energy(sm, c->n, c->pos, c->vel, c->d_reps, c->tp, c->d_atom);
+    launch_segment_sum(sm, c->R, c->d_rep_off, c->d_atom, 5, 5, 0, c->d_seg);
+    std::vector<double> seg(5 * c->R);
+    HIPCHK(c, hipMemcpyAsync(seg.data(), c->d_seg, 8 * seg.size(), hipMemcpyDeviceToHost, sm));
+    s = bounce_sync(c);
+    if (s) return s;
+    for (int32_t r = 0; r < c->R; ++r) {
+        const double *v = &seg[5 * r];
+        double *o = out + 7 * r;
+        int64_t na = c->rep_off[r + 1] - c->rep_off[r];
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; o[4] = v[2] + v[3]; o[5] = v[4];
+        o[6] = 2.0 * v[4] / (3.0 * (double)na * KB);
+    }
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_get_counters(bounce_ctx *c, int32_t replica, bounce_counters *out)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!out || replica < 0 || replica >= c->R) return BOUNCE_E_ARG;
+    RepCounters rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&rc, c->d_cnt + replica, sizeof rc, hipMemcpyDeviceToHost));
+    out->proposals = (int64_t)rc.proposals;
+    out->accepted = (int64_t)rc.accepted;
+    out->bound_violations = (int64_t)rc.bound_violations;
+    out->rebuilds = c->host_rebuilds;
+    out->steps = c->host_steps;
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_get_events(bounce_ctx *c, bounce_event *host, int64_t cap, int64_t *n_total)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!n_total || cap < 0 || (cap > 0 && !host)) return BOUNCE_E_ARG;
+    DevState st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof st, hipMemcpyDeviceToHost));
+    *n_total = st.n_events;
+    int64_t kept = std::min<int64_t>(st.n_events, c->p.log_events ? c->p.event_capacity : 0);
+    int64_t k = std::min<int64_t>(kept, cap);
+    static_assert(sizeof(Event) == sizeof(bounce_event), "event layout");
+    if (k > 0) HIPCHK(c, hipMemcpy(host, c->d_events, sizeof(Event) * k, hipMemcpyDeviceToHost));
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_get_list(bounce_ctx *c, int32_t which, int64_t *row_ptr, int32_t *col,
+                              int64_t cap)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!row_ptr || (which != BOUNCE_LIST_FORCE && which != BOUNCE_LIST_CAND)) return BOUNCE_E_ARG;
+    if (which == BOUNCE_LIST_CAND && c->p.integrator != BOUNCE_BJAOAJB) return BOUNCE_E_ARG;
+    if (c->built_step < 0) return fail(c, BOUNCE_E_STATE, "no list built yet");
+    int32_t rcap = which == 0 ? c->fcap : c->ccap;
+    launch_list_to_global(c->stream, c->n, c->main, which, c->d_xcnt, c->d_xcol, rcap);
+    s = bounce_sync(c);
+    if (s) return s;
+    std::vector<int32_t> cnt(c->n);
+    std::vector<int32_t> rows((size_t)c->n * rcap);
+    HIPCHK(c, hipMemcpy(cnt.data(), c->d_xcnt, 4 * (size_t)c->n, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(rows.data(), c->d_xcol, 4 * rows.size(), hipMemcpyDeviceToHost));
+    row_ptr[0] = 0;
+    for (int32_t g = 0; g < c->n; ++g) row_ptr[g + 1] = row_ptr[g] + cnt[g];
+    if (row_ptr[c->n] > cap) return fail(c, BOUNCE_E_ARG, "col capacity too small");
+    for (int32_t g = 0; g < c->n; ++g)
+        std::memcpy(col + row_ptr[g], &rows[(size_t)g * rcap], 4 * (size_t)cnt[g]);
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_rate_bounds(const bounce_ctx *c, double *L_ab, double *L_a)
+{
+    if (!c || !L_ab || !L_a) return BOUNCE_E_ARG;
+    if (!c->have_system) return BOUNCE_E_STATE;
+    std::memcpy(L_ab, c->L_ab.data(), 8 * c->L_ab.size());
+    std::memcpy(L_a, c->L_a.data(), 8 * c->L_a.size());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_jump_halfstep(bounce_ctx *c, int64_t step, int32_t phase)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (c->p.integrator != BOUNCE_BJAOAJB) return fail(c, BOUNCE_E_ARG, "BAOAB has no J step");
+    if (phase != BOUNCE_PH_JA && phase != BOUNCE_PH_JB) return BOUNCE_E_ARG;
+    if (c->built_step != c->step) {
+        enqueue_build(c);
+        c->built_step = c->step;
+        c->host_rebuilds++;
+    }
+    JumpArgs ja{};
+    ja.s = step_args(c, 0, 0);
+    ja.step = step;
+    ja.phase = phase;
+    launch_jump(c->stream, ja);
+    return bounce_sync(c);
+}
+
+bounce_status bounce_direct_energy(bounce_ctx *c, const double *pos, const double *params,
+                                   double *energy)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!pos || !params || !energy) return BOUNCE_E_ARG;
+    hipStream_t sm = c->stream;
+    launch_build(sm, c->n, pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    PairArgs a = pair_args(c, c->aux, 0);
+    a.type_params = params;
+    a.atom_out = c->d_atom;
+    a.energy_total = 1;
+    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_segment_sum(sm, 1, c->d_one_seg, c->d_atom, 1, 1, 0, energy);
+    HIPCHK(c, hipGetLastError());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_direct_energy_bwd(bounce_ctx *c, const double *pos, const double *params,
+                                       const double *grad_out, double *grad_pos,
+                                       double *grad_params)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!pos || !params || !grad_out || !grad_pos || !grad_params) return BOUNCE_E_ARG;
+    hipStream_t sm = c->stream;
+    launch_build(sm, c->n, pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    PairArgs a = pair_args(c, c->aux, 0);
+    a.type_params = params;
+    a.out = grad_pos;
+    a.out_global = 1;
+    a.accumulate = 0;
+    a.atom_out = c->d_atom;
+    launch_pair(sm, MODE_DBWD, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_dbwd_finish(sm, c->n, c->nt, c->d_atom, c->tp.type, params, grad_out, grad_pos,
+                       grad_params, nullptr);
+    HIPCHK(c, hipGetLastError());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, double *avg_ms)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!avg_ms || reps < 1 || (which != 0 && which != 1)) return BOUNCE_E_ARG;
+    if (c->built_step < 0) {
+        enqueue_build(c);
+        c->built_step = c->step;
+        c->host_rebuilds++;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int32_t k = 0; k < reps; ++k) {
+        if (which == 0) enqueue_force(c);
+        else enqueue_build(c);
+    }
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    return bounce_sync(c);
+}

@@ -1,0 +1,199 @@
+// Device-side building blocks of the BOUNCE library: the Philox4x64-10
+// stream, the shifted-force pair field and the switch, shared by the
+// list-build, pair, step and gradient kernels.  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bnc {
+
+constexpr double KE = 332.0637;        // kcal A / (mol e^2)
+constexpr double KB = 0.0019872041;    // kcal / (mol K)
+constexpr double ACC = 4.184e-4;       // (kcal/mol/A)/amu -> A/fs^2
+constexpr double TWO_OVER_SQRTPI = 1.1283791670955126;
+constexpr int MAXT = 8;
+
+// latched device conditions
+enum : uint32_t {
+    ST_CAPACITY = 1u, ST_SKIN = 2u, ST_BOUND = 4u, ST_POISSON = 8u, ST_NONFINITE = 16u,
+    ST_GRID = 32u
+};
+
+// per-replica geometry of the list grid
+struct RepInfo {
+    double box[3], inv_box[3];
+    double cinv[3];        // periodic: ncell / box
+    double cw[3];          // cell edge
+    double origin[3];      // droplet grid origin
+    double inv_cell;       // droplet: 1 / cell_size
+    int32_t ncell[3];
+    int32_t periodic;
+    int64_t atom_off;
+    int32_t n_atoms;
+    int32_t cell_off;
+    uint64_t key0, key1;   // Philox key (seed, replica)
+};
+
+// small device-resident state: step counter, latched status, counters
+struct DevState {
+    int64_t step;
+    int64_t n_events;
+    uint32_t status;
+    uint32_t done_blocks;
+    uint32_t pad[2];
+};
+
+struct RepCounters {
+    unsigned long long proposals, accepted, bound_violations, rebuilds, steps;
+};
+
+struct Event {
+    int64_t step;
+    int32_t phase, atom, k, partner, accepted, replica;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): 10 rounds, Weyl key schedule.
+// ---------------------------------------------------------------------------
+struct U4 { uint64_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(const RepInfo &ri, int64_t step, int32_t phase, int32_t atom,
+                                   uint64_t k)
+{
+    return philox4x64_10((uint64_t)step, ((uint64_t)(uint32_t)phase << 32) | (uint32_t)atom, k, 0,
+                         ri.key0, ri.key1);
+}
+
+// uniform in (0,1): top 52 bits plus one half, times 2^-52 (exact)
+__device__ __forceinline__ double u01(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+// ---------------------------------------------------------------------------
+// Type-pair constants of the shifted-force potential (Lorentz-Berthelot).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct TypePair {
+    R qq;      // KE q_a q_b
+    R eps4;    // 4 eps_ab
+    R sig2;    // sigma_ab^2
+    R du_rc;   // u'(rc)
+    R u_rc;    // u(rc)
+    R pad[3];
+};
+
+struct PairGlobals {
+    double alpha;     // Ewald splitting (1/A)
+    double r_on, r_off, inv_w;  // switch window and 1/(r'' - r')
+    double r_cut;
+    int32_t coulomb;  // 0 bare, 1 erfc
+    int32_t n_types;
+};
+
+// Coulomb kernel g(r) and g'(r)
+template <typename R>
+__device__ __forceinline__ void coul_g(R r, R rinv, R alpha, int coulomb, R &g, R &dg);
+
+template <>
+__device__ __forceinline__ void coul_g<float>(float r, float rinv, float alpha, int coulomb,
+                                              float &g, float &dg)
+{
+    if (coulomb) {
+        float ar = alpha * r;
+        float e = erfcf(ar);
+        float ex = __expf(-ar * ar);
+        g = e * rinv;
+        dg = -(g + (float)TWO_OVER_SQRTPI * alpha * ex) * rinv;
+    } else {
+        g = rinv;
+        dg = -rinv * rinv;
+    }
+}
+
+template <>
+__device__ __forceinline__ void coul_g<double>(double r, double rinv, double alpha, int coulomb,
+                                               double &g, double &dg)
+{
+    if (coulomb) {
+        double ar = alpha * r;
+        double e = erfc(ar);
+        double ex = exp(-ar * ar);
+        g = e * rinv;
+        dg = -(g + TWO_OVER_SQRTPI * alpha * ex) * rinv;
+    } else {
+        g = rinv;
+        dg = -rinv * rinv;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_(R x);
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x) { return __frsqrt_rn(x); }
+template <>
+__device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
+
+// W'_sf(r) = u'(r) - u'(rc) (requires r < rc); also returns 1/r
+template <typename R>
+__device__ __forceinline__ R pair_dw(R r2, const TypePair<R> &tp, R alpha, int coulomb, R &r_out,
+                                     R &rinv_out)
+{
+    R rinv = rsqrt_<R>(r2);
+    R r = r2 * rinv;
+    R g, dg;
+    coul_g<R>(r, rinv, alpha, coulomb, g, dg);
+    R rinv2 = rinv * rinv;
+    R s2 = tp.sig2 * rinv2;
+    R s6 = s2 * s2 * s2;
+    R dlj = tp.eps4 * ((R)6 * s6 - (R)12 * s6 * s6) * rinv;
+    r_out = r;
+    rinv_out = rinv;
+    return tp.qq * dg + dlj - tp.du_rc;
+}
+
+// quintic smoothstep switch on [r', r'']
+template <typename R>
+__device__ __forceinline__ R switch_chi(R r, R r_on, R inv_w)
+{
+    R x = (r - r_on) * inv_w;
+    x = x < (R)0 ? (R)0 : (x > (R)1 ? (R)1 : x);
+    return x * x * x * ((R)10 + x * ((R)6 * x - (R)15));
+}
+
+// minimum-image displacement in FP64.  The list-build translation unit is
+// compiled without FMA contraction, so there these expressions round exactly
+// where written (the list predicate must be reproducible bit for bit).
+__device__ __forceinline__ void min_image(const RepInfo &ri, double &dx, double &dy, double &dz)
+{
+    if (ri.periodic) {
+        dx = dx - ri.box[0] * rint(dx * ri.inv_box[0]);
+        dy = dy - ri.box[1] * rint(dy * ri.inv_box[1]);
+        dz = dz - ri.box[2] * rint(dz * ri.inv_box[2]);
+    }
+}
+
+__device__ __forceinline__ double norm2_exact(double dx, double dy, double dz)
+{
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ uint32_t atomic_or_status(DevState *st, uint32_t bits)
+{
+    return atomicOr(&st->status, bits);
+}
+
+}  // namespace bnc

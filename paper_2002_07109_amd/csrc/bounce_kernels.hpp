@@ -1,0 +1,79 @@
+// Launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include "bounce_lists.hpp"
+
+namespace bnc {
+
+enum PairMode { MODE_SHORT = 0, MODE_FULL = 1, MODE_LONG = 2, MODE_ENERGY = 3, MODE_DBWD = 4 };
+
+struct PairArgs {
+    int32_t n;
+    int32_t mirror_sel;           // -1: device step parity, 0/1 fixed
+    const RepInfo *reps;
+    Topo tp;
+    ListSet ls;
+    const DevState *st;
+    const double *type_params;    // [3][n_types]: charge, eps, sigma
+    PairGlobals pg;
+    double *out;                  // gradient [N][3]
+    int32_t out_global;           // 1: caller order, 0: sorted order
+    int32_t accumulate;           // 1: out += g
+    double *atom_out;             // ENERGY: per-atom energies; DBWD: [N][3*MAXT] basis sums
+    int32_t list_sel;             // 0: force list rows, 1: candidate rows
+    int32_t energy_total;         // ENERGY: 1 -> atom_out[g] = coul + lj (stride 1)
+    int32_t atom_stride;          // ENERGY with energy_total = 0: (coul, lj) at
+    int32_t atom_col;             //   atom_out[g * atom_stride + atom_col + {0,1}]
+};
+
+struct StepArgs {
+    int32_t n;
+    int32_t do_close;             // finish step n-1: J(n-1, JB), B(dt/2)
+    int32_t do_open;              // step n: B(dt/2), J(n, JA), A, O, A
+    int32_t bounce;               // 1: jumps on
+    int32_t pair_fp64;            // jump pair field precision
+    int32_t log_events;
+    int32_t max_proposals;
+    int32_t pad;
+    const RepInfo *reps;
+    Topo tp;
+    ListSet ls;
+    DevState *st;
+    RepCounters *cnt;
+    Event *events;
+    int64_t event_cap;
+    const double *fpair;          // [N][3] sorted order, pair part of F_0
+    double *pos;                  // [N][3] caller order
+    double *vel;                  // [N][3] caller order
+    const double *ou_c2;          // [N] O-step noise amplitude
+    const double *L_a;            // [n_types] rate bounds (bound_scale applied)
+    const double *type_params;
+    PairGlobals pg;
+    double dt, half_dt, c1, beta;
+    double skin_half2;            // (s/2)^2
+};
+
+struct JumpArgs {
+    StepArgs s;
+    int64_t step;
+    int32_t phase;
+};
+
+void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
+                  const int32_t *cell_rep, const Topo &tp, const ListSet &ls, const BuildSpec &bs,
+                  DevState *st);
+void launch_pair(hipStream_t sm, int mode, int fp64, const PairArgs &a);
+void launch_bonded_grad(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
+                        const Topo &tp, double *out);
+void launch_atom_energy(hipStream_t sm, int32_t n, const double *pos, const double *vel,
+                        const RepInfo *reps, const Topo &tp, double *atom5);
+void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, const double *vals,
+                        int32_t width, int32_t stride, int32_t col0, double *out);
+void launch_step(hipStream_t sm, const StepArgs &a);
+void launch_jump(hipStream_t sm, const JumpArgs &a);
+void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
+                           int32_t *cnt_global, int32_t *col_global, int32_t cap);
+void launch_dbwd_finish(hipStream_t sm, int32_t n, int32_t n_types, const double *atom_basis,
+                        const int32_t *type, const double *type_params, const double *grad_out,
+                        double *grad_pos, double *grad_params, double *scratch);
+
+}  // namespace bnc

@@ -1,0 +1,53 @@
+// Host/device view of one set of sorted atom arrays and pair lists.
+#pragma once
+#include "bounce_device.hpp"
+
+namespace bnc {
+
+struct ListSet {
+    int32_t *perm;        // sorted position -> caller id
+    int32_t *inv_perm;    // caller id -> sorted position
+    int32_t *cell_of;     // caller id -> global cell
+    int32_t *slot;        // caller id -> arrival slot in its cell
+    int32_t *cell_count;  // [n_cells]
+    int32_t *cell_start;  // [n_cells + 1]
+    double4 *x[2];        // sorted positions (x, y, z, type), double-buffered by step parity
+    double *q_build;      // [N][3] positions at the build (skin guard)
+    int32_t *fcnt;        // force list: row length per sorted atom
+    int32_t *flist;       // [N][fcap] sorted partner positions
+    int32_t *ccnt;        // candidate list (jump partners)
+    int32_t *clist;       // [N][ccap]
+    int32_t fcap, ccap;
+    int32_t n_cells;
+    int32_t pad;
+};
+
+// what one build produces
+struct BuildSpec {
+    double rf2;           // force-list radius squared
+    double rcmin2;        // candidate lower radius squared (0: none)
+    double rcmax2;        // candidate upper radius squared
+    double rsearch;       // cell-search radius (max of the radii)
+    int32_t want_force;
+    int32_t want_cand;
+    int32_t mirror_sel;   // -1: mirror of the device step parity, 0/1: fixed
+    int32_t pad;
+};
+
+// static per-atom topology on the device
+struct Topo {
+    const int32_t *type;       // [N]
+    const int32_t *rep_of;     // [N]
+    const double *acc_m;       // [N] ACC / m
+    const double *inv_mass;    // [N] 1 / m
+    const int32_t *excl_ptr;   // [N+1]
+    const int32_t *excl_idx;   // caller ids
+    const int32_t *bt_ptr;     // [N+1] bonded terms touching each atom
+    const int32_t *bt;         // term code: (kind << 28) | index
+    const int32_t *bond_ij;    // [nb][2]
+    const double *bond_kr;     // [nb][2] (k, r0)
+    const int32_t *angle_ijk;  // [na][3]
+    const double *angle_kt;    // [na][2] (k, theta0)
+};
+
+}  // namespace bnc

@@ -1,0 +1,277 @@
+// The integrator kernel: one thread per atom runs, for its own atom,
+//   [close step n-1]  J(n-1, JB) and B(dt/2)        (end of B J A O A J B)
+//   [open  step n  ]  B(dt/2), J(n, JA), A, O, A    (start of the next step)
+// with F_0 = pair part (from the pair kernel) + bonded terms at q_n.
+// Positions of other atoms are read from the sorted mirror of q_n and the new
+// positions q_{n+1} go to the other mirror buffer, so all threads may run the
+// step concurrently (Sec. IV.A: at fixed q the per-atom velocity chains are
+// independent).  J is the thinned jump chain of Sec. IV.B / Sec. V: one Poisson
+// count with mean |C_i| beta |v_i| L dt/2, then for each proposal a uniform
+// partner from C_i, an accept test U < lambda/lambda*, and a reflection.
+#include "bounce_kernels.hpp"
+#include "bounce_bonded.hpp"
+
+namespace bnc {
+
+template <typename R>
+__device__ void init_pair_table(TypePair<R> *tab, const double *tpar, const PairGlobals &pg)
+{
+    const int nt = pg.n_types;
+    for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
+        int a = k / nt, b = k % nt;
+        double qq = KE * tpar[a] * tpar[b];
+        double eps = sqrt(tpar[nt + a] * tpar[nt + b]);
+        double sig = 0.5 * (tpar[2 * nt + a] + tpar[2 * nt + b]);
+        double rc = pg.r_cut, g, dg;
+        coul_g<double>(rc, 1.0 / rc, pg.alpha, pg.coulomb, g, dg);
+        double sr = sig / rc, s6 = sr * sr * sr * sr * sr * sr, s12 = s6 * s6;
+        double dul = eps != 0.0 ? 4.0 * eps * (-12.0 * s12 + 6.0 * s6) / rc : 0.0;
+        TypePair<R> t;
+        t.qq = (R)qq; t.eps4 = (R)(4.0 * eps); t.sig2 = (R)(sig * sig);
+        t.du_rc = (R)(qq * dg + dul); t.u_rc = (R)0;
+        t.pad[0] = t.pad[1] = t.pad[2] = (R)0;
+        tab[k] = t;
+    }
+}
+
+// long-range field F_ij = chi(r) W'_sf(r) d/r on i (zero outside r' < r < rc)
+template <typename R>
+__device__ __forceinline__ void long_field(const TypePair<R> &tp, const PairGlobals &pg, double dx,
+                                           double dy, double dz, double F[3])
+{
+    F[0] = F[1] = F[2] = 0.0;
+    const R rx = (R)dx, ry = (R)dy, rz = (R)dz;
+    const R r2 = rx * rx + ry * ry + rz * rz;
+    const R rc = (R)pg.r_cut;
+    if (!(r2 < rc * rc)) return;
+    R r, rinv;
+    const R dw = pair_dw<R>(r2, tp, (R)pg.alpha, pg.coulomb, r, rinv);
+    if (!(r > (R)pg.r_on)) return;
+    const R f = switch_chi<R>(r, (R)pg.r_on, (R)pg.inv_w) * dw * rinv;
+    F[0] = (double)(f * rx);
+    F[1] = (double)(f * ry);
+    F[2] = (double)(f * rz);
+}
+
+struct JumpTally {
+    unsigned long long prop, acc, bound;
+};
+
+// the velocity chain of one atom over dt/2 at fixed positions
+template <typename R>
+__device__ void jump_atom(const StepArgs &a, const TypePair<R> *tab, const double4 *X, int32_t s,
+                          int32_t lid, int32_t rep, const RepInfo &ri, int ti, const double q[3],
+                          double v[3], int64_t step, int32_t phase, JumpTally &tally)
+{
+    const int32_t c = a.ls.ccnt[s];
+    const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    const double L = a.L_a[ti];
+    if (c == 0 || v0 == 0.0 || L == 0.0) return;
+    const double mu = (double)c * a.beta * v0 * L * a.half_dt;
+    const U4 w0 = draw(ri, step, phase, lid, 0);
+    const double U = u01(w0.x);
+    int32_t M = 0;
+    double term = exp(-mu), cdf = term;
+    while (U > cdf) {
+        ++M;
+        if (M > a.max_proposals) {
+            atomicOr(&a.st->status, ST_POISSON);
+            return;
+        }
+        term *= mu / (double)M;
+        cdf += term;
+    }
+    const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
+    const int nt = a.pg.n_types;
+    for (int32_t k = 1; k <= M; ++k) {
+        const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
+        const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
+        const int32_t p = crow[J];
+        const double u = u01(w.y);
+        const double4 xj = X[p];
+        double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
+        min_image(ri, dx, dy, dz);
+        double F[3];
+        long_field<R>(tab[ti * nt + (int)xj.w], a.pg, dx, dy, dz, F);
+        const double sdot = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+        // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
+        const int acc = (u * v0 * L) < sdot;
+        if (sdot > v0 * L * (1.0 + 1e-9)) {
+            tally.bound++;
+            atomicOr(&a.st->status, ST_BOUND);
+        }
+        if (acc) {
+            const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+            const double cf = 2.0 * sdot / f2;
+            v[0] = v[0] - cf * F[0];
+            v[1] = v[1] - cf * F[1];
+            v[2] = v[2] - cf * F[2];
+            tally.acc++;
+        }
+        tally.prop++;
+        if (a.log_events) {
+            const unsigned long long slot =
+                atomicAdd((unsigned long long *)&a.st->n_events, 1ull);
+            if ((int64_t)slot < a.event_cap) {
+                Event ev;
+                ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k;
+                ev.partner = a.ls.perm[p] - (int32_t)ri.atom_off;
+                ev.accepted = acc; ev.replica = rep;
+                a.events[slot] = ev;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+__device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t)
+{
+    const int32_t first = __shfl(rep, 0, 64);
+    const bool uniform = __all(!active || rep == first);
+    if (uniform) {
+        unsigned long long p = wave_sum(active ? t.prop : 0), c = wave_sum(active ? t.acc : 0),
+                           b = wave_sum(active ? t.bound : 0);
+        if ((threadIdx.x & 63) == 0 && (p | c | b)) {
+            atomicAdd(&a.cnt[first].proposals, p);
+            atomicAdd(&a.cnt[first].accepted, c);
+            if (b) atomicAdd(&a.cnt[first].bound_violations, b);
+        }
+    } else if (active && (t.prop | t.acc | t.bound)) {
+        atomicAdd(&a.cnt[rep].proposals, t.prop);
+        atomicAdd(&a.cnt[rep].accepted, t.acc);
+        if (t.bound) atomicAdd(&a.cnt[rep].bound_violations, t.bound);
+    }
+}
+
+template <typename R, bool BOUNCE>
+__global__ void __launch_bounds__(256) k_step(StepArgs a)
+{
+    __shared__ TypePair<R> tab[MAXT * MAXT];
+    if (BOUNCE) init_pair_table<R>(tab, a.type_params, a.pg);
+    __syncthreads();
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = s < a.n;
+    const int64_t n = a.st->step;
+    const int32_t par = (int32_t)(n & 1);
+    const double4 *__restrict__ X = a.ls.x[par];
+    double4 *__restrict__ Y = a.ls.x[par ^ 1];
+    JumpTally tally = {0, 0, 0};
+    int32_t rep = 0;
+    if (active) {
+        const int32_t g = a.ls.perm[s];
+        rep = a.tp.rep_of[g];
+        const RepInfo &ri = a.reps[rep];
+        const int32_t lid = g - (int32_t)ri.atom_off;
+        const double4 xi = X[s];
+        const int ti = (int)xi.w;
+        double q[3] = {xi.x, xi.y, xi.z};
+        double F[3] = {a.fpair[3 * (int64_t)s], a.fpair[3 * (int64_t)s + 1],
+                       a.fpair[3 * (int64_t)s + 2]};
+        bonded_grad_atom(g, MirrorPos{X, a.ls.inv_perm}, ri, a.tp, F);
+        double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
+        const double km = a.half_dt * a.tp.acc_m[g];
+        if (a.do_close) {
+            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n - 1, 2, tally);
+            v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
+        }
+        if (a.do_open) {
+            v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
+            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n, 0, tally);
+            for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
+            // O: Ornstein-Uhlenbeck exact step with Box-Muller normals
+            const U4 w = draw(ri, n, 1, lid, 0);
+            const double u1 = u01(w.x), u2 = u01(w.y), u3 = u01(w.z), u4 = u01(w.w);
+            const double ra = sqrt(-2.0 * log(u1)), rb = sqrt(-2.0 * log(u3));
+            const double G3[3] = {ra * cos(2.0 * M_PI * u2), ra * sin(2.0 * M_PI * u2),
+                                  rb * cos(2.0 * M_PI * u4)};
+            const double c2 = a.ou_c2[g];
+            for (int c = 0; c < 3; ++c) v[c] = a.c1 * v[c] + c2 * G3[c];
+            for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
+            const double *qb = a.ls.q_build + 3 * (int64_t)g;
+            const double ddx = q[0] - qb[0], ddy = q[1] - qb[1], ddz = q[2] - qb[2];
+            if (ddx * ddx + ddy * ddy + ddz * ddz >= a.skin_half2) atomicOr(&a.st->status, ST_SKIN);
+            a.pos[3 * (int64_t)g] = q[0];
+            a.pos[3 * (int64_t)g + 1] = q[1];
+            a.pos[3 * (int64_t)g + 2] = q[2];
+            Y[s] = make_double4(q[0], q[1], q[2], xi.w);
+        }
+        a.vel[3 * (int64_t)g] = v[0];
+        a.vel[3 * (int64_t)g + 1] = v[1];
+        a.vel[3 * (int64_t)g + 2] = v[2];
+        bool fin = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(q[0]) &&
+                   isfinite(q[1]) && isfinite(q[2]);
+        if (!fin) atomicOr(&a.st->status, ST_NONFINITE);
+    }
+    if (BOUNCE) flush_tally(a, rep, active, tally);
+    if (a.do_open) {
+        // the last block to finish advances the device step counter
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned int done = atomicAdd(&a.st->done_blocks, 1u);
+            if (done == gridDim.x - 1) {
+                a.st->done_blocks = 0;
+                a.st->step = n + 1;
+                __threadfence();
+            }
+        }
+    }
+}
+
+void launch_step(hipStream_t sm, const StepArgs &a)
+{
+    if (a.n <= 0) return;
+    dim3 grid((a.n + 255) / 256), block(256);
+    if (a.bounce) {
+        if (a.pair_fp64) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, sm, a);
+        else hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, sm, a);
+    } else {
+        hipLaunchKernelGGL((k_step<float, false>), grid, block, 0, sm, a);
+    }
+}
+
+// J half-step alone at the current positions (diagnostics and parity tests)
+template <typename R>
+__global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
+{
+    const StepArgs &a = ja.s;
+    __shared__ TypePair<R> tab[MAXT * MAXT];
+    init_pair_table<R>(tab, a.type_params, a.pg);
+    __syncthreads();
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = s < a.n;
+    const int32_t par = (int32_t)(a.st->step & 1);
+    const double4 *X = a.ls.x[par];
+    JumpTally tally = {0, 0, 0};
+    int32_t rep = 0;
+    if (active) {
+        const int32_t g = a.ls.perm[s];
+        rep = a.tp.rep_of[g];
+        const RepInfo &ri = a.reps[rep];
+        const double4 xi = X[s];
+        double q[3] = {xi.x, xi.y, xi.z};
+        double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
+        jump_atom<R>(a, tab, X, s, g - (int32_t)ri.atom_off, rep, ri, (int)xi.w, q, v, ja.step,
+                     ja.phase, tally);
+        a.vel[3 * (int64_t)g] = v[0];
+        a.vel[3 * (int64_t)g + 1] = v[1];
+        a.vel[3 * (int64_t)g + 2] = v[2];
+    }
+    flush_tally(a, rep, active, tally);
+}
+
+void launch_jump(hipStream_t sm, const JumpArgs &a)
+{
+    if (a.s.n <= 0) return;
+    dim3 grid((a.s.n + 255) / 256), block(256);
+    if (a.s.pair_fp64) hipLaunchKernelGGL((k_jump<double>), grid, block, 0, sm, a);
+    else hipLaunchKernelGGL((k_jump<float>), grid, block, 0, sm, a);
+}
+
+}  // namespace bnc

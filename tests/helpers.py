@@ -1,0 +1,71 @@
+"""Shared test set-up: one configuration dict drives both the oracle and the
+GPU library, so the two see the same parameters and the same seeded inputs."""
+import copy
+import os
+
+import numpy as np
+
+from workloads import tip3p_params, water_droplet
+
+FF = tip3p_params()
+
+# bare-Coulomb droplets: with the 5/6 A split the B J A O A J B scheme heats a
+# flexible-water droplet quickly at dt = 1 fs (both implementations agree); the
+# droplet trajectories run at dt = 0.25 fs, where the scheme is stable
+DROPLET = dict(integrator=0, periodic=0, coulomb=0, dt=0.25, gamma=1e-3, temperature=300.0,
+               r_on=5.0, r_off=6.0, r_cut=9.0, skin=2.0, ewald_alpha=0.35, rebuild_interval=10,
+               seed=0, bound_scale=1.0)
+BOX = dict(DROPLET, periodic=1, coulomb=1, r_on=6.0, r_off=7.0, dt=1.0)
+
+
+def oracle_params(orc, sys, cfg, replica=0):
+    return orc.make_params(sys, integrator=cfg["integrator"], coulomb=cfg["coulomb"],
+                           dt=cfg["dt"], gamma=cfg["gamma"], temperature=cfg["temperature"],
+                           r_on=cfg["r_on"], r_off=cfg["r_off"], r_cut=cfg["r_cut"],
+                           skin=cfg["skin"], ewald_alpha=cfg["ewald_alpha"],
+                           rebuild_interval=cfg["rebuild_interval"], seed=cfg["seed"],
+                           replica=replica, bound_scale=cfg["bound_scale"],
+                           periodic=bool(cfg["periodic"]))
+
+
+def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_graph=False):
+    import paper_2002_07109_amd as B
+    cell = (systems[0] if isinstance(systems, (list, tuple)) else systems).cell_size
+    p = B.make_params(integrator=cfg["integrator"], coulomb=cfg["coulomb"],
+                      periodic=cfg["periodic"], dt=cfg["dt"], gamma=cfg["gamma"],
+                      temperature=cfg["temperature"], r_on=cfg["r_on"], r_off=cfg["r_off"],
+                      r_cut=cfg["r_cut"], skin=cfg["skin"], ewald_alpha=cfg["ewald_alpha"],
+                      rebuild_interval=cfg["rebuild_interval"], seed=cfg["seed"],
+                      bound_scale=cfg["bound_scale"], cell_size=cell,
+                      pair_precision=B.PAIR_FP64 if fp64 else B.PAIR_FP32,
+                      log_events=int(log_events), event_capacity=event_capacity,
+                      use_graph=int(use_graph))
+    return B.Simulation(systems, p, FF["charge"], FF["eps"], FF["sigma"])
+
+
+def rel_err(a, b):
+    """max_i |a_i - b_i| / RMS_i |b_i| over per-atom 3-vectors."""
+    a, b = np.asarray(a), np.asarray(b)
+    rms = np.sqrt(np.mean(np.sum(b * b, axis=-1)))
+    return float(np.max(np.linalg.norm(a - b, axis=-1)) / rms)
+
+
+def event_keys(ev, fields=("step", "phase", "atom", "k", "partner", "accepted")):
+    keys = np.stack([ev[f].astype(np.int64) for f in fields], 1)
+    if keys.size == 0:
+        return keys
+    return keys[np.lexsort(keys.T[::-1])]
+
+
+_FIX = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "relaxed_droplets.npz")
+_SPEC = {"c0": (216, 0, 5), "r0": (40, 3, 200), "r1": (150, 3, 201), "r2": (90, 3, 202)}
+
+
+def relaxed_droplet(name):
+    """Seeded droplet with the oracle-relaxed positions and velocities of
+    tests/golden/relaxed_droplets.npz (written by tests/golden/make_fixtures.py)."""
+    nw, seed, stream = _SPEC[name]
+    s = copy.deepcopy(water_droplet(n_waters=nw, seed=seed, stream=stream))
+    z = np.load(_FIX)
+    s.pos, s.vel = z[name + "_pos"].copy(), z[name + "_vel"].copy()
+    return s

@@ -1,0 +1,215 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (max_i |dF_i| / RMS_i |F_i| for per-atom vectors):
+  FP64 pair arithmetic: 1e-11 (summation order only), FP32 pair arithmetic: 1e-5.
+Lists and, in FP64, jump events are compared bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import (BOX, DROPLET, FF, event_keys, gpu_sim, oracle_params, rel_err,
+                     relaxed_droplet)
+from workloads import jitter_positions, water_box, water_droplet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def droplet():
+    return relaxed_droplet("c0")
+
+
+@pytest.fixture(scope="module")
+def box():
+    return water_box(n_side=8, box_len=24.8, seed=1)
+
+
+def _sys(droplet, box, which):
+    return (droplet, DROPLET) if which == "drop" else (box, BOX)
+
+
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_rate_bounds_match_oracle(orc, droplet, box, which):
+    sys, cfg = _sys(droplet, box, which)
+    sim = gpu_sim(sys, cfg)
+    lab, la = sim.rate_bounds()
+    olab, ola = orc.rate_bounds(oracle_params(orc, sys, cfg))
+    np.testing.assert_allclose(lab, olab, rtol=1e-12)
+    np.testing.assert_allclose(la, ola, rtol=1e-12)
+
+
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_lists_bit_exact(orc, droplet, box, which):
+    import paper_2002_07109_amd as B
+    sys, cfg = _sys(droplet, box, which)
+    sim = gpu_sim(sys, cfg, fp64=True)
+    sim.jump_halfstep(0, B.PH_JA)       # builds the lists at q_0 (velocities change only)
+    p = oracle_params(orc, sys, cfg)
+    topo = orc.Topology.from_system(sys)
+    order, _ = orc.sort_order(p, sys.pos)
+    for which_list, (rmin, rmax) in [(B.LIST_FORCE, (0.0, cfg["r_off"] + cfg["skin"])),
+                                     (B.LIST_CAND, (cfg["r_on"] - cfg["skin"],
+                                                    cfg["r_cut"] + cfg["skin"]))]:
+        grp, gcol = sim.get_list(which_list)
+        orp, ocol = orc.build_list(p, topo, sys.pos, rmin, rmax, order)
+        assert np.array_equal(grp, orp)
+        assert np.array_equal(gcol, ocol)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_gradients(orc, droplet, box, which, fp64):
+    import paper_2002_07109_amd as B
+    sys, cfg = _sys(droplet, box, which)
+    sim = gpu_sim(sys, cfg, fp64=fp64)
+    q = jitter_positions(sys.pos, 0.05, seed=11)      # bonds and angles off their minima
+    sim.set_state(pos=q)
+    p = oracle_params(orc, sys, cfg)
+    topo = orc.Topology.from_system(sys)
+    tol = 1e-11 if fp64 else 1e-5
+    for gbit, obit in [(B.G_SHORT, orc.G_SHORT), (B.G_LONG, orc.G_LONG), (B.G_FULL, orc.G_FULL),
+                       (B.G_BONDED, orc.G_BONDED), (B.G_BONDED | B.G_SHORT,
+                                                    orc.G_BONDED | orc.G_SHORT)]:
+        g = sim.gradient(gbit).cpu().numpy()
+        o = orc.gradient(p, topo, q, obit)
+        err = rel_err(g, o)
+        assert err < (1e-12 if gbit == B.G_BONDED else tol), (gbit, err)
+
+
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_energies(orc, droplet, box, which):
+    sys, cfg = _sys(droplet, box, which)
+    sim = gpu_sim(sys, cfg, fp64=True)
+    e = sim.energies()[0]
+    o = orc.energies(oracle_params(orc, sys, cfg), orc.Topology.from_system(sys), sys.pos, sys.vel)
+    for k in ("bond", "angle", "coul", "lj", "pair", "kin", "tkin"):
+        assert e[k] == pytest.approx(o[k], rel=1e-11, abs=1e-9), k
+    # FP32 pair energies: ~1e-7 relative per pair; the total cancels pair
+    # energies of either sign, so the bound is taken against the sum of |u_pair|
+    sim32 = gpu_sim(sys, cfg, fp64=False)
+    e32 = sim32.energies()[0]
+    n_pairs = orc.build_list(oracle_params(orc, sys, cfg), orc.Topology.from_system(sys), sys.pos,
+                             0.0, cfg["r_cut"])[0][-1] // 2
+    assert abs(e32["pair"] - o["pair"]) < 1e-7 * 20.0 * n_pairs
+
+
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_jump_halfstep_events_bit_exact(orc, droplet, box, which):
+    import paper_2002_07109_amd as B
+    sys, cfg = _sys(droplet, box, which)
+    cfg = dict(cfg, r_on=4.0, r_off=5.0)           # many proposals
+    sim = gpu_sim(sys, cfg, fp64=True, log_events=True, event_capacity=4_000_000)
+    p = oracle_params(orc, sys, cfg)
+    topo = orc.Topology.from_system(sys)
+    order, _ = orc.sort_order(p, sys.pos)
+    rp, col = orc.build_list(p, topo, sys.pos, cfg["r_on"] - cfg["skin"],
+                             cfg["r_cut"] + cfg["skin"], order)
+    v = sys.vel.copy()
+    all_o = []
+    for step, phase in [(0, B.PH_JA), (0, B.PH_JB), (7, B.PH_JA)]:
+        sim.jump_halfstep(step, phase)
+        out = orc.jump_halfstep(p, topo, sys.pos, v, rp, col, step, phase, ev_cap=4_000_000)
+        assert out["status"] == 0
+        v = out["v"]
+        all_o.append(out["events"])
+        np.testing.assert_allclose(sim.vel.cpu().numpy(), v, rtol=0, atol=1e-14)
+    ev, n = sim.events()
+    o = np.concatenate(all_o)
+    assert n == o.size and n > 1000
+    assert np.array_equal(event_keys(ev), event_keys(o))
+    assert sim.counters()["accepted"] == int(o["accepted"].sum())
+
+
+def _traj(orc, sys, cfg, nsteps, fp64, use_graph=False):
+    sim = gpu_sim(sys, cfg, fp64=fp64, log_events=True, event_capacity=4_000_000,
+                  use_graph=use_graph)
+    sim.step(nsteps)
+    sim.sync()
+    p = oracle_params(orc, sys, cfg)
+    o = orc.run(p, orc.Topology.from_system(sys), sys.pos, sys.vel, 0, nsteps, ev_cap=4_000_000)
+    assert o["status"] == 0, o["status_name"]
+    return sim, o
+
+
+@pytest.mark.parametrize("which,nsteps", [("drop", 200), ("box", 100)])
+def test_trajectory_fp64(orc, droplet, box, which, nsteps):
+    sys, cfg = _sys(droplet, box, which)
+    sim, o = _traj(orc, sys, cfg, nsteps, fp64=True)
+    dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
+    dv = np.abs(sim.vel.cpu().numpy() - o["v"]).max()
+    assert dq <= 1e-6, dq
+    assert dv <= 1e-6, dv
+    ev, n = sim.events()
+    assert n == o["n_events"]
+    assert np.array_equal(event_keys(ev), event_keys(o["events"]))
+    c = sim.counters()
+    assert c["proposals"] == o["counters"]["proposals"]
+    assert c["accepted"] == o["counters"]["accepted"]
+    assert c["bound_violations"] == 0
+
+
+def test_trajectory_baoab_fp64(orc, droplet):
+    cfg = dict(DROPLET, integrator=1, dt=1.0)
+    sim, o = _traj(orc, droplet, cfg, 100, fp64=True)
+    assert np.abs(sim.pos.cpu().numpy() - o["q"]).max() <= 1e-6
+
+
+def test_trajectory_fp32_divergence(orc, droplet):
+    """FP32 pair arithmetic: positions after 100 steps stay close to the FP64
+    oracle; any differing event is explained by a near-tie of the accept test."""
+    sim, o = _traj(orc, droplet, DROPLET, 100, fp64=False)
+    dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
+    assert dq < 1e-2, dq
+    ev, n = sim.events()
+    a, b = event_keys(ev[ev["step"] < 20]), event_keys(o["events"][o["events"]["step"] < 20])
+    same = a.shape == b.shape and np.array_equal(a, b)
+    print(f"FP32 vs FP64 oracle after 100 steps: max |dq| = {dq:.3e} A; "
+          f"events {n} vs {o['n_events']}; first 20 steps identical: {same}")
+
+
+def test_graph_replay_equals_direct_launches(orc, box):
+    sa = gpu_sim(box, BOX, fp64=False, use_graph=False)
+    sb = gpu_sim(box, BOX, fp64=False, use_graph=True)
+    for sim in (sa, sb):
+        sim.step(35)
+        sim.sync()
+    assert np.array_equal(sa.pos.cpu().numpy(), sb.pos.cpu().numpy())
+    assert np.array_equal(sa.vel.cpu().numpy(), sb.vel.cpu().numpy())
+
+
+def test_deterministic_and_resumable(box):
+    a = gpu_sim(box, BOX)
+    a.step(40)
+    a.sync()
+    b = gpu_sim(box, BOX)
+    b.step(20)
+    b.sync()
+    b.step(20)
+    b.sync()
+    assert np.array_equal(a.pos.cpu().numpy(), b.pos.cpu().numpy())
+    assert np.array_equal(a.vel.cpu().numpy(), b.vel.cpu().numpy())
+
+
+def test_replicas_match_independent_oracle_runs(orc):
+    systems = [relaxed_droplet(name) for name in ("r0", "r1", "r2")]
+    sim = gpu_sim(systems, DROPLET, fp64=True, log_events=True, event_capacity=2_000_000)
+    sim.step(30)
+    sim.sync()
+    pos = sim.pos.cpu().numpy()
+    for r, s in enumerate(systems):
+        o = orc.run(oracle_params(orc, s, DROPLET, replica=r), orc.Topology.from_system(s),
+                    s.pos, s.vel, 0, 30)
+        assert o["status"] == 0
+        b, e = sim.offsets[r], sim.offsets[r + 1]
+        assert np.abs(pos[b:e] - o["q"]).max() <= 1e-6
+        assert sim.counters(r)["proposals"] == o["counters"]["proposals"]
+
+
+def test_device_conditions_are_reported(droplet):
+    import paper_2002_07109_amd as B
+    sim = gpu_sim(droplet, dict(DROPLET, skin=0.02, rebuild_interval=1000, dt=1.0))
+    sim.step(60)
+    with pytest.raises(B.BounceError) as e:
+        sim.sync()
+    assert e.value.status == -4
