@@ -57,6 +57,9 @@ def run_gpu(args, system, ff, integrator, state):
     sim.set_state(pos=state[0], vel=state[1], step=0)
     sim.step(args.warmup)
     sim.sync()
+    lanes, tune = sim.autotune(reps=20)
+    sim.step(10)
+    sim.sync()
     c0 = sim.counters()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -76,6 +79,7 @@ def run_gpu(args, system, ff, integrator, state):
                proposals_per_step=(c1["proposals"] - c0["proposals"]) / args.steps,
                accepted_per_step=(c1["accepted"] - c0["accepted"]) / args.steps,
                pair_kernel_ms=pair_ms, build_ms=build_ms, t_kin=e["tkin"],
+               lanes=lanes, tune_ms={k: round(v, 5) for k, v in tune.items()},
                e_pot=e["pair"] + e["bond"] + e["angle"],
                pos=sim.pos.cpu().numpy())
     sim.close()
@@ -193,6 +197,7 @@ def main():
                    "accepted_per_step": bo["accepted_per_step"],
                    "pair_kernel_us": round(bo["pair_kernel_ms"] * 1e3, 3),
                    "list_build_us": round(bo["build_ms"] * 1e3, 3),
+                   "pair_lanes": bo["lanes"], "autotune_ms": bo["tune_ms"],
                    "t_kin_K": round(bo["t_kin"], 2), "e_pot": round(bo["e_pot"], 2)},
         "baoab": {"ns_per_day": round(ns_day(ba["ms_per_step"]), 3),
                   "ms_per_step": round(ba["ms_per_step"], 5),
@@ -201,6 +206,7 @@ def main():
                   "pair_kernel_us": round(ba["pair_kernel_ms"] * 1e3, 3),
                   "list_build_us": round(ba["build_ms"] * 1e3, 3),
                   "pair_kernel_tflops": round(achieved_ba, 3),
+                  "pair_lanes": ba["lanes"], "autotune_ms": ba["tune_ms"],
                   "t_kin_K": round(ba["t_kin"], 2), "e_pot": round(ba["e_pot"], 2)},
         "speedup_vs_baoab": round(ba["ms_per_step"] / bo["ms_per_step"], 4),
         "roofline": {"kernel": "F_0 pair kernel (BOUNCE short range)", "bound": "alu",

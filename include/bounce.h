@@ -84,6 +84,8 @@ typedef struct {
     double cell_size;          /* target cell edge of the list grid (Angstrom)             */
     uint64_t seed;             /* Philox key word 0                                        */
     int64_t event_capacity;    /* events kept when log_events = 1                          */
+    int32_t pair_lanes;        /* lanes per atom in the pair kernel: 4, 8, 16, 32 (0 = 8)  */
+    int32_t reserved;
 } bounce_params;
 
 typedef struct {
@@ -186,6 +188,12 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
    HIP events on the bound stream and return the mean duration in ms.  Leaves
    the trajectory unchanged.  Synchronous. */
 bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);
+
+/* Autotuner: time the F_0 pair kernel (reps launches each) with 4, 8, 16 and 32
+   lanes per atom at the current positions, keep the fastest in the context and
+   return it in *lanes_out; ms_out (NULL or [4]) receives the mean times.
+   Synchronous; leaves the trajectory unchanged. */
+bounce_status bounce_autotune(bounce_ctx *ctx, int32_t reps, int32_t *lanes_out, double *ms_out);
 
 const char *bounce_status_string(int32_t status);
 const char *bounce_last_error(const bounce_ctx *ctx);

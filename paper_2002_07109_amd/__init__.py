@@ -33,7 +33,8 @@ def make_params(**kw) -> bounce_params:
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
-             ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0)
+             ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
+             pair_lanes=0)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():
@@ -221,6 +222,14 @@ class Simulation:
         check(self.L.bounce_profile_kernel(self.ctx, int(which), int(reps), C.byref(ms)), self.ctx,
               "bounce_profile_kernel")
         return ms.value
+
+    def autotune(self, reps=20):
+        """Pick the pair kernel's lanes per atom by timing; returns (lanes, {lanes: ms})."""
+        lanes = C.c_int32()
+        ms = np.zeros(4)
+        check(self.L.bounce_autotune(self.ctx, int(reps), C.byref(lanes), _ptr(ms)), self.ctx,
+              "bounce_autotune")
+        return lanes.value, dict(zip((4, 8, 16, 32), ms.tolist()))
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -29,7 +29,8 @@ class bounce_params(C.Structure):
                 ("dt", C.c_double), ("gamma", C.c_double), ("temperature", C.c_double),
                 ("r_on", C.c_double), ("r_off", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("ewald_alpha", C.c_double), ("bound_scale", C.c_double),
-                ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64)]
+                ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64),
+                ("pair_lanes", C.c_int32), ("reserved", C.c_int32)]
 
 
 class bounce_system(C.Structure):
@@ -79,6 +80,7 @@ SIGNATURES = {
     "bounce_direct_energy": (i32, [ctx_p, vp, vp, vp]),
     "bounce_direct_energy_bwd": (i32, [ctx_p, vp, vp, vp, vp, vp]),
     "bounce_profile_kernel": (i32, [ctx_p, i32, i32, _P(C.c_double)]),
+    "bounce_autotune": (i32, [ctx_p, i32, _P(i32), vp]),
     "bounce_status_string": (C.c_char_p, [i32]),
     "bounce_last_error": (C.c_char_p, [ctx_p]),
 }

@@ -158,8 +158,12 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->integrator == BOUNCE_BJAOAJB && !(p->r_on > 0 && p->r_off > p->r_on)) return BOUNCE_E_ARG;
     if (p->rebuild_interval < 1 || p->max_proposals < 1) return BOUNCE_E_ARG;
     if (!(p->bound_scale > 0)) return BOUNCE_E_ARG;
+    if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
+        p->pair_lanes != 32)
+        return BOUNCE_E_ARG;
     bounce_ctx *c = new bounce_ctx();
     c->p = *p;
+    if (c->p.pair_lanes == 0) c->p.pair_lanes = 8;
     *out = c;
     return BOUNCE_OK;
 }
@@ -647,7 +651,7 @@ static void enqueue_force(bounce_ctx *c)
     a.out_global = 0;
     a.accumulate = 0;
     launch_pair(c->stream, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
-                c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+                c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
 }
 
 static StepArgs step_args(bounce_ctx *c, int close, int open)
@@ -804,7 +808,7 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
         a.out = grad;
         a.out_global = 1;
         a.accumulate = !first;
-        launch_pair(sm, modes[k], c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+        launch_pair(sm, modes[k], c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
         first = 0;
     }
     if (which & BOUNCE_G_BONDED) {
@@ -826,7 +830,7 @@ bounce_status bounce_compute_energies(bounce_ctx *c, double *out)
     a.energy_total = 0;
     a.atom_stride = 5;
     a.atom_col = 2;
-    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
     launch_atom_energy(sm, c->n, c->pos, c->vel, c->d_reps, c->tp, c->d_atom);
     launch_segment_sum(sm, c->R, c->d_rep_off, c->d_atom, 5, 5, 0, c->d_seg);
     std::vector<double> seg(5 * c->R);
@@ -939,7 +943,7 @@ bounce_status bounce_direct_energy(bounce_ctx *c, const double *pos, const doubl
     a.type_params = params;
     a.atom_out = c->d_atom;
     a.energy_total = 1;
-    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
     launch_segment_sum(sm, 1, c->d_one_seg, c->d_atom, 1, 1, 0, energy);
     HIPCHK(c, hipGetLastError());
     return BOUNCE_OK;
@@ -960,7 +964,7 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *c, const double *pos, const d
     a.out_global = 1;
     a.accumulate = 0;
     a.atom_out = c->d_atom;
-    launch_pair(sm, MODE_DBWD, c->p.pair_precision == BOUNCE_PAIR_FP64, a);
+    launch_pair(sm, MODE_DBWD, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
     launch_dbwd_finish(sm, c->n, c->nt, c->d_atom, c->tp.type, params, grad_out, grad_pos,
                        grad_params, nullptr);
     HIPCHK(c, hipGetLastError());
@@ -993,4 +997,32 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / reps;
     return bounce_sync(c);
+}
+
+bounce_status bounce_autotune(bounce_ctx *c, int32_t reps, int32_t *lanes_out, double *ms_out)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (reps < 1) return BOUNCE_E_ARG;
+    const int32_t cand[4] = {4, 8, 16, 32};
+    int32_t best = c->p.pair_lanes;
+    double best_ms = 1e300;
+    for (int k = 0; k < 4; ++k) {
+        c->p.pair_lanes = cand[k];
+        double ms = 0.0;
+        s = bounce_profile_kernel(c, 0, 2, &ms);   // warm the instantiation
+        if (s) return s;
+        s = bounce_profile_kernel(c, 0, reps, &ms);
+        if (s) return s;
+        if (ms_out) ms_out[k] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[k];
+        }
+    }
+    c->p.pair_lanes = best;
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if (lanes_out) *lanes_out = best;
+    return BOUNCE_OK;
 }

@@ -38,45 +38,51 @@ __device__ __forceinline__ void disp_of(const RepInfo &ri, const PosF &pf, int32
     d[0] = dx; d[1] = dy; d[2] = dz;
 }
 
+// gradient on atom g of one bonded term (code = kind << 28 | index)
+template <class PosF>
+__device__ __forceinline__ void bonded_term_grad(int32_t g, int32_t code, const PosF &pf,
+                                                 const RepInfo &ri, const Topo &tp, double out[3])
+{
+    const int32_t kind = code >> 28, idx = code & 0x0fffffff;
+    if (kind == 0) {
+        const int32_t a0 = tp.bond_ij[2 * idx], a1 = tp.bond_ij[2 * idx + 1];
+        double d[3];
+        disp_of(ri, pf, a0, a1, d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double c = 2.0 * tp.bond_kr[2 * idx] * (r - tp.bond_kr[2 * idx + 1]) / r;
+        const double sg = (g == a0) ? c : -c;
+        out[0] += sg * d[0]; out[1] += sg * d[1]; out[2] += sg * d[2];
+    } else {
+        const int32_t x = tp.angle_ijk[3 * idx], v = tp.angle_ijk[3 * idx + 1],
+                      y = tp.angle_ijk[3 * idx + 2];
+        double e1[3], e2[3];
+        disp_of(ri, pf, x, v, e1);
+        disp_of(ri, pf, y, v, e2);
+        const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        const double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        const double il = 1.0 / (l1 * l2);
+        double cs = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) * il;
+        cs = fmin(1.0, fmax(-1.0, cs));
+        const double th = acos(cs);
+        const double sn = sqrt(1.0 - cs * cs);
+        // dE/dtheta * dtheta/dcos, with dtheta/dcos = -1/sin
+        const double w = -2.0 * tp.angle_kt[2 * idx] * (th - tp.angle_kt[2 * idx + 1]) / sn;
+        for (int c = 0; c < 3; ++c) {
+            const double gx = w * (e2[c] * il - cs * e1[c] / (l1 * l1));
+            const double gy = w * (e1[c] * il - cs * e2[c] / (l2 * l2));
+            if (g == x) out[c] += gx;
+            if (g == y) out[c] += gy;
+            if (g == v) out[c] -= gx + gy;
+        }
+    }
+}
+
 template <class PosF>
 __device__ void bonded_grad_atom(int32_t g, const PosF &pf, const RepInfo &ri, const Topo &tp,
                                  double out[3])
 {
-    for (int32_t k = tp.bt_ptr[g]; k < tp.bt_ptr[g + 1]; ++k) {
-        const int32_t code = tp.bt[k];
-        const int32_t kind = code >> 28, idx = code & 0x0fffffff;
-        if (kind == 0) {
-            const int32_t a0 = tp.bond_ij[2 * idx], a1 = tp.bond_ij[2 * idx + 1];
-            double d[3];
-            disp_of(ri, pf, a0, a1, d);
-            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            const double c = 2.0 * tp.bond_kr[2 * idx] * (r - tp.bond_kr[2 * idx + 1]) / r;
-            const double sg = (g == a0) ? c : -c;
-            out[0] += sg * d[0]; out[1] += sg * d[1]; out[2] += sg * d[2];
-        } else {
-            const int32_t x = tp.angle_ijk[3 * idx], v = tp.angle_ijk[3 * idx + 1],
-                          y = tp.angle_ijk[3 * idx + 2];
-            double e1[3], e2[3];
-            disp_of(ri, pf, x, v, e1);
-            disp_of(ri, pf, y, v, e2);
-            const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
-            const double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
-            const double il = 1.0 / (l1 * l2);
-            double cs = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) * il;
-            cs = fmin(1.0, fmax(-1.0, cs));
-            const double th = acos(cs);
-            const double sn = sqrt(1.0 - cs * cs);
-            // dE/dtheta * dtheta/dcos, with dtheta/dcos = -1/sin
-            const double w = -2.0 * tp.angle_kt[2 * idx] * (th - tp.angle_kt[2 * idx + 1]) / sn;
-            for (int c = 0; c < 3; ++c) {
-                const double gx = w * (e2[c] * il - cs * e1[c] / (l1 * l1));
-                const double gy = w * (e1[c] * il - cs * e2[c] / (l2 * l2));
-                if (g == x) out[c] += gx;
-                if (g == y) out[c] += gy;
-                if (g == v) out[c] -= gx + gy;
-            }
-        }
-    }
+    for (int32_t k = tp.bt_ptr[g]; k < tp.bt_ptr[g + 1]; ++k)
+        bonded_term_grad(g, tp.bt[k], pf, ri, tp, out);
 }
 
 }  // namespace bnc

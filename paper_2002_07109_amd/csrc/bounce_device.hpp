@@ -108,15 +108,33 @@ struct PairGlobals {
 template <typename R>
 __device__ __forceinline__ void coul_g(R r, R rinv, R alpha, int coulomb, R &g, R &dg);
 
+// FP32: erfc(x) from the Chebyshev-fitted form of Press et al., Numerical
+// Recipes (2nd ed., sec. 6.2, "erfcc"): erfc(x) = t exp(-x^2 + P(t)), t = 1/(1 + x/2),
+// relative error below 1.2e-7 for x >= 0; exp(-x^2) is shared with g'(r).
+__device__ __forceinline__ float erfc_nr(float x, float e)
+{
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    return t * e * __expf(p);
+}
+
 template <>
 __device__ __forceinline__ void coul_g<float>(float r, float rinv, float alpha, int coulomb,
                                               float &g, float &dg)
 {
     if (coulomb) {
-        float ar = alpha * r;
-        float e = erfcf(ar);
-        float ex = __expf(-ar * ar);
-        g = e * rinv;
+        const float ar = alpha * r;
+        const float ex = __expf(-ar * ar);
+        g = erfc_nr(ar, ex) * rinv;
         dg = -(g + (float)TWO_OVER_SQRTPI * alpha * ex) * rinv;
     } else {
         g = rinv;
@@ -143,7 +161,7 @@ __device__ __forceinline__ void coul_g<double>(double r, double rinv, double alp
 template <typename R>
 __device__ __forceinline__ R rsqrt_(R x);
 template <>
-__device__ __forceinline__ float rsqrt_<float>(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <>
 __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
 
@@ -174,6 +192,13 @@ __device__ __forceinline__ R switch_chi(R r, R r_on, R inv_w)
     return x * x * x * ((R)10 + x * ((R)6 * x - (R)15));
 }
 
+// The sorted position mirror stores (x, y, z, w) with w = 16 id + type, an
+// integer exactly representable in FP64, so one 32-byte load gives a partner's
+// position, type and caller id.
+__device__ __forceinline__ double mirror_w(int32_t id, int32_t type) { return (double)(id * 16 + type); }
+__device__ __forceinline__ int32_t mirror_type(double w) { return (int32_t)w & 15; }
+__device__ __forceinline__ int32_t mirror_id(double w) { return (int32_t)w >> 4; }
+
 // minimum-image displacement in FP64.  The list-build translation unit is
 // compiled without FMA contraction, so there these expressions round exactly
 // where written (the list predicate must be reproducible bit for bit).
@@ -185,6 +210,25 @@ __device__ __forceinline__ void min_image(const RepInfo &ri, double &dx, double 
         dz = dz - ri.box[2] * rint(dz * ri.inv_box[2]);
     }
 }
+
+// the periodic box of one replica, held in registers by the pair loops
+struct BoxReg {
+    double L[3], iL[3];
+    int periodic;
+    __device__ __forceinline__ explicit BoxReg(const RepInfo &ri)
+    {
+        periodic = ri.periodic;
+        for (int k = 0; k < 3; ++k) { L[k] = ri.box[k]; iL[k] = ri.inv_box[k]; }
+    }
+    __device__ __forceinline__ void apply(double &dx, double &dy, double &dz) const
+    {
+        if (periodic) {
+            dx = dx - L[0] * rint(dx * iL[0]);
+            dy = dy - L[1] * rint(dy * iL[1]);
+            dz = dz - L[2] * rint(dz * iL[2]);
+        }
+    }
+};
 
 __device__ __forceinline__ double norm2_exact(double dx, double dy, double dz)
 {

@@ -61,7 +61,7 @@ struct JumpArgs {
 void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
                   const int32_t *cell_rep, const Topo &tp, const ListSet &ls, const BuildSpec &bs,
                   DevState *st);
-void launch_pair(hipStream_t sm, int mode, int fp64, const PairArgs &a);
+void launch_pair(hipStream_t sm, int mode, int fp64, int lanes, const PairArgs &a);
 void launch_bonded_grad(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
                         const Topo &tp, double *out);
 void launch_atom_energy(hipStream_t sm, int32_t n, const double *pos, const double *vel,

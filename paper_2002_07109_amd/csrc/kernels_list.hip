@@ -84,26 +84,46 @@ __global__ void k_scatter(int32_t n, ListSet ls)
     ls.perm[ls.cell_start[ls.cell_of[g]] + ls.slot[g]] = g;
 }
 
-// one thread per cell: order the cell's atoms by caller id, fill the mirror
-__global__ void k_cellsort(int32_t n_cells, const double *__restrict__ pos, Topo tp, ListSet ls,
-                           const DevState *st, int32_t mirror_sel)
+__device__ __forceinline__ void wave_sync()
 {
-    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    int32_t b = ls.cell_start[c], e = ls.cell_start[c + 1];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per cell: order the cell's atoms by caller id (rank sort over
+// the lanes; a serial insertion sort above 64 atoms) and fill the mirror.
+__global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double *__restrict__ pos,
+                                                  Topo tp, ListSet ls, const DevState *st,
+                                                  int32_t mirror_sel)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= n_cells) return;                       // uniform per wavefront
+    const int32_t b = ls.cell_start[c], e = ls.cell_start[c + 1], m = e - b;
     int32_t *p = ls.perm;
-    for (int32_t i = b + 1; i < e; ++i) {
-        int32_t v = p[i], j = i - 1;
-        while (j >= b && p[j] > v) { p[j + 1] = p[j]; --j; }
-        p[j + 1] = v;
+    if (m <= 64) {
+        const int32_t mine = lane < m ? p[b + lane] : 0x7fffffff;
+        int32_t rank = 0;
+        for (int32_t k = 0; k < m; ++k) rank += __shfl(mine, k, 64) < mine;
+        wave_sync();
+        if (lane < m) p[b + rank] = mine;
+    } else if (lane == 0) {
+        for (int32_t i = b + 1; i < e; ++i) {
+            int32_t v = p[i], j = i - 1;
+            while (j >= b && p[j] > v) { p[j + 1] = p[j]; --j; }
+            p[j + 1] = v;
+        }
     }
-    int32_t par = mirror_sel >= 0 ? mirror_sel : (int32_t)(st->step & 1);
+    __threadfence_block();
+    wave_sync();
+    const int32_t par = mirror_sel >= 0 ? mirror_sel : (int32_t)(st->step & 1);
     double4 *X = ls.x[par];
-    for (int32_t i = b; i < e; ++i) {
-        int32_t g = p[i];
+    for (int32_t i = b + lane; i < e; i += 64) {
+        const int32_t g = p[i];
         ls.inv_perm[g] = i;
         const double *x = pos + 3 * (int64_t)g;
-        X[i] = make_double4(x[0], x[1], x[2], (double)tp.type[g]);
+        X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
     }
 }
 
@@ -116,98 +136,208 @@ __device__ __forceinline__ double cell_gap(int32_t ci, int32_t cj, int32_t n, do
     return d > 1 ? (double)(d - 1) * w : 0.0;
 }
 
-// One wavefront per cell: lanes (a, b) = (lane / 8, lane % 8) test i = i0 + a
-// of the cell against j = j0 + b of each candidate cell.  Candidate cells are
-// visited in ascending cell index and atoms inside a cell in ascending id, and
-// the hits of each i are appended in lane order through a ballot, so every row
-// comes out in canonical order without a sort.
+constexpr int LW = 4;          // wavefronts (cells) per workgroup
+constexpr int LCAP = 1024;     // candidate atoms gathered per batch
+constexpr int LMAXI = 64;      // atoms per cell handled
+constexpr int LDIM = 12;       // candidate cells per dimension
+constexpr int LCELLS = 320;     // candidate cells kept per cell
+constexpr int LEXCL = 8;       // exclusions per atom held in registers
+
+// One wavefront per cell.  (1) The candidate cells (cell gap below the search
+// radius) are enumerated by the lanes in ascending cell index, their atom
+// ranges fetched in parallel and compacted by ballots.  (2) Their atoms are
+// gathered, in ascending cell and id order, into a flat LDS batch.  (3) For
+// each atom i of the cell the 64 lanes test 64 consecutive candidates at a
+// time and a ballot appends the hits in candidate order, so every row comes
+// out in canonical order.
 __global__ void __launch_bounds__(256) k_lists(int32_t n_cells, const RepInfo *__restrict__ reps,
                                                const int32_t *__restrict__ cell_rep, Topo tp,
                                                ListSet ls, BuildSpec bs, DevState *st)
 {
-    const int lane = threadIdx.x & 63;
-    const int32_t ci = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    __shared__ int32_t cand[LW][LCAP];
+    __shared__ int32_t rowf[LW][LMAXI], rowc[LW][LMAXI];
+    __shared__ int32_t dcell[LW][3][LDIM];
+    __shared__ double dgap[LW][3][LDIM];
+    __shared__ int32_t cbeg[LW][LCELLS], cnum[LW][LCELLS], cpre[LW][LCELLS + 1];
+    __shared__ double4 ipos[LW][LMAXI];
+    __shared__ int32_t iex[LW][LMAXI][LEXCL], iexn[LW][LMAXI];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t ci = blockIdx.x * LW + w;
     if (ci >= n_cells) return;                       // uniform per wavefront
-    const int32_t bi = ls.cell_start[ci], ei = ls.cell_start[ci + 1];
+    const int32_t bi = ls.cell_start[ci], ei_all = ls.cell_start[ci + 1];
+    const int32_t ei = min(ei_all, bi + LMAXI);
+    bool overflow = ei_all > ei;
+    for (int32_t i = ei + lane; i < ei_all; i += 64) {   // atoms beyond the per-cell limit
+        ls.fcnt[i] = 0;
+        ls.ccnt[i] = 0;
+    }
     if (bi == ei) return;                            // uniform per wavefront
     const RepInfo &ri = reps[cell_rep[ci]];
     const int32_t par = bs.mirror_sel >= 0 ? bs.mirror_sel : (int32_t)(st->step & 1);
     const double4 *__restrict__ X = ls.x[par];
-    const int32_t nx = ri.ncell[0], ny = ri.ncell[1], nz = ri.ncell[2];
     const int32_t loc = ci - ri.cell_off;
-    const int32_t cx = loc / (ny * nz), cy = (loc / nz) % ny, cz = loc % nz;
+    const int32_t cc[3] = {loc / (ri.ncell[1] * ri.ncell[2]), (loc / ri.ncell[2]) % ri.ncell[1],
+                           loc % ri.ncell[2]};
     const double R = bs.rsearch * (1.0 + 1e-12) + 1e-9;
     const double R2 = R * R;
     const double rmax2 = fmax(bs.want_force ? bs.rf2 : 0.0, bs.want_cand ? bs.rcmax2 : 0.0);
-    const int a = lane >> 3, b = lane & 7;
-    const uint32_t below = (1u << b) - 1u;
-    bool overflow = false;
-    for (int32_t i0 = bi; i0 < ei; i0 += 8) {
-        const int32_t i = i0 + a;
-        const bool ivalid = i < ei;
-        double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-        int32_t gi = -1, e_b = 0, e_e = 0;
-        if (ivalid) {
-            xi = X[i];
-            gi = ls.perm[i];
-            e_b = tp.excl_ptr[gi];
-            e_e = tp.excl_ptr[gi + 1];
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int32_t k = lane; k < ei - bi; k += 64) rowf[w][k] = rowc[w][k] = 0;
+    // (1a) candidate cell indices per dimension, ascending
+    int32_t nd[3];
+    for (int d = 0; d < 3; ++d) {
+        int32_t cnt = 0;
+        for (int32_t j0 = 0; j0 < ri.ncell[d]; j0 += 64) {
+            const int32_t j = j0 + lane;
+            double gp = 0.0;
+            bool ok = false;
+            if (j < ri.ncell[d]) {
+                gp = cell_gap(cc[d], j, ri.ncell[d], ri.cw[d], ri.periodic);
+                ok = gp < R;
+            }
+            const uint64_t m = __ballot(ok);
+            const int32_t k = cnt + __popcll(m & below);
+            if (ok && k < LDIM) {
+                dcell[w][d][k] = j;
+                dgap[w][d][k] = gp * gp;
+            }
+            cnt += __popcll(m);
         }
-        int32_t nf = 0, ncand = 0;
-        int32_t *frow = ls.flist + (int64_t)(ivalid ? i : 0) * ls.fcap;
-        int32_t *crow = ls.clist + (int64_t)(ivalid ? i : 0) * ls.ccap;
-        for (int32_t jx = 0; jx < nx; ++jx) {
-            const double gx = cell_gap(cx, jx, nx, ri.cw[0], ri.periodic);
-            if (gx >= R) continue;
-            for (int32_t jy = 0; jy < ny; ++jy) {
-                const double gy = cell_gap(cy, jy, ny, ri.cw[1], ri.periodic);
-                const double gxy = gx * gx + gy * gy;
-                if (gxy >= R2) continue;
-                for (int32_t jz = 0; jz < nz; ++jz) {
-                    const double gz = cell_gap(cz, jz, nz, ri.cw[2], ri.periodic);
-                    if (gxy + gz * gz >= R2) continue;
-                    const int32_t cj = ri.cell_off + (jx * ny + jy) * nz + jz;
-                    const int32_t bj = ls.cell_start[cj], ej = ls.cell_start[cj + 1];
-                    for (int32_t j0 = bj; j0 < ej; j0 += 8) {
-                        const int32_t j = j0 + b;
-                        bool f = false, c = false;
-                        if (ivalid && j < ej && j != i) {
-                            const double4 xj = X[j];
-                            double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                            min_image(ri, dx, dy, dz);
-                            const double r2 = norm2_exact(dx, dy, dz);
-                            if (r2 < rmax2) {
-                                const int32_t gj = ls.perm[j];
-                                bool ex = false;
-                                for (int32_t k = e_b; k < e_e; ++k) ex |= (tp.excl_idx[k] == gj);
-                                if (!ex) {
-                                    f = bs.want_force && r2 < bs.rf2;
-                                    c = bs.want_cand && r2 < bs.rcmax2 &&
-                                        !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
-                                }
-                            }
-                        }
-                        const uint32_t mf = (uint32_t)(__ballot(f) >> (8 * a)) & 0xffu;
-                        const uint32_t mc = (uint32_t)(__ballot(c) >> (8 * a)) & 0xffu;
-                        if (f) {
-                            const int32_t k = nf + __popc(mf & below);
-                            if (k < ls.fcap) frow[k] = j;
-                        }
-                        if (c) {
-                            const int32_t k = ncand + __popc(mc & below);
-                            if (k < ls.ccap) crow[k] = j;
-                        }
-                        nf += __popc(mf);
-                        ncand += __popc(mc);
-                    }
-                }
+        if (cnt > LDIM) overflow = true;
+        nd[d] = min(cnt, LDIM);
+    }
+    wave_sync();
+    // (1b) candidate cells in ascending index with their atom ranges
+    const int32_t ntrip = nd[0] * nd[1] * nd[2];
+    int32_t ncells = 0;
+    for (int32_t t0 = 0; t0 < ntrip; t0 += 64) {
+        const int32_t t = t0 + lane;
+        bool ok = false;
+        int32_t jb = 0, jn = 0;
+        if (t < ntrip) {
+            const int32_t a = t / (nd[1] * nd[2]), b = (t / nd[2]) % nd[1], c = t % nd[2];
+            if (dgap[w][0][a] + dgap[w][1][b] + dgap[w][2][c] < R2) {
+                const int32_t cj = ri.cell_off +
+                                   (dcell[w][0][a] * ri.ncell[1] + dcell[w][1][b]) * ri.ncell[2] +
+                                   dcell[w][2][c];
+                jb = ls.cell_start[cj];
+                jn = ls.cell_start[cj + 1] - jb;
+                ok = jn > 0;
             }
         }
-        if (ivalid && b == 0) {
-            if (bs.want_force) ls.fcnt[i] = min(nf, ls.fcap);
-            if (bs.want_cand) ls.ccnt[i] = min(ncand, ls.ccap);
+        const uint64_t m = __ballot(ok);
+        const int32_t k = ncells + __popcll(m & below);
+        if (ok && k < LCELLS) {
+            cbeg[w][k] = jb;
+            cnum[w][k] = jn;
         }
-        overflow |= ivalid && (nf > ls.fcap || ncand > ls.ccap);
+        ncells += __popcll(m);
+    }
+    if (ncells > LCELLS) overflow = true;
+    ncells = min(ncells, LCELLS);
+    wave_sync();
+    // prefix sum of the cell sizes (fixed order, wave scan in chunks of 64)
+    int32_t run = 0;
+    for (int32_t k0 = 0; k0 < ncells; k0 += 64) {
+        const int32_t k = k0 + lane;
+        const int32_t v = k < ncells ? cnum[w][k] : 0;
+        int32_t incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (k < ncells) cpre[w][k] = run + incl - v;
+        run += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) cpre[w][ncells] = run;
+    // the cell's own atoms: positions, ids and exclusions, loaded once
+    for (int32_t k = lane; k < ei - bi; k += 64) {
+        const double4 x = X[bi + k];
+        ipos[w][k] = x;
+        const int32_t g = mirror_id(x.w);
+        const int32_t e_b = tp.excl_ptr[g], e_n = tp.excl_ptr[g + 1] - e_b;
+        iexn[w][k] = min(e_n, LEXCL);
+        for (int32_t t = 0; t < LEXCL; ++t) iex[w][k][t] = t < e_n ? tp.excl_idx[e_b + t] : -1;
+        if (e_n > LEXCL) overflow = true;
+    }
+    wave_sync();
+    const int32_t total = cpre[w][ncells];
+
+    for (int32_t lo = 0; lo < total; lo += LCAP) {
+        const int32_t nb = min(LCAP, total - lo);
+        // (2) gather candidates [lo, lo + nb) of the flat sequence
+        for (int32_t k = lane; k < ncells; k += 64) {
+            const int32_t p0 = cpre[w][k], jb = cbeg[w][k], jn = cnum[w][k];
+            const int32_t t_lo = max(0, lo - p0), t_hi = min(jn, lo + nb - p0);
+            for (int32_t t = t_lo; t < t_hi; ++t) cand[w][p0 + t - lo] = jb + t;
+        }
+        wave_sync();
+        // (3) test every atom of this cell against the batch
+        for (int32_t i = bi; i < ei; ++i) {
+            const double4 xi = ipos[w][i - bi];
+            int32_t ex_id[LEXCL];
+#pragma unroll
+            for (int k = 0; k < LEXCL; ++k) ex_id[k] = iex[w][i - bi][k];
+            int32_t nf = rowf[w][i - bi], nc = rowc[w][i - bi];
+            int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
+            int32_t *crow = ls.clist + (int64_t)i * ls.ccap;
+            constexpr int UF = 2;
+            for (int32_t f0 = 0; f0 < nb; f0 += 64 * UF) {
+                int32_t jj[UF];
+                double4 xj[UF];
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    const int32_t f = f0 + 64 * u + lane;
+                    jj[u] = f < nb ? cand[w][f] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < UF; ++u) xj[u] = X[jj[u] >= 0 ? jj[u] : i];
+#pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    bool hf = false, hc = false;
+                    const int32_t j = jj[u];
+                    if (j >= 0 && j != i) {
+                        double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
+                        min_image(ri, dx, dy, dz);
+                        const double r2 = norm2_exact(dx, dy, dz);
+                        if (r2 < rmax2) {
+                            const int32_t gj = mirror_id(xj[u].w);
+                            bool ex = false;
+#pragma unroll
+                            for (int k = 0; k < LEXCL; ++k) ex |= ex_id[k] == gj;
+                            if (!ex) {
+                                hf = bs.want_force && r2 < bs.rf2;
+                                hc = bs.want_cand && r2 < bs.rcmax2 &&
+                                     !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
+                            }
+                        }
+                    }
+                    const uint64_t mf = __ballot(hf), mc = __ballot(hc);
+                    if (hf) {
+                        const int32_t k = nf + __popcll(mf & below);
+                        if (k < ls.fcap) frow[k] = j;
+                    }
+                    if (hc) {
+                        const int32_t k = nc + __popcll(mc & below);
+                        if (k < ls.ccap) crow[k] = j;
+                    }
+                    nf += __popcll(mf);
+                    nc += __popcll(mc);
+                }
+            }
+            if (lane == 0) {
+                rowf[w][i - bi] = nf;
+                rowc[w][i - bi] = nc;
+            }
+        }
+        wave_sync();
+    }
+    for (int32_t k = lane; k < ei - bi; k += 64) {
+        const int32_t nf = rowf[w][k], nc = rowc[w][k];
+        if (bs.want_force) ls.fcnt[bi + k] = min(nf, ls.fcap);
+        if (bs.want_cand) ls.ccnt[bi + k] = min(nc, ls.ccap);
+        overflow |= nf > ls.fcap || nc > ls.ccap;
     }
     if (overflow) atomicOr(&st->status, ST_CAPACITY);
 }
@@ -221,10 +351,10 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_bin, dim3(nb), dim3(256), 0, sm, n, pos, reps, tp, ls, st);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
-    hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 127) / 128), dim3(128), 0, sm, ls.n_cells,
+    hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
                        pos, tp, ls, st, bs.mirror_sel);
-    hipLaunchKernelGGL(k_lists, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells, reps,
-                       cell_rep, tp, ls, bs, st);
+    hipLaunchKernelGGL(k_lists, dim3((ls.n_cells + LW - 1) / LW), dim3(64 * LW), 0, sm, ls.n_cells,
+                       reps, cell_rep, tp, ls, bs, st);
 }
 
 }  // namespace bnc

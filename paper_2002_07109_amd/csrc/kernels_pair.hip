@@ -13,8 +13,6 @@
 
 namespace bnc {
 
-constexpr int G = 8;
-
 template <typename R>
 struct DbwdConst {
     R fe_rc, dfe_rc;   // eps basis 4[(s/r)^12 - (s/r)^6] and d/dr at rc
@@ -69,6 +67,7 @@ __device__ void init_tables(TypePair<R> *tab, TypePair<double> *tabc, DbwdConst<
     }
 }
 
+template <int G>
 __device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
@@ -76,7 +75,8 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-template <typename R, int MODE>
+// G lanes per atom (4, 8, 16 or 32; chosen by the autotuner)
+template <typename R, int MODE, int G>
 __global__ void __launch_bounds__(256) k_pair(PairArgs a)
 {
     __shared__ TypePair<R> tab[MAXT * MAXT];
@@ -113,17 +113,17 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const int32_t par = a.mirror_sel >= 0 ? a.mirror_sel : (int32_t)(a.st->step & 1);
         const double4 *__restrict__ X = a.ls.x[par];
         const double4 xi = X[s];
-        const int ti = (int)xi.w;
+        const int ti = mirror_type(xi.w);
         gi = a.ls.perm[s];
-        const RepInfo &ri = a.reps[a.tp.rep_of[gi]];
+        const BoxReg box(a.reps[a.tp.rep_of[gi]]);
         const int32_t *row;
         int32_t cnt;
         if (a.list_sel == 1) {
             row = a.ls.clist + (int64_t)s * a.ls.ccap;
-            cnt = a.ls.ccnt[s];
+            cnt = min(a.ls.ccnt[s], a.ls.ccap);
         } else {
             row = a.ls.flist + (int64_t)s * a.ls.fcap;
-            cnt = a.ls.fcnt[s];
+            cnt = min(a.ls.fcnt[s], a.ls.fcap);
         }
         // U rows entries per lane in flight: their index and position loads are
         // issued together, which hides the gather latency
@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
             int32_t pj[U];
             double4 xj[U];
+            R px = (R)0, py = (R)0, pz = (R)0;   // partial sum of this block of U pairs
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = e0 + u * G;
@@ -140,13 +141,14 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
             for (int u = 0; u < U; ++u) xj[u] = X[pj[u] >= 0 ? pj[u] : s];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (pj[u] < 0) continue;
+                // every loaded position is used (an empty slot gets r2 = lim2), so
+                // the U gathers stay in flight together
                 double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
-                min_image(ri, dx, dy, dz);
+                box.apply(dx, dy, dz);
                 const R rx = (R)dx, ry = (R)dy, rz = (R)dz;
-                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
                 if (!(r2 < lim2)) continue;
-                const int tj = (int)xj[u].w;
+                const int tj = mirror_type(xj[u].w);
                 const TypePair<R> &tp = tab[ti * nt + tj];
                 if (MODE == MODE_ENERGY) {
                     // u(r) in R, the shifted-force terms u(rc) + (r - rc) u'(rc) in FP64
@@ -172,9 +174,9 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
                 } else {
                     f = dw * rinv;
                 }
-                ax += (double)(f * rx);
-                ay += (double)(f * ry);
-                az += (double)(f * rz);
+                px += f * rx;
+                py += f * ry;
+                pz += f * rz;
                 if (MODE == MODE_DBWD) {
                     R gg, dgg;
                     coul_g<R>(r, rinv, alpha, a.pg.coulomb, gg, dgg);
@@ -196,11 +198,14 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
                     }
                 }
             }
+            ax += (double)px;
+            ay += (double)py;
+            az += (double)pz;
         }
     }
     if (MODE == MODE_ENERGY) {
-        ec = group_sum(ec);
-        el = group_sum(el);
+        ec = group_sum<G>(ec);
+        el = group_sum<G>(el);
         if (valid && lig == 0) {
             if (a.energy_total) {
                 a.atom_out[gi] = 0.5 * (ec + el);
@@ -211,12 +216,12 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         }
         return;
     }
-    ax = group_sum(ax);
-    ay = group_sum(ay);
-    az = group_sum(az);
+    ax = group_sum<G>(ax);
+    ay = group_sum<G>(ay);
+    az = group_sum<G>(az);
     if (MODE == MODE_DBWD) {
 #pragma unroll
-        for (int k = 0; k < 3 * MAXT; ++k) bas[k] = group_sum(bas[k]);
+        for (int k = 0; k < 3 * MAXT; ++k) bas[k] = group_sum<G>(bas[k]);
         if (valid && lig == 0) {
             double *o = a.atom_out + (int64_t)gi * 3 * MAXT;
             for (int k = 0; k < 3 * nt; ++k) o[k] = bas[k];
@@ -236,29 +241,35 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
     }
 }
 
-void launch_pair(hipStream_t sm, int mode, int fp64, const PairArgs &a)
+template <typename R, int G>
+static void launch_pair_g(hipStream_t sm, int mode, const PairArgs &a)
+{
+    dim3 grid(((int64_t)a.n * G + 255) / 256), block(256);
+    switch (mode) {
+        case MODE_SHORT: hipLaunchKernelGGL((k_pair<R, MODE_SHORT, G>), grid, block, 0, sm, a); break;
+        case MODE_FULL: hipLaunchKernelGGL((k_pair<R, MODE_FULL, G>), grid, block, 0, sm, a); break;
+        case MODE_LONG: hipLaunchKernelGGL((k_pair<R, MODE_LONG, G>), grid, block, 0, sm, a); break;
+        case MODE_ENERGY: hipLaunchKernelGGL((k_pair<R, MODE_ENERGY, G>), grid, block, 0, sm, a); break;
+        case MODE_DBWD: hipLaunchKernelGGL((k_pair<R, MODE_DBWD, G>), grid, block, 0, sm, a); break;
+    }
+}
+
+template <typename R>
+static void launch_pair_r(hipStream_t sm, int mode, int lanes, const PairArgs &a)
+{
+    switch (lanes) {
+        case 4: launch_pair_g<R, 4>(sm, mode, a); break;
+        case 16: launch_pair_g<R, 16>(sm, mode, a); break;
+        case 32: launch_pair_g<R, 32>(sm, mode, a); break;
+        default: launch_pair_g<R, 8>(sm, mode, a); break;
+    }
+}
+
+void launch_pair(hipStream_t sm, int mode, int fp64, int lanes, const PairArgs &a)
 {
     if (a.n <= 0) return;
-    dim3 grid(((int64_t)a.n * G + 255) / 256), block(256);
-#define L_(R, M) hipLaunchKernelGGL((k_pair<R, M>), grid, block, 0, sm, a)
-    if (fp64) {
-        switch (mode) {
-            case MODE_SHORT: L_(double, MODE_SHORT); break;
-            case MODE_FULL: L_(double, MODE_FULL); break;
-            case MODE_LONG: L_(double, MODE_LONG); break;
-            case MODE_ENERGY: L_(double, MODE_ENERGY); break;
-            case MODE_DBWD: L_(double, MODE_DBWD); break;
-        }
-    } else {
-        switch (mode) {
-            case MODE_SHORT: L_(float, MODE_SHORT); break;
-            case MODE_FULL: L_(float, MODE_FULL); break;
-            case MODE_LONG: L_(float, MODE_LONG); break;
-            case MODE_ENERGY: L_(float, MODE_ENERGY); break;
-            case MODE_DBWD: L_(float, MODE_DBWD); break;
-        }
-    }
-#undef L_
+    if (fp64) launch_pair_r<double>(sm, mode, lanes, a);
+    else launch_pair_r<float>(sm, mode, lanes, a);
 }
 
 __global__ void k_bonded_grad(int32_t n, const double *pos, const RepInfo *reps, Topo tp,

@@ -58,18 +58,17 @@ struct JumpTally {
 };
 
 // the velocity chain of one atom over dt/2 at fixed positions
+// (U: the uniform of the atom's Poisson draw, counter (step, phase, lid, 0))
 template <typename R>
 __device__ void jump_atom(const StepArgs &a, const TypePair<R> *tab, const double4 *X, int32_t s,
                           int32_t lid, int32_t rep, const RepInfo &ri, int ti, const double q[3],
-                          double v[3], int64_t step, int32_t phase, JumpTally &tally)
+                          double v[3], int64_t step, int32_t phase, double U, JumpTally &tally)
 {
-    const int32_t c = a.ls.ccnt[s];
+    const int32_t c = min(a.ls.ccnt[s], a.ls.ccap);
     const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     const double L = a.L_a[ti];
     if (c == 0 || v0 == 0.0 || L == 0.0) return;
     const double mu = (double)c * a.beta * v0 * L * a.half_dt;
-    const U4 w0 = draw(ri, step, phase, lid, 0);
-    const double U = u01(w0.x);
     int32_t M = 0;
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
@@ -90,9 +89,9 @@ __device__ void jump_atom(const StepArgs &a, const TypePair<R> *tab, const doubl
         const double u = u01(w.y);
         const double4 xj = X[p];
         double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
-        min_image(ri, dx, dy, dz);
+        BoxReg(ri).apply(dx, dy, dz);
         double F[3];
-        long_field<R>(tab[ti * nt + (int)xj.w], a.pg, dx, dy, dz, F);
+        long_field<R>(tab[ti * nt + mirror_type(xj.w)], a.pg, dx, dy, dz, F);
         const double sdot = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
         // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
         const int acc = (u * v0 * L) < sdot;
@@ -149,49 +148,96 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
     }
 }
 
+// Four lanes per atom, running the same code on different data: each lane
+// draws one Philox block (lane 0: the O step, lane 1: the Poisson uniform of
+// J(n-1, JB), lane 2: that of J(n, JA)), lanes 0-2 turn the O block into the
+// three Box-Muller normals, and the lanes share the atom's bonded terms; lane 0
+// then runs the atom's sequential chain (kicks, jump chains, drifts, O step).
+constexpr int LPA = 4;
+
+__device__ __forceinline__ double group_get(double v, int src)
+{
+    return __shfl(v, (int)(threadIdx.x & 63 & ~(LPA - 1)) + src, 64);
+}
+
+__device__ __forceinline__ uint64_t group_get_u64(uint64_t v, int src)
+{
+    return (uint64_t)__shfl((long long)v, (int)(threadIdx.x & 63 & ~(LPA - 1)) + src, 64);
+}
+
 template <typename R, bool BOUNCE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
     __shared__ TypePair<R> tab[MAXT * MAXT];
     if (BOUNCE) init_pair_table<R>(tab, a.type_params, a.pg);
     __syncthreads();
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = t / LPA, sub = t % LPA;
     const bool active = s < a.n;
     const int64_t n = a.st->step;
     const int32_t par = (int32_t)(n & 1);
     const double4 *__restrict__ X = a.ls.x[par];
     double4 *__restrict__ Y = a.ls.x[par ^ 1];
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0;
+    int32_t rep = 0, g = 0, lid = 0;
+    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    U4 w = {0, 0, 0, 0};
+    double fb[3] = {0.0, 0.0, 0.0};
     if (active) {
-        const int32_t g = a.ls.perm[s];
+        g = a.ls.perm[s];
         rep = a.tp.rep_of[g];
         const RepInfo &ri = a.reps[rep];
-        const int32_t lid = g - (int32_t)ri.atom_off;
-        const double4 xi = X[s];
-        const int ti = (int)xi.w;
+        lid = g - (int32_t)ri.atom_off;
+        xi = X[s];
+        // one Philox block per lane
+        const int64_t dstep = sub == 1 ? n - 1 : n;
+        const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
+        w = draw(ri, dstep, dphase, lid, 0);
+        // bonded terms shared by the lanes
+        for (int32_t k = a.tp.bt_ptr[g] + sub; k < a.tp.bt_ptr[g + 1]; k += LPA)
+            bonded_term_grad(g, a.tp.bt[k], MirrorPos{X, a.ls.inv_perm}, ri, a.tp, fb);
+    }
+    // Box-Muller on the O block: lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
+    const uint64_t ow0 = group_get_u64(w.x, 0), ow1 = group_get_u64(w.y, 0);
+    const uint64_t ow2 = group_get_u64(w.z, 0), ow3 = group_get_u64(w.w, 0);
+    double gauss;
+    {
+        const double ua = u01(sub >= 2 ? ow2 : ow0), ub = u01(sub >= 2 ? ow3 : ow1);
+        const double rad = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincos(2.0 * M_PI * ub, &sn, &cs);
+        gauss = rad * (sub == 1 ? sn : cs);
+    }
+    const double G0 = group_get(gauss, 0), G1 = group_get(gauss, 1), G2 = group_get(gauss, 2);
+    const double U_jb = u01(group_get_u64(w.x, 1)), U_ja = u01(group_get_u64(w.x, 2));
+    double B0 = fb[0], B1 = fb[1], B2 = fb[2];
+#pragma unroll
+    for (int m = 1; m < LPA; m <<= 1) {
+        B0 += __shfl_xor(B0, m, LPA);
+        B1 += __shfl_xor(B1, m, LPA);
+        B2 += __shfl_xor(B2, m, LPA);
+    }
+
+    if (active && sub == 0) {
+        const RepInfo &ri = a.reps[rep];
+        const int ti = mirror_type(xi.w);
         double q[3] = {xi.x, xi.y, xi.z};
-        double F[3] = {a.fpair[3 * (int64_t)s], a.fpair[3 * (int64_t)s + 1],
-                       a.fpair[3 * (int64_t)s + 2]};
-        bonded_grad_atom(g, MirrorPos{X, a.ls.inv_perm}, ri, a.tp, F);
+        const double F[3] = {a.fpair[3 * (int64_t)s] + B0, a.fpair[3 * (int64_t)s + 1] + B1,
+                             a.fpair[3 * (int64_t)s + 2] + B2};
         double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
         const double km = a.half_dt * a.tp.acc_m[g];
         if (a.do_close) {
-            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n - 1, 2, tally);
+            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n - 1, 2, U_jb, tally);
             v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
         }
         if (a.do_open) {
             v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
-            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n, 0, tally);
+            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n, 0, U_ja, tally);
             for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
-            // O: Ornstein-Uhlenbeck exact step with Box-Muller normals
-            const U4 w = draw(ri, n, 1, lid, 0);
-            const double u1 = u01(w.x), u2 = u01(w.y), u3 = u01(w.z), u4 = u01(w.w);
-            const double ra = sqrt(-2.0 * log(u1)), rb = sqrt(-2.0 * log(u3));
-            const double G3[3] = {ra * cos(2.0 * M_PI * u2), ra * sin(2.0 * M_PI * u2),
-                                  rb * cos(2.0 * M_PI * u4)};
             const double c2 = a.ou_c2[g];
-            for (int c = 0; c < 3; ++c) v[c] = a.c1 * v[c] + c2 * G3[c];
+            v[0] = a.c1 * v[0] + c2 * G0;
+            v[1] = a.c1 * v[1] + c2 * G1;
+            v[2] = a.c1 * v[2] + c2 * G2;
             for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
             const double *qb = a.ls.q_build + 3 * (int64_t)g;
             const double ddx = q[0] - qb[0], ddy = q[1] - qb[1], ddz = q[2] - qb[2];
@@ -208,7 +254,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
                    isfinite(q[1]) && isfinite(q[2]);
         if (!fin) atomicOr(&a.st->status, ST_NONFINITE);
     }
-    if (BOUNCE) flush_tally(a, rep, active, tally);
+    if (BOUNCE) flush_tally(a, rep, active && sub == 0, tally);
     if (a.do_open) {
         // the last block to finish advances the device step counter
         __syncthreads();
@@ -227,7 +273,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
 void launch_step(hipStream_t sm, const StepArgs &a)
 {
     if (a.n <= 0) return;
-    dim3 grid((a.n + 255) / 256), block(256);
+    dim3 grid(((int64_t)a.n * LPA + 255) / 256), block(256);
     if (a.bounce) {
         if (a.pair_fp64) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, sm, a);
         else hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, sm, a);
@@ -257,8 +303,9 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
         const double4 xi = X[s];
         double q[3] = {xi.x, xi.y, xi.z};
         double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
-        jump_atom<R>(a, tab, X, s, g - (int32_t)ri.atom_off, rep, ri, (int)xi.w, q, v, ja.step,
-                     ja.phase, tally);
+        const int32_t lid = g - (int32_t)ri.atom_off;
+        jump_atom<R>(a, tab, X, s, lid, rep, ri, mirror_type(xi.w), q, v, ja.step, ja.phase,
+                     u01(draw(ri, ja.step, ja.phase, lid, 0).x), tally);
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];
         a.vel[3 * (int64_t)g + 2] = v[2];

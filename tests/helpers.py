@@ -15,7 +15,8 @@ FF = tip3p_params()
 DROPLET = dict(integrator=0, periodic=0, coulomb=0, dt=0.25, gamma=1e-3, temperature=300.0,
                r_on=5.0, r_off=6.0, r_cut=9.0, skin=2.0, ewald_alpha=0.35, rebuild_interval=10,
                seed=0, bound_scale=1.0)
-BOX = dict(DROPLET, periodic=1, coulomb=1, r_on=6.0, r_off=7.0, dt=1.0)
+# periodic boxes: Ewald real-space erfc with alpha = 0.45/A (the benchmark's model)
+BOX = dict(DROPLET, periodic=1, coulomb=1, r_on=6.0, r_off=7.0, dt=1.0, ewald_alpha=0.45)
 
 
 def oracle_params(orc, sys, cfg, replica=0):
@@ -59,6 +60,7 @@ def event_keys(ev, fields=("step", "phase", "atom", "k", "partner", "accepted"))
 
 _FIX = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "relaxed_droplets.npz")
 _SPEC = {"c0": (216, 0, 5), "r0": (40, 3, 200), "r1": (150, 3, 201), "r2": (90, 3, 202)}
+_BOX_SPEC = {"b8": (8, 24.8, 1)}
 
 
 def relaxed_droplet(name):
@@ -69,3 +71,21 @@ def relaxed_droplet(name):
     z = np.load(_FIX)
     s.pos, s.vel = z[name + "_pos"].copy(), z[name + "_vel"].copy()
     return s
+
+
+def relaxed_box(name):
+    """Seeded periodic box with the oracle-relaxed state of the fixture file."""
+    from workloads import water_box
+    n_side, edge, seed = _BOX_SPEC[name]
+    s = copy.deepcopy(water_box(n_side=n_side, box_len=edge, seed=seed))
+    z = np.load(_FIX)
+    s.pos, s.vel = z[name + "_pos"].copy(), z[name + "_vel"].copy()
+    return s
+
+
+def rel_err_total(a, b, total):
+    """max_i |a_i - b_i| / RMS_i |total_i|: error of one force part against the
+    scale of the whole force."""
+    a, b, total = np.asarray(a), np.asarray(b), np.asarray(total)
+    rms = np.sqrt(np.mean(np.sum(total * total, axis=-1)))
+    return float(np.max(np.linalg.norm(a - b, axis=-1)) / rms)
