@@ -32,8 +32,48 @@ FLOPS_FULL = 36      # W'_sf d/r without the switch
 PEAK_FP32 = 157.3    # TFLOP/s, MI355X vector FP32 (published)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_short_24k_box_traffic.md")
+PAIR_SOURCES = ("kernels_pair.hip", "bounce_device.hpp", "bounce_kernels.hpp", "bounce_lists.hpp")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def pair_source_hash():
+    """Hash of the sources the short-range pair kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_07109_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(lanes):
+    """HBM bytes per launch of the short-range pair kernel, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary; None unless that summary was taken
+    on the current kernel source with the same lanes per atom."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_hash") != pair_source_hash() or rec.get("lanes") != lanes:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    counters (FETCH_SIZE, WRITE_SIZE) of a rocprofv3 --pmc run of this script."""
+    import torch
+    a = torch.ones(mib << 20, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {mib} MiB")
 
 
 def pair_count(pos, box, r, n_excl_within):
@@ -139,6 +179,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -211,12 +253,15 @@ def main():
         "speedup_vs_baoab": round(ba["ms_per_step"] / bo["ms_per_step"], 4),
         "roofline": {"kernel": "F_0 pair kernel (BOUNCE short range)", "bound": "alu",
                      "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32, 5), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32, 5),
+                     "traffic": measured_traffic(bo["lanes"]),
                      "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs},
     }
     if not args.skip_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(args, system)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
     print(json.dumps(line), flush=True)
 
 

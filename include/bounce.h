@@ -101,6 +101,7 @@ typedef struct {
     const double *charge, *eps, *sigma;  /* [n_types] e, kcal/mol, Angstrom; Lorentz-Berthelot mixing */
     int32_t n_bonds;   const int32_t *bonds;  const double *bond_k, *bond_r0;   /* E = k (r - r0)^2       */
     int32_t n_angles;  const int32_t *angles; const double *angle_k, *angle_t0; /* [na][3], vertex middle */
+                                     /* at most 8 bonds + angles may touch one atom     */
     int32_t n_excl;    const int32_t *excl;   /* [n_excl][2] pairs with no nonbonded term        */
 } bounce_system;
 

@@ -86,6 +86,8 @@ struct bounce_ctx {
     std::vector<int32_t> type, rep_of, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, angle_ijk;
     std::vector<double> mass, acc_m, inv_mass, ou_c2, bond_kr, angle_kt, tparams;
     std::vector<double> L_ab, L_a;
+    std::vector<TypePair<float>> tab_f;     // jump-field pair constants per type pair
+    std::vector<TypePair<double>> tab_d;
     int32_t n_cells = 0, fcap = 0, ccap = 0, acap = 0, xcap = 0;
     // workspace
     char *ws = nullptr;
@@ -98,6 +100,8 @@ struct bounce_ctx {
     DevState *d_st = nullptr;
     RepCounters *d_cnt = nullptr;
     Event *d_events = nullptr;
+    const TypePair<float> *d_tab_f = nullptr;
+    const TypePair<double> *d_tab_d = nullptr;
     double *d_La = nullptr, *d_tparams = nullptr, *d_fpair = nullptr, *d_atom = nullptr,
            *d_seg = nullptr, *d_ou_c2 = nullptr;
     int64_t *d_rep_off = nullptr, *d_one_seg = nullptr;
@@ -105,7 +109,8 @@ struct bounce_ctx {
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
     // schedule
-    int64_t step = 0;
+    int64_t step = 0;             // host view: device counter + pending
+    int32_t pending = 0;          // steps opened since the device counter last moved
     int64_t built_step = -1;
     int64_t host_steps = 0, host_rebuilds = 0;
     // graphs of K steps
@@ -196,6 +201,21 @@ static void make_bounds(bounce_ctx *c)
     ff.r_on = c->p.r_on; ff.r_off = c->p.r_off; ff.r_cut = c->p.r_cut;
     c->L_ab.assign(c->nt * c->nt, 0.0);
     c->L_a.assign(c->nt, 0.0);
+    // pair constants of the jump field chi W'_sf: q_a q_b, LJ, u'(rc)
+    c->tab_f.assign(MAXT * MAXT, TypePair<float>{});
+    c->tab_d.assign(MAXT * MAXT, TypePair<double>{});
+    for (int a = 0; a < c->nt; ++a)
+        for (int b = 0; b < c->nt; ++b) {
+            const double qq = KE * ff.q[a] * ff.q[b], eps = std::sqrt(ff.eps[a] * ff.eps[b]);
+            const double sig = 0.5 * (ff.sig[a] + ff.sig[b]);
+            double drc;
+            ff.du(a, b, ff.r_cut, drc);
+            TypePair<double> &td = c->tab_d[a * c->nt + b];
+            td.qq = qq; td.eps4 = 4.0 * eps; td.sig2 = sig * sig; td.du_rc = drc;
+            TypePair<float> &tf = c->tab_f[a * c->nt + b];
+            tf.qq = (float)qq; tf.eps4 = (float)(4.0 * eps); tf.sig2 = (float)(sig * sig);
+            tf.du_rc = (float)drc;
+        }
     if (c->p.integrator != BOUNCE_BJAOAJB) return;
     for (int a = 0; a < c->nt; ++a)
         for (int b = a; b < c->nt; ++b) c->L_ab[a * c->nt + b] = c->L_ab[b * c->nt + a] = ff.bound(a, b);
@@ -323,6 +343,8 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
             bt[a].push_back((1 << 28) | k);
         }
     }
+    for (int32_t g = 0; g < n; ++g)
+        if ((int)bt[g].size() > BTMAX) return fail(c, BOUNCE_E_ARG, "more than 8 bonded terms on one atom");
     c->excl_ptr.assign(n + 1, 0);
     c->bt_ptr.assign(n + 1, 0);
     c->excl_idx.clear();
@@ -362,9 +384,9 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
-        angle_ijk, angle_kt, reps, La, tparams, rep_off, one_seg, st, cnt, events, fpair, atom,
+        angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep;
-    size_t ls[2][12];
+    size_t ls[2][13];
 };
 
 static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
@@ -386,11 +408,13 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.reps = L.take(sizeof(RepInfo) * R);
     o.La = L.take(8 * MAXT);
     o.tparams = L.take(8 * 3 * MAXT);
+    o.tab_f = L.take(sizeof(TypePair<float>) * MAXT * MAXT);
+    o.tab_d = L.take(sizeof(TypePair<double>) * MAXT * MAXT);
     o.rep_off = L.take(8 * (R + 1));
     o.cell_rep = L.take(4 * (size_t)c->n_cells);
     o.one_seg = L.take(16);
     o.st = L.take(sizeof(DevState));
-    o.cnt = L.take(sizeof(RepCounters) * R);
+    o.cnt = L.take(sizeof(RepCounters) * CNT_SPREAD * R);
     o.events = L.take(sizeof(Event) * std::max<int64_t>(1, c->p.log_events ? c->p.event_capacity : 1));
     o.fpair = L.take(24 * n);
     o.atom = L.take(8 * n * std::max(5, 3 * MAXT));
@@ -412,6 +436,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[9] = L.take(4 * n);                      // fcnt
         q[10] = L.take(4 * n * fcap);              // flist
         q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
+        q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
     }
 }
 
@@ -468,12 +493,14 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     for (int a = 0; a < c->nt; ++a) La[a] = c->L_a[a] * c->p.bound_scale;
     HIPCHK(c, up(sm, ws, o.La, La));
     HIPCHK(c, up(sm, ws, o.tparams, c->tparams));
+    HIPCHK(c, up(sm, ws, o.tab_f, c->tab_f));
+    HIPCHK(c, up(sm, ws, o.tab_d, c->tab_d));
     HIPCHK(c, up(sm, ws, o.rep_off, c->rep_off));
     HIPCHK(c, up(sm, ws, o.cell_rep, c->cell_rep));
     std::vector<int64_t> one = {0, c->n};
     HIPCHK(c, up(sm, ws, o.one_seg, one));
     HIPCHK(c, hipMemsetAsync(ws + o.st, 0, sizeof(DevState), sm));
-    HIPCHK(c, hipMemsetAsync(ws + o.cnt, 0, sizeof(RepCounters) * c->R, sm));
+    HIPCHK(c, hipMemsetAsync(ws + o.cnt, 0, sizeof(RepCounters) * CNT_SPREAD * c->R, sm));
     Topo &t = c->tp;
     t.type = at<int32_t>(ws, o.type);
     t.rep_of = at<int32_t>(ws, o.rep_of);
@@ -490,6 +517,8 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     c->d_reps = at<RepInfo>(ws, o.reps);
     c->d_La = at<double>(ws, o.La);
     c->d_tparams = at<double>(ws, o.tparams);
+    c->d_tab_f = at<TypePair<float>>(ws, o.tab_f);
+    c->d_tab_d = at<TypePair<double>>(ws, o.tab_d);
     c->d_rep_off = at<int64_t>(ws, o.rep_off);
     c->d_cell_rep = at<int32_t>(ws, o.cell_rep);
     c->d_one_seg = at<int64_t>(ws, o.one_seg);
@@ -518,6 +547,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
         ls.flist = at<int32_t>(ws, q[10]);
         ls.ccnt = at<int32_t>(ws, q[11]);
         ls.clist = at<int32_t>(ws, q[11]) + c->n;
+        ls.bslot = k == 0 ? at<int4>(ws, q[12]) : nullptr;
         ls.fcap = k == 0 ? c->fcap : c->acap;
         ls.ccap = k == 0 ? c->ccap : 0;
         ls.n_cells = c->n_cells;
@@ -527,6 +557,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
     if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
     c->step = 0;
+    c->pending = 0;
     c->built_step = -1;
     c->host_steps = 0;
     c->host_rebuilds = 0;
@@ -577,6 +608,7 @@ bounce_status bounce_set_step(bounce_ctx *c, int64_t step)
     HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->step = step;
+    c->pending = 0;
     c->built_step = -1;
     return BOUNCE_OK;
 }
@@ -625,9 +657,11 @@ static BuildSpec main_spec(const bounce_ctx *c)
     return b;
 }
 
-static void enqueue_build(bounce_ctx *c)
+static void enqueue_build(bounce_ctx *c, int32_t step_off)
 {
-    launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, main_spec(c), c->d_st);
+    BuildSpec b = main_spec(c);
+    b.step_off = step_off;
+    launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, b, c->d_st);
 }
 
 static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
@@ -644,9 +678,10 @@ static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
     return a;
 }
 
-static void enqueue_force(bounce_ctx *c)
+static void enqueue_force(bounce_ctx *c, int32_t step_off)
 {
     PairArgs a = pair_args(c, c->main, -1);
+    a.step_off = step_off;
     a.out = c->d_fpair;
     a.out_global = 0;
     a.accumulate = 0;
@@ -654,10 +689,11 @@ static void enqueue_force(bounce_ctx *c)
                 c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
 }
 
-static StepArgs step_args(bounce_ctx *c, int close, int open)
+static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
 {
     StepArgs a{};
     a.n = c->n;
+    a.step_off = step_off;
     a.do_close = close;
     a.do_open = open;
     a.bounce = c->p.integrator == BOUNCE_BJAOAJB;
@@ -676,7 +712,8 @@ static StepArgs step_args(bounce_ctx *c, int close, int open)
     a.vel = c->vel;
     a.ou_c2 = c->d_ou_c2;
     a.L_a = c->d_La;
-    a.type_params = c->d_tparams;
+    a.tab_f = c->d_tab_f;
+    a.tab_d = c->d_tab_d;
     a.pg = pair_globals(c);
     a.dt = c->p.dt;
     a.half_dt = 0.5 * c->p.dt;
@@ -687,16 +724,27 @@ static StepArgs step_args(bounce_ctx *c, int close, int open)
 }
 
 // one substep of the fused schedule at the current step index c->step
+// (= device counter + c->pending once the launches before it have run)
 static void enqueue_substep(bounce_ctx *c, int close, int open)
 {
     if (c->built_step < 0 || (c->step % c->p.rebuild_interval == 0 && c->built_step != c->step)) {
-        enqueue_build(c);
+        enqueue_build(c, c->pending);
         c->built_step = c->step;
         c->host_rebuilds++;
     }
-    enqueue_force(c);
-    launch_step(c->stream, step_args(c, close, open));
-    if (open) c->step++;
+    enqueue_force(c, c->pending);
+    launch_step(c->stream, step_args(c, close, open, c->pending));
+    if (open) {
+        c->step++;
+        c->pending++;
+    }
+}
+
+// bring the device step counter up to c->step
+static void flush_pending(bounce_ctx *c)
+{
+    launch_advance(c->stream, c->d_st, c->pending);
+    c->pending = 0;
 }
 
 // a graph of K fused steps starting at a multiple of K (rebuild at its head)
@@ -714,10 +762,11 @@ static bounce_status make_graph(bounce_ctx *c)
         return fail(c, BOUNCE_E_HIP, std::string("capture: ") + hipGetErrorString(e));
     }
     for (int k = 0; k < c->p.rebuild_interval; ++k) {
-        if (k == 0) enqueue_build(c);
-        enqueue_force(c);
-        launch_step(c->stream, step_args(c, 1, 1));
+        if (k == 0) enqueue_build(c, 0);
+        enqueue_force(c, k);
+        launch_step(c->stream, step_args(c, 1, 1, k));
     }
+    launch_advance(c->stream, c->d_st, c->p.rebuild_interval);
     e = hipStreamEndCapture(cap, &c->graph);
     c->stream = saved;
     (void)hipStreamDestroy(cap);
@@ -740,6 +789,7 @@ bounce_status bounce_step(bounce_ctx *c, int32_t n_steps)
         if (c->p.use_graph && c->step % K == 0 && c->step + K <= end) {
             s = make_graph(c);
             if (s) return s;
+            flush_pending(c);
             HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
             c->step += K;
             c->built_step = c->step - K;
@@ -750,6 +800,7 @@ bounce_status bounce_step(bounce_ctx *c, int32_t n_steps)
     }
     // close the last step: J(n-1, JB), B(dt/2) with F_0 at q_n
     enqueue_substep(c, 1, 0);
+    flush_pending(c);
     c->host_steps += n_steps;
     HIPCHK(c, hipGetLastError());
     return BOUNCE_OK;
@@ -852,12 +903,16 @@ bounce_status bounce_get_counters(bounce_ctx *c, int32_t replica, bounce_counter
     bounce_status s = ready(c);
     if (s) return s;
     if (!out || replica < 0 || replica >= c->R) return BOUNCE_E_ARG;
-    RepCounters rc;
+    std::vector<RepCounters> rc(CNT_SPREAD);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(&rc, c->d_cnt + replica, sizeof rc, hipMemcpyDeviceToHost));
-    out->proposals = (int64_t)rc.proposals;
-    out->accepted = (int64_t)rc.accepted;
-    out->bound_violations = (int64_t)rc.bound_violations;
+    HIPCHK(c, hipMemcpy(rc.data(), c->d_cnt + (int64_t)replica * CNT_SPREAD,
+                        sizeof(RepCounters) * CNT_SPREAD, hipMemcpyDeviceToHost));
+    out->proposals = out->accepted = out->bound_violations = 0;
+    for (const RepCounters &k : rc) {
+        out->proposals += (int64_t)k.proposals;
+        out->accepted += (int64_t)k.accepted;
+        out->bound_violations += (int64_t)k.bound_violations;
+    }
     out->rebuilds = c->host_rebuilds;
     out->steps = c->host_steps;
     return BOUNCE_OK;
@@ -919,12 +974,12 @@ bounce_status bounce_jump_halfstep(bounce_ctx *c, int64_t step, int32_t phase)
     if (c->p.integrator != BOUNCE_BJAOAJB) return fail(c, BOUNCE_E_ARG, "BAOAB has no J step");
     if (phase != BOUNCE_PH_JA && phase != BOUNCE_PH_JB) return BOUNCE_E_ARG;
     if (c->built_step != c->step) {
-        enqueue_build(c);
+        enqueue_build(c, 0);
         c->built_step = c->step;
         c->host_rebuilds++;
     }
     JumpArgs ja{};
-    ja.s = step_args(c, 0, 0);
+    ja.s = step_args(c, 0, 0, 0);
     ja.step = step;
     ja.phase = phase;
     launch_jump(c->stream, ja);
@@ -977,7 +1032,7 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     if (s) return s;
     if (!avg_ms || reps < 1 || (which != 0 && which != 1)) return BOUNCE_E_ARG;
     if (c->built_step < 0) {
-        enqueue_build(c);
+        enqueue_build(c, 0);
         c->built_step = c->step;
         c->host_rebuilds++;
     }
@@ -986,8 +1041,8 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     HIPCHK(c, hipEventCreate(&e1));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int32_t k = 0; k < reps; ++k) {
-        if (which == 0) enqueue_force(c);
-        else enqueue_build(c);
+        if (which == 0) enqueue_force(c, 0);
+        else enqueue_build(c, 0);
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));

@@ -77,6 +77,47 @@ __device__ __forceinline__ void bonded_term_grad(int32_t g, int32_t code, const 
     }
 }
 
+// the same gradient from a resolved term e = (code, slot of each atom) of the
+// atom at sorted position s, positions from the sorted mirror X
+__device__ __forceinline__ void bonded_slot_grad(int32_t s, int4 e, const double4 *X,
+                                                 const RepInfo &ri, const Topo &tp, double out[3])
+{
+    const int32_t kind = e.x >> 28, idx = e.x & 0x0fffffff;
+    auto disp = [&](int32_t a, int32_t b, double d[3]) {
+        const double4 xa = X[a], xb = X[b];
+        double dx = xa.x - xb.x, dy = xa.y - xb.y, dz = xa.z - xb.z;
+        min_image(ri, dx, dy, dz);
+        d[0] = dx; d[1] = dy; d[2] = dz;
+    };
+    if (kind == 0) {
+        double d[3];
+        disp(e.y, e.z, d);
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double c = 2.0 * tp.bond_kr[2 * idx] * (r - tp.bond_kr[2 * idx + 1]) / r;
+        const double sg = (s == e.y) ? c : -c;
+        out[0] += sg * d[0]; out[1] += sg * d[1]; out[2] += sg * d[2];
+    } else {
+        double e1[3], e2[3];
+        disp(e.y, e.z, e1);
+        disp(e.w, e.z, e2);
+        const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        const double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        const double il = 1.0 / (l1 * l2);
+        double cs = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) * il;
+        cs = fmin(1.0, fmax(-1.0, cs));
+        const double th = acos(cs);
+        const double sn = sqrt(1.0 - cs * cs);
+        const double w = -2.0 * tp.angle_kt[2 * idx] * (th - tp.angle_kt[2 * idx + 1]) / sn;
+        for (int c = 0; c < 3; ++c) {
+            const double gx = w * (e2[c] * il - cs * e1[c] / (l1 * l1));
+            const double gy = w * (e1[c] * il - cs * e2[c] / (l2 * l2));
+            if (s == e.y) out[c] += gx;
+            if (s == e.w) out[c] += gy;
+            if (s == e.z) out[c] -= gx + gy;
+        }
+    }
+}
+
 template <class PosF>
 __device__ void bonded_grad_atom(int32_t g, const PosF &pf, const RepInfo &ri, const Topo &tp,
                                  double out[3])

@@ -39,12 +39,15 @@ struct DevState {
     int64_t step;
     int64_t n_events;
     uint32_t status;
-    uint32_t done_blocks;
-    uint32_t pad[2];
+    uint32_t pad[3];
 };
 
+// jump counters of one replica, held in CNT_SPREAD copies (one 128-byte line
+// each) so that the wavefronts' atomic adds spread over many addresses; a read
+// sums the copies
+constexpr int CNT_SPREAD = 64;
 struct RepCounters {
-    unsigned long long proposals, accepted, bound_violations, rebuilds, steps;
+    unsigned long long proposals, accepted, bound_violations, pad[13];
 };
 
 struct Event {

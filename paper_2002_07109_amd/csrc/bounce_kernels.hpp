@@ -8,7 +8,8 @@ enum PairMode { MODE_SHORT = 0, MODE_FULL = 1, MODE_LONG = 2, MODE_ENERGY = 3, M
 
 struct PairArgs {
     int32_t n;
-    int32_t mirror_sel;           // -1: device step parity, 0/1 fixed
+    int32_t mirror_sel;           // -1: parity of step (device counter + step_off), 0/1 fixed
+    int32_t step_off;
     const RepInfo *reps;
     Topo tp;
     ListSet ls;
@@ -33,7 +34,7 @@ struct StepArgs {
     int32_t pair_fp64;            // jump pair field precision
     int32_t log_events;
     int32_t max_proposals;
-    int32_t pad;
+    int32_t step_off;             // step n = device counter + step_off
     const RepInfo *reps;
     Topo tp;
     ListSet ls;
@@ -46,7 +47,8 @@ struct StepArgs {
     double *vel;                  // [N][3] caller order
     const double *ou_c2;          // [N] O-step noise amplitude
     const double *L_a;            // [n_types] rate bounds (bound_scale applied)
-    const double *type_params;
+    const TypePair<float> *tab_f; // [MAXT][MAXT] pair constants of the jump field
+    const TypePair<double> *tab_d;
     PairGlobals pg;
     double dt, half_dt, c1, beta;
     double skin_half2;            // (s/2)^2
@@ -69,6 +71,8 @@ void launch_atom_energy(hipStream_t sm, int32_t n, const double *pos, const doub
 void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, const double *vals,
                         int32_t width, int32_t stride, int32_t col0, double *out);
 void launch_step(hipStream_t sm, const StepArgs &a);
+// device step counter += count (one thread; orders after the preceding launches)
+void launch_advance(hipStream_t sm, DevState *st, int32_t count);
 void launch_jump(hipStream_t sm, const JumpArgs &a);
 void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
                            int32_t *cnt_global, int32_t *col_global, int32_t cap);

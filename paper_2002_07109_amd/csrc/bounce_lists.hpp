@@ -17,10 +17,15 @@ struct ListSet {
     int32_t *flist;       // [N][fcap] sorted partner positions
     int32_t *ccnt;        // candidate list (jump partners)
     int32_t *clist;       // [N][ccap]
+    int4 *bslot;          // [N][BTMAX] bonded terms of each sorted atom with their
+                          //   atoms as sorted positions (x = term code, -1: none); or NULL
     int32_t fcap, ccap;
     int32_t n_cells;
     int32_t pad;
 };
+
+// most bonded terms (bonds + angles) touching one atom
+constexpr int BTMAX = 8;
 
 // what one build produces
 struct BuildSpec {
@@ -30,8 +35,8 @@ struct BuildSpec {
     double rsearch;       // cell-search radius (max of the radii)
     int32_t want_force;
     int32_t want_cand;
-    int32_t mirror_sel;   // -1: mirror of the device step parity, 0/1: fixed
-    int32_t pad;
+    int32_t mirror_sel;   // -1: mirror of the parity of step (device counter + step_off), 0/1: fixed
+    int32_t step_off;
 };
 
 // static per-atom topology on the device

@@ -95,7 +95,7 @@ __device__ __forceinline__ void wave_sync()
 // the lanes; a serial insertion sort above 64 atoms) and fill the mirror.
 __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double *__restrict__ pos,
                                                   Topo tp, ListSet ls, const DevState *st,
-                                                  int32_t mirror_sel)
+                                                  int32_t mirror_sel, int32_t step_off)
 {
     const int lane = threadIdx.x & 63;
     const int32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -117,13 +117,38 @@ __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double 
     }
     __threadfence_block();
     wave_sync();
-    const int32_t par = mirror_sel >= 0 ? mirror_sel : (int32_t)(st->step & 1);
+    const int32_t par = mirror_sel >= 0 ? mirror_sel : (int32_t)((st->step + step_off) & 1);
     double4 *X = ls.x[par];
     for (int32_t i = b + lane; i < e; i += 64) {
         const int32_t g = p[i];
         ls.inv_perm[g] = i;
         const double *x = pos + 3 * (int64_t)g;
         X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
+    }
+}
+
+// each atom's bonded terms with their atoms as sorted positions (after the sort)
+__global__ void k_bslots(int32_t n, Topo tp, ListSet ls)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int4 *row = ls.bslot + (int64_t)ls.inv_perm[g] * BTMAX;
+    const int32_t b = tp.bt_ptr[g], e = tp.bt_ptr[g + 1];
+    for (int32_t k = 0; k < BTMAX; ++k) {
+        int4 t = make_int4(-1, 0, 0, 0);
+        if (b + k < e) {
+            const int32_t code = tp.bt[b + k], idx = code & 0x0fffffff;
+            t.x = code;
+            if ((code >> 28) == 0) {
+                t.y = ls.inv_perm[tp.bond_ij[2 * idx]];
+                t.z = ls.inv_perm[tp.bond_ij[2 * idx + 1]];
+            } else {
+                t.y = ls.inv_perm[tp.angle_ijk[3 * idx]];
+                t.z = ls.inv_perm[tp.angle_ijk[3 * idx + 1]];
+                t.w = ls.inv_perm[tp.angle_ijk[3 * idx + 2]];
+            }
+        }
+        row[k] = t;
     }
 }
 
@@ -136,210 +161,216 @@ __device__ __forceinline__ double cell_gap(int32_t ci, int32_t cj, int32_t n, do
     return d > 1 ? (double)(d - 1) * w : 0.0;
 }
 
-constexpr int LW = 4;          // wavefronts (cells) per workgroup
-constexpr int LCAP = 1024;     // candidate atoms gathered per batch
+constexpr int LB = 4;          // wavefronts per cell
+constexpr int LCAP = 512;      // candidate atoms staged in LDS per batch
 constexpr int LMAXI = 64;      // atoms per cell handled
 constexpr int LDIM = 12;       // candidate cells per dimension
-constexpr int LCELLS = 320;     // candidate cells kept per cell
+constexpr int LCELLS = 320;    // candidate cells kept per cell
 constexpr int LEXCL = 8;       // exclusions per atom held in registers
 
-// One wavefront per cell.  (1) The candidate cells (cell gap below the search
-// radius) are enumerated by the lanes in ascending cell index, their atom
-// ranges fetched in parallel and compacted by ballots.  (2) Their atoms are
-// gathered, in ascending cell and id order, into a flat LDS batch.  (3) For
-// each atom i of the cell the 64 lanes test 64 consecutive candidates at a
-// time and a ballot appends the hits in candidate order, so every row comes
-// out in canonical order.
-__global__ void __launch_bounds__(256) k_lists(int32_t n_cells, const RepInfo *__restrict__ reps,
-                                               const int32_t *__restrict__ cell_rep, Topo tp,
-                                               ListSet ls, BuildSpec bs, DevState *st)
+// One workgroup per cell.  (1) Wavefront 0 enumerates the candidate cells
+// (cell gap below the search radius) in ascending cell index, fetching their
+// atom ranges in parallel and compacting them by ballots, and prefix-sums the
+// range sizes.  (2) The workgroup stages a batch of candidate atoms (slot,
+// FP64 position, caller id), in ascending cell and id order, in LDS.  (3) Each
+// wavefront takes every LB-th atom i of the cell; its 64 lanes test 64
+// consecutive staged candidates at a time and a ballot appends the hits in
+// candidate order, so every row comes out in canonical order.
+__global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInfo *__restrict__ reps,
+                                                   const int32_t *__restrict__ cell_rep, Topo tp,
+                                                   ListSet ls, BuildSpec bs, DevState *st)
 {
-    __shared__ int32_t cand[LW][LCAP];
-    __shared__ int32_t rowf[LW][LMAXI], rowc[LW][LMAXI];
-    __shared__ int32_t dcell[LW][3][LDIM];
-    __shared__ double dgap[LW][3][LDIM];
-    __shared__ int32_t cbeg[LW][LCELLS], cnum[LW][LCELLS], cpre[LW][LCELLS + 1];
-    __shared__ double4 ipos[LW][LMAXI];
-    __shared__ int32_t iex[LW][LMAXI][LEXCL], iexn[LW][LMAXI];
+    __shared__ double cx[LCAP], cy[LCAP], cz[LCAP];
+    __shared__ int32_t cj[LCAP], cg[LCAP];
+    __shared__ int32_t rowf[LMAXI], rowc[LMAXI];
+    __shared__ int32_t dcell[3][LDIM];
+    __shared__ double dgap[3][LDIM];
+    __shared__ int32_t cbeg[LCELLS], cnum[LCELLS], cpre[LCELLS + 1];
+    __shared__ double4 ipos[LMAXI];
+    __shared__ int32_t iex[LMAXI][LEXCL];
+    __shared__ int32_t s_ncells;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t ci = blockIdx.x * LW + w;
-    if (ci >= n_cells) return;                       // uniform per wavefront
+    const int32_t ci = blockIdx.x;
     const int32_t bi = ls.cell_start[ci], ei_all = ls.cell_start[ci + 1];
-    const int32_t ei = min(ei_all, bi + LMAXI);
-    bool overflow = ei_all > ei;
-    for (int32_t i = ei + lane; i < ei_all; i += 64) {   // atoms beyond the per-cell limit
+    const int32_t ei = min(ei_all, bi + LMAXI), ni = ei - bi;
+    for (int32_t i = ei + threadIdx.x; i < ei_all; i += 64 * LB) {   // atoms beyond the limit
         ls.fcnt[i] = 0;
         ls.ccnt[i] = 0;
     }
-    if (bi == ei) return;                            // uniform per wavefront
+    if (ni == 0) return;                             // uniform per workgroup
     const RepInfo &ri = reps[cell_rep[ci]];
-    const int32_t par = bs.mirror_sel >= 0 ? bs.mirror_sel : (int32_t)(st->step & 1);
+    const BoxReg box(ri);
+    const int32_t par = bs.mirror_sel >= 0 ? bs.mirror_sel : (int32_t)((st->step + bs.step_off) & 1);
     const double4 *__restrict__ X = ls.x[par];
-    const int32_t loc = ci - ri.cell_off;
-    const int32_t cc[3] = {loc / (ri.ncell[1] * ri.ncell[2]), (loc / ri.ncell[2]) % ri.ncell[1],
-                           loc % ri.ncell[2]};
-    const double R = bs.rsearch * (1.0 + 1e-12) + 1e-9;
-    const double R2 = R * R;
     const double rmax2 = fmax(bs.want_force ? bs.rf2 : 0.0, bs.want_cand ? bs.rcmax2 : 0.0);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int32_t k = lane; k < ei - bi; k += 64) rowf[w][k] = rowc[w][k] = 0;
-    // (1a) candidate cell indices per dimension, ascending
-    int32_t nd[3];
-    for (int d = 0; d < 3; ++d) {
-        int32_t cnt = 0;
-        for (int32_t j0 = 0; j0 < ri.ncell[d]; j0 += 64) {
-            const int32_t j = j0 + lane;
-            double gp = 0.0;
-            bool ok = false;
-            if (j < ri.ncell[d]) {
-                gp = cell_gap(cc[d], j, ri.ncell[d], ri.cw[d], ri.periodic);
-                ok = gp < R;
-            }
-            const uint64_t m = __ballot(ok);
-            const int32_t k = cnt + __popcll(m & below);
-            if (ok && k < LDIM) {
-                dcell[w][d][k] = j;
-                dgap[w][d][k] = gp * gp;
-            }
-            cnt += __popcll(m);
-        }
-        if (cnt > LDIM) overflow = true;
-        nd[d] = min(cnt, LDIM);
-    }
-    wave_sync();
-    // (1b) candidate cells in ascending index with their atom ranges
-    const int32_t ntrip = nd[0] * nd[1] * nd[2];
-    int32_t ncells = 0;
-    for (int32_t t0 = 0; t0 < ntrip; t0 += 64) {
-        const int32_t t = t0 + lane;
-        bool ok = false;
-        int32_t jb = 0, jn = 0;
-        if (t < ntrip) {
-            const int32_t a = t / (nd[1] * nd[2]), b = (t / nd[2]) % nd[1], c = t % nd[2];
-            if (dgap[w][0][a] + dgap[w][1][b] + dgap[w][2][c] < R2) {
-                const int32_t cj = ri.cell_off +
-                                   (dcell[w][0][a] * ri.ncell[1] + dcell[w][1][b]) * ri.ncell[2] +
-                                   dcell[w][2][c];
-                jb = ls.cell_start[cj];
-                jn = ls.cell_start[cj + 1] - jb;
-                ok = jn > 0;
-            }
-        }
-        const uint64_t m = __ballot(ok);
-        const int32_t k = ncells + __popcll(m & below);
-        if (ok && k < LCELLS) {
-            cbeg[w][k] = jb;
-            cnum[w][k] = jn;
-        }
-        ncells += __popcll(m);
-    }
-    if (ncells > LCELLS) overflow = true;
-    ncells = min(ncells, LCELLS);
-    wave_sync();
-    // prefix sum of the cell sizes (fixed order, wave scan in chunks of 64)
-    int32_t run = 0;
-    for (int32_t k0 = 0; k0 < ncells; k0 += 64) {
-        const int32_t k = k0 + lane;
-        const int32_t v = k < ncells ? cnum[w][k] : 0;
-        int32_t incl = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (k < ncells) cpre[w][k] = run + incl - v;
-        run += __shfl(incl, 63, 64);
-    }
-    if (lane == 0) cpre[w][ncells] = run;
-    // the cell's own atoms: positions, ids and exclusions, loaded once
-    for (int32_t k = lane; k < ei - bi; k += 64) {
+    bool overflow = ei_all > ei;
+    for (int32_t k = threadIdx.x; k < ni; k += 64 * LB) {
+        rowf[k] = rowc[k] = 0;
+        // the cell's own atoms: positions and exclusions
         const double4 x = X[bi + k];
-        ipos[w][k] = x;
+        ipos[k] = x;
         const int32_t g = mirror_id(x.w);
         const int32_t e_b = tp.excl_ptr[g], e_n = tp.excl_ptr[g + 1] - e_b;
-        iexn[w][k] = min(e_n, LEXCL);
-        for (int32_t t = 0; t < LEXCL; ++t) iex[w][k][t] = t < e_n ? tp.excl_idx[e_b + t] : -1;
+        for (int32_t t = 0; t < LEXCL; ++t) iex[k][t] = t < e_n ? tp.excl_idx[e_b + t] : -1;
         if (e_n > LEXCL) overflow = true;
     }
-    wave_sync();
-    const int32_t total = cpre[w][ncells];
+    if (w == 0) {
+        const int32_t loc = ci - ri.cell_off;
+        const int32_t cc[3] = {loc / (ri.ncell[1] * ri.ncell[2]), (loc / ri.ncell[2]) % ri.ncell[1],
+                               loc % ri.ncell[2]};
+        const double R = bs.rsearch * (1.0 + 1e-12) + 1e-9;
+        const double R2 = R * R;
+        // (1a) candidate cell indices per dimension, ascending
+        int32_t nd[3];
+        for (int d = 0; d < 3; ++d) {
+            int32_t cnt = 0;
+            for (int32_t j0 = 0; j0 < ri.ncell[d]; j0 += 64) {
+                const int32_t j = j0 + lane;
+                double gp = 0.0;
+                bool ok = false;
+                if (j < ri.ncell[d]) {
+                    gp = cell_gap(cc[d], j, ri.ncell[d], ri.cw[d], ri.periodic);
+                    ok = gp < R;
+                }
+                const uint64_t m = __ballot(ok);
+                const int32_t k = cnt + __popcll(m & below);
+                if (ok && k < LDIM) {
+                    dcell[d][k] = j;
+                    dgap[d][k] = gp * gp;
+                }
+                cnt += __popcll(m);
+            }
+            if (cnt > LDIM) overflow = true;
+            nd[d] = min(cnt, LDIM);
+        }
+        wave_sync();
+        // (1b) candidate cells in ascending index with their atom ranges
+        const int32_t ntrip = nd[0] * nd[1] * nd[2];
+        int32_t ncells = 0;
+        for (int32_t t0 = 0; t0 < ntrip; t0 += 64) {
+            const int32_t t = t0 + lane;
+            bool ok = false;
+            int32_t jb = 0, jn = 0;
+            if (t < ntrip) {
+                const int32_t a = t / (nd[1] * nd[2]), b = (t / nd[2]) % nd[1], c = t % nd[2];
+                if (dgap[0][a] + dgap[1][b] + dgap[2][c] < R2) {
+                    const int32_t cjx = ri.cell_off +
+                                        (dcell[0][a] * ri.ncell[1] + dcell[1][b]) * ri.ncell[2] +
+                                        dcell[2][c];
+                    jb = ls.cell_start[cjx];
+                    jn = ls.cell_start[cjx + 1] - jb;
+                    ok = jn > 0;
+                }
+            }
+            const uint64_t m = __ballot(ok);
+            const int32_t k = ncells + __popcll(m & below);
+            if (ok && k < LCELLS) {
+                cbeg[k] = jb;
+                cnum[k] = jn;
+            }
+            ncells += __popcll(m);
+        }
+        if (ncells > LCELLS) overflow = true;
+        ncells = min(ncells, LCELLS);
+        wave_sync();
+        // prefix sum of the cell sizes (fixed order, wave scan in chunks of 64)
+        int32_t run = 0;
+        for (int32_t k0 = 0; k0 < ncells; k0 += 64) {
+            const int32_t k = k0 + lane;
+            const int32_t v = k < ncells ? cnum[k] : 0;
+            int32_t incl = v;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t o = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += o;
+            }
+            if (k < ncells) cpre[k] = run + incl - v;
+            run += __shfl(incl, 63, 64);
+        }
+        if (lane == 0) {
+            cpre[ncells] = run;
+            s_ncells = ncells;
+        }
+    }
+    __syncthreads();
+    const int32_t ncells = s_ncells;
+    const int32_t total = cpre[ncells];
 
     for (int32_t lo = 0; lo < total; lo += LCAP) {
         const int32_t nb = min(LCAP, total - lo);
-        // (2) gather candidates [lo, lo + nb) of the flat sequence
-        for (int32_t k = lane; k < ncells; k += 64) {
-            const int32_t p0 = cpre[w][k], jb = cbeg[w][k], jn = cnum[w][k];
+        // (2a) slots of candidates [lo, lo + nb) of the flat sequence
+        for (int32_t k = threadIdx.x; k < ncells; k += 64 * LB) {
+            const int32_t p0 = cpre[k], jb = cbeg[k], jn = cnum[k];
             const int32_t t_lo = max(0, lo - p0), t_hi = min(jn, lo + nb - p0);
-            for (int32_t t = t_lo; t < t_hi; ++t) cand[w][p0 + t - lo] = jb + t;
+            for (int32_t t = t_lo; t < t_hi; ++t) cj[p0 + t - lo] = jb + t;
         }
-        wave_sync();
-        // (3) test every atom of this cell against the batch
-        for (int32_t i = bi; i < ei; ++i) {
-            const double4 xi = ipos[w][i - bi];
+        __syncthreads();
+        // (2b) their positions and caller ids
+        for (int32_t f = threadIdx.x; f < nb; f += 64 * LB) {
+            const double4 x = X[cj[f]];
+            cx[f] = x.x;
+            cy[f] = x.y;
+            cz[f] = x.z;
+            cg[f] = mirror_id(x.w);
+        }
+        __syncthreads();
+        // (3) this wavefront's atoms of the cell against the batch
+        for (int32_t k = w; k < ni; k += LB) {
+            const int32_t i = bi + k;
+            const double4 xi = ipos[k];
             int32_t ex_id[LEXCL];
 #pragma unroll
-            for (int k = 0; k < LEXCL; ++k) ex_id[k] = iex[w][i - bi][k];
-            int32_t nf = rowf[w][i - bi], nc = rowc[w][i - bi];
+            for (int t = 0; t < LEXCL; ++t) ex_id[t] = iex[k][t];
+            int32_t nf = rowf[k], nc = rowc[k];
             int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
             int32_t *crow = ls.clist + (int64_t)i * ls.ccap;
-            constexpr int UF = 2;
-            for (int32_t f0 = 0; f0 < nb; f0 += 64 * UF) {
-                int32_t jj[UF];
-                double4 xj[UF];
+            for (int32_t f0 = 0; f0 < nb; f0 += 64) {
+                const int32_t f = f0 + lane;
+                bool hf = false, hc = false;
+                int32_t j = -1;
+                if (f < nb) {
+                    j = cj[f];
+                    double dx = xi.x - cx[f], dy = xi.y - cy[f], dz = xi.z - cz[f];
+                    box.apply(dx, dy, dz);
+                    const double r2 = norm2_exact(dx, dy, dz);
+                    if (j != i && r2 < rmax2) {
+                        const int32_t gj = cg[f];
+                        bool ex = false;
 #pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    const int32_t f = f0 + 64 * u + lane;
-                    jj[u] = f < nb ? cand[w][f] : -1;
-                }
-#pragma unroll
-                for (int u = 0; u < UF; ++u) xj[u] = X[jj[u] >= 0 ? jj[u] : i];
-#pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    bool hf = false, hc = false;
-                    const int32_t j = jj[u];
-                    if (j >= 0 && j != i) {
-                        double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
-                        min_image(ri, dx, dy, dz);
-                        const double r2 = norm2_exact(dx, dy, dz);
-                        if (r2 < rmax2) {
-                            const int32_t gj = mirror_id(xj[u].w);
-                            bool ex = false;
-#pragma unroll
-                            for (int k = 0; k < LEXCL; ++k) ex |= ex_id[k] == gj;
-                            if (!ex) {
-                                hf = bs.want_force && r2 < bs.rf2;
-                                hc = bs.want_cand && r2 < bs.rcmax2 &&
-                                     !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
-                            }
+                        for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == gj;
+                        if (!ex) {
+                            hf = bs.want_force && r2 < bs.rf2;
+                            hc = bs.want_cand && r2 < bs.rcmax2 && !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
                         }
                     }
-                    const uint64_t mf = __ballot(hf), mc = __ballot(hc);
-                    if (hf) {
-                        const int32_t k = nf + __popcll(mf & below);
-                        if (k < ls.fcap) frow[k] = j;
-                    }
-                    if (hc) {
-                        const int32_t k = nc + __popcll(mc & below);
-                        if (k < ls.ccap) crow[k] = j;
-                    }
-                    nf += __popcll(mf);
-                    nc += __popcll(mc);
                 }
+                const uint64_t mf = __ballot(hf), mc = __ballot(hc);
+                if (hf) {
+                    const int32_t q = nf + __popcll(mf & below);
+                    if (q < ls.fcap) frow[q] = j;
+                }
+                if (hc) {
+                    const int32_t q = nc + __popcll(mc & below);
+                    if (q < ls.ccap) crow[q] = j;
+                }
+                nf += __popcll(mf);
+                nc += __popcll(mc);
             }
             if (lane == 0) {
-                rowf[w][i - bi] = nf;
-                rowc[w][i - bi] = nc;
+                rowf[k] = nf;
+                rowc[k] = nc;
             }
         }
-        wave_sync();
+        __syncthreads();
     }
-    for (int32_t k = lane; k < ei - bi; k += 64) {
-        const int32_t nf = rowf[w][k], nc = rowc[w][k];
+    for (int32_t k = threadIdx.x; k < ni; k += 64 * LB) {
+        const int32_t nf = rowf[k], nc = rowc[k];
         if (bs.want_force) ls.fcnt[bi + k] = min(nf, ls.fcap);
         if (bs.want_cand) ls.ccnt[bi + k] = min(nc, ls.ccap);
-        overflow |= nf > ls.fcap || nc > ls.ccap;
+        if (nf > ls.fcap || nc > ls.ccap) overflow = true;
     }
-    if (overflow) atomicOr(&st->status, ST_CAPACITY);
+    if (__syncthreads_or(overflow) && threadIdx.x == 0) atomicOr(&st->status, ST_CAPACITY);
 }
 
 void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
@@ -352,9 +383,10 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
-                       pos, tp, ls, st, bs.mirror_sel);
-    hipLaunchKernelGGL(k_lists, dim3((ls.n_cells + LW - 1) / LW), dim3(64 * LW), 0, sm, ls.n_cells,
-                       reps, cell_rep, tp, ls, bs, st);
+                       pos, tp, ls, st, bs.mirror_sel, bs.step_off);
+    if (ls.bslot) hipLaunchKernelGGL(k_bslots, dim3(nb), dim3(256), 0, sm, n, tp, ls);
+    hipLaunchKernelGGL(k_lists, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps, cell_rep,
+                       tp, ls, bs, st);
 }
 
 }  // namespace bnc

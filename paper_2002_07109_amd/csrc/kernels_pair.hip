@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
     }
     int32_t gi = 0;
     if (valid) {
-        const int32_t par = a.mirror_sel >= 0 ? a.mirror_sel : (int32_t)(a.st->step & 1);
+        const int32_t par = a.mirror_sel >= 0 ? a.mirror_sel : (int32_t)((a.st->step + a.step_off) & 1);
         const double4 *__restrict__ X = a.ls.x[par];
         const double4 xi = X[s];
         const int ti = mirror_type(xi.w);

@@ -14,25 +14,11 @@
 namespace bnc {
 
 template <typename R>
-__device__ void init_pair_table(TypePair<R> *tab, const double *tpar, const PairGlobals &pg)
-{
-    const int nt = pg.n_types;
-    for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
-        int a = k / nt, b = k % nt;
-        double qq = KE * tpar[a] * tpar[b];
-        double eps = sqrt(tpar[nt + a] * tpar[nt + b]);
-        double sig = 0.5 * (tpar[2 * nt + a] + tpar[2 * nt + b]);
-        double rc = pg.r_cut, g, dg;
-        coul_g<double>(rc, 1.0 / rc, pg.alpha, pg.coulomb, g, dg);
-        double sr = sig / rc, s6 = sr * sr * sr * sr * sr * sr, s12 = s6 * s6;
-        double dul = eps != 0.0 ? 4.0 * eps * (-12.0 * s12 + 6.0 * s6) / rc : 0.0;
-        TypePair<R> t;
-        t.qq = (R)qq; t.eps4 = (R)(4.0 * eps); t.sig2 = (R)(sig * sig);
-        t.du_rc = (R)(qq * dg + dul); t.u_rc = (R)0;
-        t.pad[0] = t.pad[1] = t.pad[2] = (R)0;
-        tab[k] = t;
-    }
-}
+__device__ __forceinline__ const TypePair<R> *jump_table(const StepArgs &a);
+template <>
+__device__ __forceinline__ const TypePair<float> *jump_table<float>(const StepArgs &a) { return a.tab_f; }
+template <>
+__device__ __forceinline__ const TypePair<double> *jump_table<double>(const StepArgs &a) { return a.tab_d; }
 
 // long-range field F_ij = chi(r) W'_sf(r) d/r on i (zero outside r' < r < rc)
 template <typename R>
@@ -57,66 +43,114 @@ struct JumpTally {
     unsigned long long prop, acc, bound;
 };
 
-// the velocity chain of one atom over dt/2 at fixed positions
-// (U: the uniform of the atom's Poisson draw, counter (step, phase, lid, 0))
-template <typename R>
-__device__ void jump_atom(const StepArgs &a, const TypePair<R> *tab, const double4 *X, int32_t s,
-                          int32_t lid, int32_t rep, const RepInfo &ri, int ti, const double q[3],
-                          double v[3], int64_t step, int32_t phase, double U, JumpTally &tally)
+// Four lanes per atom ("group"), running the same code on different data.
+constexpr int LPA = 4;
+
+__device__ __forceinline__ int group_base() { return (int)(threadIdx.x & 63 & ~(LPA - 1)); }
+
+__device__ __forceinline__ double group_get(double v, int src)
 {
-    const int32_t c = min(a.ls.ccnt[s], a.ls.ccap);
-    const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    const double L = a.L_a[ti];
-    if (c == 0 || v0 == 0.0 || L == 0.0) return;
-    const double mu = (double)c * a.beta * v0 * L * a.half_dt;
-    int32_t M = 0;
-    double term = exp(-mu), cdf = term;
-    while (U > cdf) {
-        ++M;
-        if (M > a.max_proposals) {
-            atomicOr(&a.st->status, ST_POISSON);
-            return;
+    return __shfl(v, group_base() + src, 64);
+}
+
+__device__ __forceinline__ uint64_t group_get_u64(uint64_t v, int src)
+{
+    return (uint64_t)__shfl((long long)v, group_base() + src, 64);
+}
+
+__device__ __forceinline__ int32_t group_get_i32(int32_t v, int src)
+{
+    return __shfl(v, group_base() + src, 64);
+}
+
+// The velocity chain of one atom over dt/2 at fixed positions, run by the
+// atom's LPA lanes together.  Positions do not move during J, so the fields of
+// all proposals are independent of the chain: lane t of the group draws and
+// evaluates proposals k = k0 + t of a batch in parallel, then every lane walks
+// the batch in order k = k0, k0+1, ... applying the accept test and reflection
+// (same FP64 arithmetic on every lane, so the lanes keep identical v).
+// U: the uniform of the atom's Poisson draw, counter (step, phase, lid, 0).
+// Every lane of the wavefront must call this (active = false for padding).
+template <typename R>
+__device__ void jump_group(const StepArgs &a, const TypePair<R> *tab, const double4 *X, bool active,
+                           int32_t s, int32_t lid, int32_t rep, const RepInfo &ri, int ti,
+                           const double q[3], double v[3], int64_t step, int32_t phase, double U,
+                           int sub, JumpTally &tally)
+{
+    int32_t M = 0, c = 0;
+    double v0 = 0.0, L = 0.0;
+    if (active) {
+        c = min(a.ls.ccnt[s], a.ls.ccap);
+        v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        L = a.L_a[ti];
+        if (c > 0 && v0 != 0.0 && L != 0.0) {
+            const double mu = (double)c * a.beta * v0 * L * a.half_dt;
+            double term = exp(-mu), cdf = term;
+            while (U > cdf) {
+                ++M;
+                if (M > a.max_proposals) break;
+                term *= mu / (double)M;
+                cdf += term;
+            }
+            if (M > a.max_proposals) {
+                if (sub == 0) atomicOr(&a.st->status, ST_POISSON);
+                M = 0;
+            }
         }
-        term *= mu / (double)M;
-        cdf += term;
     }
     const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
     const int nt = a.pg.n_types;
-    for (int32_t k = 1; k <= M; ++k) {
-        const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
-        const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
-        const int32_t p = crow[J];
-        const double u = u01(w.y);
-        const double4 xj = X[p];
-        double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
-        BoxReg(ri).apply(dx, dy, dz);
-        double F[3];
-        long_field<R>(tab[ti * nt + mirror_type(xj.w)], a.pg, dx, dy, dz, F);
-        const double sdot = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
-        // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
-        const int acc = (u * v0 * L) < sdot;
-        if (sdot > v0 * L * (1.0 + 1e-9)) {
-            tally.bound++;
-            atomicOr(&a.st->status, ST_BOUND);
+    for (int32_t k0 = 1; __any(k0 <= M); k0 += LPA) {
+        // this lane's proposal of the batch
+        const int32_t k = k0 + sub;
+        double F[3] = {0.0, 0.0, 0.0}, u = 1.0;
+        int32_t p = 0;
+        if (k <= M) {
+            const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
+            const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
+            p = crow[J];
+            u = u01(w.y);
+            const double4 xj = X[p];
+            double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
+            BoxReg(ri).apply(dx, dy, dz);
+            long_field<R>(tab[ti * nt + mirror_type(xj.w)], a.pg, dx, dy, dz, F);
         }
-        if (acc) {
-            const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-            const double cf = 2.0 * sdot / f2;
-            v[0] = v[0] - cf * F[0];
-            v[1] = v[1] - cf * F[1];
-            v[2] = v[2] - cf * F[2];
-            tally.acc++;
-        }
-        tally.prop++;
-        if (a.log_events) {
-            const unsigned long long slot =
-                atomicAdd((unsigned long long *)&a.st->n_events, 1ull);
-            if ((int64_t)slot < a.event_cap) {
-                Event ev;
-                ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k;
-                ev.partner = a.ls.perm[p] - (int32_t)ri.atom_off;
-                ev.accepted = acc; ev.replica = rep;
-                a.events[slot] = ev;
+        // the chain, in order
+#pragma unroll
+        for (int t = 0; t < LPA; ++t) {
+            const double Fx = group_get(F[0], t), Fy = group_get(F[1], t), Fz = group_get(F[2], t);
+            const double ut = group_get(u, t);
+            const int32_t pt = group_get_i32(p, t);
+            if (k0 + t <= M) {
+                const double sdot = v[0] * Fx + v[1] * Fy + v[2] * Fz;
+                // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
+                const int acc = (ut * v0 * L) < sdot;
+                if (acc) {
+                    const double f2 = Fx * Fx + Fy * Fy + Fz * Fz;
+                    const double cf = 2.0 * sdot / f2;
+                    v[0] = v[0] - cf * Fx;
+                    v[1] = v[1] - cf * Fy;
+                    v[2] = v[2] - cf * Fz;
+                }
+                if (sub == 0) {
+                    if (sdot > v0 * L * (1.0 + 1e-9)) {
+                        tally.bound++;
+                        atomicOr(&a.st->status, ST_BOUND);
+                    }
+                    tally.acc += acc;
+                    tally.prop++;
+                    if (a.log_events) {
+                        const unsigned long long slot =
+                            atomicAdd((unsigned long long *)&a.st->n_events, 1ull);
+                        if ((int64_t)slot < a.event_cap) {
+                            Event ev;
+                            ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k0 + t;
+                            ev.partner = a.ls.perm[pt] - (int32_t)ri.atom_off;
+                            ev.accepted = acc; ev.replica = rep;
+                            a.events[slot] = ev;
+                        }
+                    }
+                }
             }
         }
     }
@@ -131,50 +165,40 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t)
 {
+    // this wavefront's copy of the counters
+    const int32_t copy = (int32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (CNT_SPREAD - 1));
     const int32_t first = __shfl(rep, 0, 64);
     const bool uniform = __all(!active || rep == first);
     if (uniform) {
         unsigned long long p = wave_sum(active ? t.prop : 0), c = wave_sum(active ? t.acc : 0),
                            b = wave_sum(active ? t.bound : 0);
         if ((threadIdx.x & 63) == 0 && (p | c | b)) {
-            atomicAdd(&a.cnt[first].proposals, p);
-            atomicAdd(&a.cnt[first].accepted, c);
-            if (b) atomicAdd(&a.cnt[first].bound_violations, b);
+            RepCounters &rc = a.cnt[first * CNT_SPREAD + copy];
+            atomicAdd(&rc.proposals, p);
+            atomicAdd(&rc.accepted, c);
+            if (b) atomicAdd(&rc.bound_violations, b);
         }
     } else if (active && (t.prop | t.acc | t.bound)) {
-        atomicAdd(&a.cnt[rep].proposals, t.prop);
-        atomicAdd(&a.cnt[rep].accepted, t.acc);
-        if (t.bound) atomicAdd(&a.cnt[rep].bound_violations, t.bound);
+        RepCounters &rc = a.cnt[rep * CNT_SPREAD + copy];
+        atomicAdd(&rc.proposals, t.prop);
+        atomicAdd(&rc.accepted, t.acc);
+        if (t.bound) atomicAdd(&rc.bound_violations, t.bound);
     }
 }
 
-// Four lanes per atom, running the same code on different data: each lane
-// draws one Philox block (lane 0: the O step, lane 1: the Poisson uniform of
-// J(n-1, JB), lane 2: that of J(n, JA)), lanes 0-2 turn the O block into the
-// three Box-Muller normals, and the lanes share the atom's bonded terms; lane 0
-// then runs the atom's sequential chain (kicks, jump chains, drifts, O step).
-constexpr int LPA = 4;
-
-__device__ __forceinline__ double group_get(double v, int src)
-{
-    return __shfl(v, (int)(threadIdx.x & 63 & ~(LPA - 1)) + src, 64);
-}
-
-__device__ __forceinline__ uint64_t group_get_u64(uint64_t v, int src)
-{
-    return (uint64_t)__shfl((long long)v, (int)(threadIdx.x & 63 & ~(LPA - 1)) + src, 64);
-}
-
+// Each lane of an atom's group draws one Philox block (lane 0: the O step,
+// lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA)), lanes
+// 0-2 turn the O block into the three Box-Muller normals and the lanes share
+// the atom's bonded terms; then the group runs the atom's chain (kicks, jump
+// chains, drifts, O step) together and lane 0 writes the results.
 template <typename R, bool BOUNCE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
-    __shared__ TypePair<R> tab[MAXT * MAXT];
-    if (BOUNCE) init_pair_table<R>(tab, a.type_params, a.pg);
-    __syncthreads();
+    const TypePair<R> *tab = jump_table<R>(a);
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t s = t / LPA, sub = t % LPA;
     const bool active = s < a.n;
-    const int64_t n = a.st->step;
+    const int64_t n = a.st->step + a.step_off;
     const int32_t par = (int32_t)(n & 1);
     const double4 *__restrict__ X = a.ls.x[par];
     double4 *__restrict__ Y = a.ls.x[par ^ 1];
@@ -194,8 +218,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
         w = draw(ri, dstep, dphase, lid, 0);
         // bonded terms shared by the lanes
-        for (int32_t k = a.tp.bt_ptr[g] + sub; k < a.tp.bt_ptr[g + 1]; k += LPA)
-            bonded_term_grad(g, a.tp.bt[k], MirrorPos{X, a.ls.inv_perm}, ri, a.tp, fb);
+        const int4 *brow = a.ls.bslot + (int64_t)s * BTMAX;
+        for (int k = sub; k < BTMAX; k += LPA) {
+            const int4 e = brow[k];
+            if (e.x < 0) break;
+            bonded_slot_grad(s, e, X, ri, a.tp, fb);
+        }
     }
     // Box-Muller on the O block: lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
     const uint64_t ow0 = group_get_u64(w.x, 0), ow1 = group_get_u64(w.y, 0);
@@ -218,21 +246,33 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         B2 += __shfl_xor(B2, m, LPA);
     }
 
+    // the atom's chain, on every lane of the group
+    const RepInfo &ri = a.reps[rep];
+    const int ti = mirror_type(xi.w);
+    double q[3] = {xi.x, xi.y, xi.z};
+    double F[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    double km = 0.0;
+    if (active) {
+        F[0] = a.fpair[3 * (int64_t)s] + B0;
+        F[1] = a.fpair[3 * (int64_t)s + 1] + B1;
+        F[2] = a.fpair[3 * (int64_t)s + 2] + B2;
+        v[0] = a.vel[3 * (int64_t)g];
+        v[1] = a.vel[3 * (int64_t)g + 1];
+        v[2] = a.vel[3 * (int64_t)g + 2];
+        km = a.half_dt * a.tp.acc_m[g];
+    }
+    if (a.do_close) {
+        if (BOUNCE)
+            jump_group<R>(a, tab, X, active, s, lid, rep, ri, ti, q, v, n - 1, 2, U_jb, sub, tally);
+        v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
+    }
+    if (a.do_open) {
+        v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
+        if (BOUNCE)
+            jump_group<R>(a, tab, X, active, s, lid, rep, ri, ti, q, v, n, 0, U_ja, sub, tally);
+    }
     if (active && sub == 0) {
-        const RepInfo &ri = a.reps[rep];
-        const int ti = mirror_type(xi.w);
-        double q[3] = {xi.x, xi.y, xi.z};
-        const double F[3] = {a.fpair[3 * (int64_t)s] + B0, a.fpair[3 * (int64_t)s + 1] + B1,
-                             a.fpair[3 * (int64_t)s + 2] + B2};
-        double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
-        const double km = a.half_dt * a.tp.acc_m[g];
-        if (a.do_close) {
-            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n - 1, 2, U_jb, tally);
-            v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
-        }
         if (a.do_open) {
-            v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
-            if (BOUNCE) jump_atom<R>(a, tab, X, s, lid, rep, ri, ti, q, v, n, 0, U_ja, tally);
             for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
             const double c2 = a.ou_c2[g];
             v[0] = a.c1 * v[0] + c2 * G0;
@@ -255,19 +295,15 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         if (!fin) atomicOr(&a.st->status, ST_NONFINITE);
     }
     if (BOUNCE) flush_tally(a, rep, active && sub == 0, tally);
-    if (a.do_open) {
-        // the last block to finish advances the device step counter
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const unsigned int done = atomicAdd(&a.st->done_blocks, 1u);
-            if (done == gridDim.x - 1) {
-                a.st->done_blocks = 0;
-                a.st->step = n + 1;
-                __threadfence();
-            }
-        }
-    }
+}
+
+// the device step counter moves once per batch of launched steps, in a kernel
+// of its own: kernels of one stream see it in launch order, with no fences
+__global__ void k_advance(DevState *st, int32_t count) { st->step += count; }
+
+void launch_advance(hipStream_t sm, DevState *st, int32_t count)
+{
+    if (count > 0) hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, sm, st, count);
 }
 
 void launch_step(hipStream_t sm, const StepArgs &a)
@@ -287,36 +323,43 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
 {
     const StepArgs &a = ja.s;
-    __shared__ TypePair<R> tab[MAXT * MAXT];
-    init_pair_table<R>(tab, a.type_params, a.pg);
-    __syncthreads();
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const TypePair<R> *tab = jump_table<R>(a);
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = t / LPA, sub = t % LPA;
     const bool active = s < a.n;
-    const int32_t par = (int32_t)(a.st->step & 1);
+    const int32_t par = (int32_t)((a.st->step + a.step_off) & 1);
     const double4 *X = a.ls.x[par];
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0;
+    int32_t rep = 0, g = 0, lid = 0;
+    double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    double v[3] = {0.0, 0.0, 0.0};
+    double U = 0.0;
     if (active) {
-        const int32_t g = a.ls.perm[s];
+        g = a.ls.perm[s];
         rep = a.tp.rep_of[g];
-        const RepInfo &ri = a.reps[rep];
-        const double4 xi = X[s];
-        double q[3] = {xi.x, xi.y, xi.z};
-        double v[3] = {a.vel[3 * (int64_t)g], a.vel[3 * (int64_t)g + 1], a.vel[3 * (int64_t)g + 2]};
-        const int32_t lid = g - (int32_t)ri.atom_off;
-        jump_atom<R>(a, tab, X, s, lid, rep, ri, mirror_type(xi.w), q, v, ja.step, ja.phase,
-                     u01(draw(ri, ja.step, ja.phase, lid, 0).x), tally);
+        lid = g - (int32_t)a.reps[rep].atom_off;
+        xi = X[s];
+        v[0] = a.vel[3 * (int64_t)g];
+        v[1] = a.vel[3 * (int64_t)g + 1];
+        v[2] = a.vel[3 * (int64_t)g + 2];
+        U = u01(draw(a.reps[rep], ja.step, ja.phase, lid, 0).x);
+    }
+    const RepInfo &ri = a.reps[rep];
+    const double q[3] = {xi.x, xi.y, xi.z};
+    jump_group<R>(a, tab, X, active, s, lid, rep, ri, mirror_type(xi.w), q, v, ja.step, ja.phase, U,
+                  sub, tally);
+    if (active && sub == 0) {
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];
         a.vel[3 * (int64_t)g + 2] = v[2];
     }
-    flush_tally(a, rep, active, tally);
+    flush_tally(a, rep, active && sub == 0, tally);
 }
 
 void launch_jump(hipStream_t sm, const JumpArgs &a)
 {
     if (a.s.n <= 0) return;
-    dim3 grid((a.s.n + 255) / 256), block(256);
+    dim3 grid(((int64_t)a.s.n * LPA + 255) / 256), block(256);
     if (a.s.pair_fp64) hipLaunchKernelGGL((k_jump<double>), grid, block, 0, sm, a);
     else hipLaunchKernelGGL((k_jump<float>), grid, block, 0, sm, a);
 }
