@@ -183,11 +183,15 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
                                        const double *params_dev, const double *grad_out_dev,
                                        double *grad_pos_dev, double *grad_params_dev);
 
-/* Kernel timing for measurement: enqueue reps back-to-back launches of one
-   kernel of the step exactly as bounce_step launches it (which = 0: the F_0
-   pair kernel at the current positions; which = 1: the list build) between two
-   HIP events on the bound stream and return the mean duration in ms.  Leaves
-   the trajectory unchanged.  Synchronous. */
+/* Kernel timing for measurement, with HIP events on the bound stream; returns
+   the mean duration per launch in ms.  Synchronous.
+     which = 0: the standalone F_0 pair kernel at the current positions,
+     which = 1: the list build,
+     which = 2: the integrator kernel with its kicks, jumps and drifts off
+                (bonded terms and random draws; velocities rewritten unchanged),
+   each as reps back-to-back launches that leave the trajectory unchanged;
+     which = 3: the integrator kernel of reps real steps (advances the
+                trajectory by reps + 1 steps; only that kernel is timed). */
 bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);
 
 /* Autotuner: time the F_0 pair kernel (reps launches each) with 4, 8, 16 and 32

@@ -386,7 +386,7 @@ struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep;
-    size_t ls[2][13];
+    size_t ls[2][14];
 };
 
 static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
@@ -437,6 +437,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[10] = L.take(4 * n * fcap);              // flist
         q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
+        q[13] = L.take(sizeof(int2) * n);                               // sinfo
     }
 }
 
@@ -548,6 +549,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
         ls.ccnt = at<int32_t>(ws, q[11]);
         ls.clist = at<int32_t>(ws, q[11]) + c->n;
         ls.bslot = k == 0 ? at<int4>(ws, q[12]) : nullptr;
+        ls.sinfo = at<int2>(ws, q[13]);
         ls.fcap = k == 0 ? c->fcap : c->acap;
         ls.ccap = k == 0 ? c->ccap : 0;
         ls.n_cells = c->n_cells;
@@ -674,6 +676,8 @@ static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
     a.ls = ls;
     a.st = c->d_st;
     a.type_params = c->d_tparams;
+    a.tab_f = c->d_tab_f;
+    a.tab_d = c->d_tab_d;
     a.pg = pair_globals(c);
     return a;
 }
@@ -725,7 +729,9 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
 
 // one substep of the fused schedule at the current step index c->step
 // (= device counter + c->pending once the launches before it have run)
-static void enqueue_substep(bounce_ctx *c, int close, int open)
+// (e0, e1: optional events recorded around the integrator kernel alone)
+static void enqueue_substep(bounce_ctx *c, int close, int open, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr)
 {
     if (c->built_step < 0 || (c->step % c->p.rebuild_interval == 0 && c->built_step != c->step)) {
         enqueue_build(c, c->pending);
@@ -733,7 +739,9 @@ static void enqueue_substep(bounce_ctx *c, int close, int open)
         c->host_rebuilds++;
     }
     enqueue_force(c, c->pending);
+    if (e0) (void)hipEventRecord(e0, c->stream);
     launch_step(c->stream, step_args(c, close, open, c->pending));
+    if (e1) (void)hipEventRecord(e1, c->stream);
     if (open) {
         c->step++;
         c->pending++;
@@ -996,6 +1004,8 @@ bounce_status bounce_direct_energy(bounce_ctx *c, const double *pos, const doubl
     launch_build(sm, c->n, pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
     PairArgs a = pair_args(c, c->aux, 0);
     a.type_params = params;
+    a.tab_f = nullptr;
+    a.tab_d = nullptr;
     a.atom_out = c->d_atom;
     a.energy_total = 1;
     launch_pair(sm, MODE_ENERGY, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
@@ -1015,6 +1025,8 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *c, const double *pos, const d
     launch_build(sm, c->n, pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
     PairArgs a = pair_args(c, c->aux, 0);
     a.type_params = params;
+    a.tab_f = nullptr;
+    a.tab_d = nullptr;
     a.out = grad_pos;
     a.out_global = 1;
     a.accumulate = 0;
@@ -1030,11 +1042,31 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
 {
     bounce_status s = ready(c);
     if (s) return s;
-    if (!avg_ms || reps < 1 || (which != 0 && which != 1)) return BOUNCE_E_ARG;
+    if (!avg_ms || reps < 1 || which < 0 || which > 3) return BOUNCE_E_ARG;
     if (c->built_step < 0) {
         enqueue_build(c, 0);
         c->built_step = c->step;
         c->host_rebuilds++;
+    }
+    if (which == 3) {
+        // reps real steps; only the integrator kernels are timed
+        std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+        for (hipEvent_t &e : ev) HIPCHK(c, hipEventCreate(&e));
+        enqueue_substep(c, 0, 1);
+        for (int32_t k = 0; k < reps; ++k) enqueue_substep(c, 1, 1, ev[2 * k], ev[2 * k + 1]);
+        enqueue_substep(c, 1, 0);
+        flush_pending(c);
+        c->host_steps += reps + 1;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double tot = 0.0;
+        for (int32_t k = 0; k < reps; ++k) {
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+            tot += ms;
+        }
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        *avg_ms = tot / reps;
+        return bounce_sync(c);
     }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1042,7 +1074,8 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int32_t k = 0; k < reps; ++k) {
         if (which == 0) enqueue_force(c, 0);
-        else enqueue_build(c, 0);
+        else if (which == 1) enqueue_build(c, 0);
+        else launch_step(c->stream, step_args(c, 0, 0, 0));   // no kicks, jumps or drifts
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));

@@ -15,6 +15,8 @@ struct PairArgs {
     ListSet ls;
     const DevState *st;
     const double *type_params;    // [3][n_types]: charge, eps, sigma
+    const TypePair<float> *tab_f; // force modes: precomputed pair constants of type_params
+    const TypePair<double> *tab_d;//   (NULL: computed in the kernel)
     PairGlobals pg;
     double *out;                  // gradient [N][3]
     int32_t out_global;           // 1: caller order, 0: sorted order

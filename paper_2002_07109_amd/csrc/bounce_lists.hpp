@@ -11,6 +11,7 @@ struct ListSet {
     int32_t *slot;        // caller id -> arrival slot in its cell
     int32_t *cell_count;  // [n_cells]
     int32_t *cell_start;  // [n_cells + 1]
+    int2 *sinfo;          // sorted position -> (caller id, replica)
     double4 *x[2];        // sorted positions (x, y, z, type), double-buffered by step parity
     double *q_build;      // [N][3] positions at the build (skin guard)
     int32_t *fcnt;        // force list: row length per sorted atom

@@ -1,0 +1,79 @@
+// The pair-force sum of one atom over its list row, walked by a group of G
+// lanes (lane lig takes entries lig, lig + G, ...).
+//
+// MODE_SHORT: (1 - chi(r)) W'_sf(r) d/r for r < r''  (F_0 pair part, Sec. IV.A)
+// MODE_FULL:  W'_sf(r) d/r for r < rc                 (BAOAB)
+// MODE_LONG:  chi(r) W'_sf(r) d/r for r' < r < rc     (the jump fields, summed)
+//
+// The displacement is formed and minimum-imaged in FP64 and rounded to R; the
+// pair field is evaluated in R; each block of U entries is summed in R and
+// added to FP64 accumulators.  The caller combines the G partial sums.
+#pragma once
+#include "bounce_kernels.hpp"
+
+namespace bnc {
+
+template <typename R, int MODE, int G>
+__device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, const double4 &xi,
+                                               const BoxReg &box, const int32_t *__restrict__ row,
+                                               int32_t cnt, int lig, int32_t self,
+                                               const TypePair<R> *tab_i, const PairGlobals &pg,
+                                               double &ax, double &ay, double &az)
+{
+    const R alpha = (R)pg.alpha, r_on = (R)pg.r_on, inv_w = (R)pg.inv_w;
+    const R lim = MODE == MODE_SHORT ? (R)pg.r_off : (R)pg.r_cut;
+    const R lim2 = lim * lim;
+    // U entries per lane in flight: their index and position loads are issued
+    // together, which hides the gather latency
+    constexpr int U = 4;
+    for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
+        int32_t pj[U];
+        double4 xj[U];
+        R px = (R)0, py = (R)0, pz = (R)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + u * G;
+            pj[u] = e < cnt ? row[e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = X[pj[u] >= 0 ? pj[u] : self];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // every loaded position is used (an empty slot gets r2 = lim2), so
+            // the U gathers stay in flight together
+            double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y, dz = xi.z - xj[u].z;
+            box.apply(dx, dy, dz);
+            const R rx = (R)dx, ry = (R)dy, rz = (R)dz;
+            const R r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
+            if (!(r2 < lim2)) continue;
+            const TypePair<R> &tp = tab_i[mirror_type(xj[u].w)];
+            R r, rinv;
+            const R dw = pair_dw<R>(r2, tp, alpha, pg.coulomb, r, rinv);
+            R f;
+            if (MODE == MODE_SHORT) {
+                f = ((R)1 - switch_chi<R>(r, r_on, inv_w)) * dw * rinv;
+            } else if (MODE == MODE_LONG) {
+                f = r > r_on ? switch_chi<R>(r, r_on, inv_w) * dw * rinv : (R)0;
+            } else {
+                f = dw * rinv;
+            }
+            px += f * rx;
+            py += f * ry;
+            pz += f * rz;
+        }
+        ax += (double)px;
+        ay += (double)py;
+        az += (double)pz;
+    }
+}
+
+// sum over the G lanes of a group (fixed butterfly: deterministic)
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+    return v;
+}
+
+}  // namespace bnc

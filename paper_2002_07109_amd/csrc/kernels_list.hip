@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double 
     for (int32_t i = b + lane; i < e; i += 64) {
         const int32_t g = p[i];
         ls.inv_perm[g] = i;
+        ls.sinfo[i] = make_int2(g, tp.rep_of[g]);
         const double *x = pos + 3 * (int64_t)g;
         X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
     }
@@ -245,31 +246,39 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             nd[d] = min(cnt, LDIM);
         }
         wave_sync();
-        // (1b) candidate cells in ascending index with their atom ranges
+        // (1b) candidate cells in ascending index with their atom ranges: each
+        // lane takes TPL triples per pass, so their range loads are in flight together
         const int32_t ntrip = nd[0] * nd[1] * nd[2];
         int32_t ncells = 0;
-        for (int32_t t0 = 0; t0 < ntrip; t0 += 64) {
-            const int32_t t = t0 + lane;
-            bool ok = false;
-            int32_t jb = 0, jn = 0;
-            if (t < ntrip) {
-                const int32_t a = t / (nd[1] * nd[2]), b = (t / nd[2]) % nd[1], c = t % nd[2];
-                if (dgap[0][a] + dgap[1][b] + dgap[2][c] < R2) {
-                    const int32_t cjx = ri.cell_off +
-                                        (dcell[0][a] * ri.ncell[1] + dcell[1][b]) * ri.ncell[2] +
-                                        dcell[2][c];
-                    jb = ls.cell_start[cjx];
-                    jn = ls.cell_start[cjx + 1] - jb;
-                    ok = jn > 0;
+        constexpr int TPL = 6;
+        for (int32_t t0 = 0; t0 < ntrip; t0 += 64 * TPL) {
+            int32_t jb[TPL], je[TPL];
+#pragma unroll
+            for (int u = 0; u < TPL; ++u) {
+                const int32_t t = t0 + 64 * u + lane;
+                jb[u] = je[u] = 0;
+                if (t < ntrip) {
+                    const int32_t a = t / (nd[1] * nd[2]), b = (t / nd[2]) % nd[1], c = t % nd[2];
+                    if (dgap[0][a] + dgap[1][b] + dgap[2][c] < R2) {
+                        const int32_t cjx = ri.cell_off +
+                                            (dcell[0][a] * ri.ncell[1] + dcell[1][b]) * ri.ncell[2] +
+                                            dcell[2][c];
+                        jb[u] = ls.cell_start[cjx];
+                        je[u] = ls.cell_start[cjx + 1];
+                    }
                 }
             }
-            const uint64_t m = __ballot(ok);
-            const int32_t k = ncells + __popcll(m & below);
-            if (ok && k < LCELLS) {
-                cbeg[k] = jb;
-                cnum[k] = jn;
+#pragma unroll
+            for (int u = 0; u < TPL; ++u) {
+                const bool ok = je[u] > jb[u];
+                const uint64_t m = __ballot(ok);
+                const int32_t k = ncells + __popcll(m & below);
+                if (ok && k < LCELLS) {
+                    cbeg[k] = jb[u];
+                    cnum[k] = je[u] - jb[u];
+                }
+                ncells += __popcll(m);
             }
-            ncells += __popcll(m);
         }
         if (ncells > LCELLS) overflow = true;
         ncells = min(ncells, LCELLS);

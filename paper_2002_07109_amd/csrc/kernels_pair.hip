@@ -10,6 +10,7 @@
 // run-to-run deterministic.
 #include "bounce_kernels.hpp"
 #include "bounce_bonded.hpp"
+#include "bounce_pairrow.hpp"
 
 namespace bnc {
 
@@ -67,13 +68,12 @@ __device__ void init_tables(TypePair<R> *tab, TypePair<double> *tabc, DbwdConst<
     }
 }
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v)
-{
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
-    return v;
-}
+template <typename R>
+__device__ __forceinline__ const TypePair<R> *pair_table(const PairArgs &a);
+template <>
+__device__ __forceinline__ const TypePair<float> *pair_table<float>(const PairArgs &a) { return a.tab_f; }
+template <>
+__device__ __forceinline__ const TypePair<double> *pair_table<double>(const PairArgs &a) { return a.tab_d; }
 
 // G lanes per atom (4, 8, 16 or 32; chosen by the autotuner)
 template <typename R, int MODE, int G>
@@ -83,8 +83,13 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
     __shared__ TypePair<double> tabc[MAXT * MAXT];
     __shared__ DbwdConst<double> tabd[MAXT * MAXT];
     __shared__ double gconst[2];
-    init_tables<R>(tab, MODE == MODE_ENERGY ? tabc : nullptr, MODE == MODE_DBWD ? tabd : nullptr,
-                   a.type_params, a.pg);
+    const TypePair<R> *pre = pair_table<R>(a);
+    if ((MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) && pre) {
+        for (int k = threadIdx.x; k < a.pg.n_types * a.pg.n_types; k += blockDim.x) tab[k] = pre[k];
+    } else {
+        init_tables<R>(tab, MODE == MODE_ENERGY ? tabc : nullptr, MODE == MODE_DBWD ? tabd : nullptr,
+                       a.type_params, a.pg);
+    }
     if (MODE == MODE_DBWD && threadIdx.x == 0) {
         double g, dg, rc = a.pg.r_cut;
         coul_g<double>(rc, 1.0 / rc, a.pg.alpha, a.pg.coulomb, g, dg);
@@ -125,8 +130,10 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
             row = a.ls.flist + (int64_t)s * a.ls.fcap;
             cnt = min(a.ls.fcnt[s], a.ls.fcap);
         }
-        // U rows entries per lane in flight: their index and position loads are
-        // issued together, which hides the gather latency
+        if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
+            pair_force_row<R, MODE, G>(X, xi, box, row, cnt, lig, s, tab + ti * nt, a.pg, ax, ay, az);
+        } else {
+        // energies and parameter-gradient bases: U entries per lane in flight
         constexpr int U = 4;
         for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
             int32_t pj[U];
@@ -201,6 +208,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
             ax += (double)px;
             ay += (double)py;
             az += (double)pz;
+        }
         }
     }
     if (MODE == MODE_ENERGY) {

@@ -1,9 +1,10 @@
-// The integrator kernel: one thread per atom runs, for its own atom,
+// The integrator kernel: a group of lanes per atom adds the atom's bonded
+// terms to the pair part of F_0 at q_n (from the pair kernel), then runs, for
+// its own atom,
 //   [close step n-1]  J(n-1, JB) and B(dt/2)        (end of B J A O A J B)
 //   [open  step n  ]  B(dt/2), J(n, JA), A, O, A    (start of the next step)
-// with F_0 = pair part (from the pair kernel) + bonded terms at q_n.
 // Positions of other atoms are read from the sorted mirror of q_n and the new
-// positions q_{n+1} go to the other mirror buffer, so all threads may run the
+// positions q_{n+1} go to the other mirror buffer, so all groups may run the
 // step concurrently (Sec. IV.A: at fixed q the per-atom velocity chains are
 // independent).  J is the thinned jump chain of Sec. IV.B / Sec. V: one Poisson
 // count with mean |C_i| beta |v_i| L dt/2, then for each proposal a uniform
@@ -43,84 +44,128 @@ struct JumpTally {
     unsigned long long prop, acc, bound;
 };
 
-// Four lanes per atom ("group"), running the same code on different data.
-constexpr int LPA = 4;
+// An atom's lanes form a group of GS consecutive lanes, running the same code
+// on different data; PB of them evaluate jump proposals side by side.
+constexpr int PB = 4;
 
-__device__ __forceinline__ int group_base() { return (int)(threadIdx.x & 63 & ~(LPA - 1)); }
+template <int GS>
+__device__ __forceinline__ int group_base() { return (int)(threadIdx.x & 63 & ~(GS - 1)); }
 
+template <int GS>
 __device__ __forceinline__ double group_get(double v, int src)
 {
-    return __shfl(v, group_base() + src, 64);
+    return __shfl(v, group_base<GS>() + src, 64);
 }
 
+template <int GS>
 __device__ __forceinline__ uint64_t group_get_u64(uint64_t v, int src)
 {
-    return (uint64_t)__shfl((long long)v, group_base() + src, 64);
+    return (uint64_t)__shfl((long long)v, group_base<GS>() + src, 64);
 }
 
+template <int GS>
 __device__ __forceinline__ int32_t group_get_i32(int32_t v, int src)
 {
-    return __shfl(v, group_base() + src, 64);
+    return __shfl(v, group_base<GS>() + src, 64);
+}
+
+// Poisson count of proposals for one atom and J half-step: inversion of the
+// CDF of Poisson(|C_i| beta |v_i| L dt/2) with the uniform U (Sec. IV.B, Sec. V)
+__device__ __forceinline__ int32_t poisson_count(const StepArgs &a, int32_t c, double v0, double L,
+                                                 double U, bool &capped)
+{
+    capped = false;
+    if (c == 0 || v0 == 0.0 || L == 0.0) return 0;
+    const double mu = (double)c * a.beta * v0 * L * a.half_dt;
+    int32_t M = 0;
+    double term = exp(-mu), cdf = term;
+    while (U > cdf) {
+        ++M;
+        if (M > a.max_proposals) {
+            capped = true;
+            return 0;
+        }
+        term *= mu / (double)M;
+        cdf += term;
+    }
+    return M;
+}
+
+// one proposal: partner and uniform from the Philox block (step, phase, lid, k)
+// and the long-range field of that partner on the atom
+struct Proposal {
+    double F[3];
+    double u;
+    int32_t p;
+};
+
+// first stage: the draw, the partner and the uniform
+__device__ __forceinline__ void draw_proposal(const int32_t *crow, int32_t c, const RepInfo &ri,
+                                              int64_t step, int32_t phase, int32_t lid, int32_t k,
+                                              Proposal &o)
+{
+    const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
+    const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
+    o.p = crow[J];
+    o.u = u01(w.y);
+}
+
+// second stage: the partner's long-range field on the atom
+template <typename R>
+__device__ __forceinline__ void field_proposal(const StepArgs &a, const TypePair<R> *tab,
+                                               const double4 *X, const RepInfo &ri, int ti,
+                                               const double q[3], Proposal &o)
+{
+    const double4 xj = X[o.p];
+    double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
+    BoxReg(ri).apply(dx, dy, dz);
+    long_field<R>(tab[ti * a.pg.n_types + mirror_type(xj.w)], a.pg, dx, dy, dz, o.F);
+}
+
+template <typename R>
+__device__ __forceinline__ void eval_proposal(const StepArgs &a, const TypePair<R> *tab,
+                                              const double4 *X, const int32_t *crow, int32_t c,
+                                              const RepInfo &ri, int ti, const double q[3],
+                                              int64_t step, int32_t phase, int32_t lid, int32_t k,
+                                              Proposal &o)
+{
+    draw_proposal(crow, c, ri, step, phase, lid, k, o);
+    field_proposal<R>(a, tab, X, ri, ti, q, o);
 }
 
 // The velocity chain of one atom over dt/2 at fixed positions, run by the
-// atom's LPA lanes together.  Positions do not move during J, so the fields of
-// all proposals are independent of the chain: lane t of the group draws and
-// evaluates proposals k = k0 + t of a batch in parallel, then every lane walks
-// the batch in order k = k0, k0+1, ... applying the accept test and reflection
-// (same FP64 arithmetic on every lane, so the lanes keep identical v).
-// U: the uniform of the atom's Poisson draw, counter (step, phase, lid, 0).
-// Every lane of the wavefront must call this (active = false for padding).
-template <typename R>
-__device__ void jump_group(const StepArgs &a, const TypePair<R> *tab, const double4 *X, bool active,
-                           int32_t s, int32_t lid, int32_t rep, const RepInfo &ri, int ti,
-                           const double q[3], double v[3], int64_t step, int32_t phase, double U,
-                           int sub, JumpTally &tally)
+// atom's GS lanes together.  Positions do not move during J, so the fields of
+// all proposals are independent of the chain: lane t < PB of the group
+// evaluates proposal k = k0 + t of a batch (the first batch may have been
+// evaluated ahead: pre holds proposal 1 + t if 1 + t <= M_pre), then every lane
+// walks the batch in order k = k0, k0+1, ... applying the accept test and
+// reflection (same FP64 arithmetic on every lane, so the lanes keep identical
+// v).  Every lane of the wavefront must call this (M = 0 for padding lanes).
+template <typename R, int GS>
+__device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const double4 *X,
+                           const int32_t *crow, int32_t c, int32_t lid, int32_t rep,
+                           const RepInfo &ri, int ti, const double q[3], double v[3], double v0,
+                           double L, int64_t step, int32_t phase, int32_t M, int32_t M_pre,
+                           const Proposal &pre, int sub, JumpTally &tally)
 {
-    int32_t M = 0, c = 0;
-    double v0 = 0.0, L = 0.0;
-    if (active) {
-        c = min(a.ls.ccnt[s], a.ls.ccap);
-        v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        L = a.L_a[ti];
-        if (c > 0 && v0 != 0.0 && L != 0.0) {
-            const double mu = (double)c * a.beta * v0 * L * a.half_dt;
-            double term = exp(-mu), cdf = term;
-            while (U > cdf) {
-                ++M;
-                if (M > a.max_proposals) break;
-                term *= mu / (double)M;
-                cdf += term;
-            }
-            if (M > a.max_proposals) {
-                if (sub == 0) atomicOr(&a.st->status, ST_POISSON);
-                M = 0;
-            }
-        }
-    }
-    const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
-    const int nt = a.pg.n_types;
-    for (int32_t k0 = 1; __any(k0 <= M); k0 += LPA) {
-        // this lane's proposal of the batch
+    for (int32_t k0 = 1; __any(k0 <= M); k0 += PB) {
         const int32_t k = k0 + sub;
-        double F[3] = {0.0, 0.0, 0.0}, u = 1.0;
-        int32_t p = 0;
-        if (k <= M) {
-            const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
-            const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
-            p = crow[J];
-            u = u01(w.y);
-            const double4 xj = X[p];
-            double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
-            BoxReg(ri).apply(dx, dy, dz);
-            long_field<R>(tab[ti * nt + mirror_type(xj.w)], a.pg, dx, dy, dz, F);
+        Proposal P;
+        if (k0 == 1 && k <= M_pre && sub < PB) {
+            P = pre;
+        } else {
+            P.F[0] = P.F[1] = P.F[2] = 0.0;
+            P.u = 1.0;
+            P.p = 0;
+            if (k <= M && sub < PB)
+                eval_proposal<R>(a, tab, X, crow, c, ri, ti, q, step, phase, lid, k, P);
         }
-        // the chain, in order
 #pragma unroll
-        for (int t = 0; t < LPA; ++t) {
-            const double Fx = group_get(F[0], t), Fy = group_get(F[1], t), Fz = group_get(F[2], t);
-            const double ut = group_get(u, t);
-            const int32_t pt = group_get_i32(p, t);
+        for (int t = 0; t < PB; ++t) {
+            const double Fx = group_get<GS>(P.F[0], t), Fy = group_get<GS>(P.F[1], t),
+                         Fz = group_get<GS>(P.F[2], t);
+            const double ut = group_get<GS>(P.u, t);
+            const int32_t pt = group_get_i32<GS>(P.p, t);
             if (k0 + t <= M) {
                 const double sdot = v[0] * Fx + v[1] * Fy + v[2] * Fz;
                 // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
@@ -186,48 +231,105 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
     }
 }
 
-// Each lane of an atom's group draws one Philox block (lane 0: the O step,
-// lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA)), lanes
-// 0-2 turn the O block into the three Box-Muller normals and the lanes share
-// the atom's bonded terms; then the group runs the atom's chain (kicks, jump
-// chains, drifts, O step) together and lane 0 writes the results.
+// PB = 4 lanes per atom.  Lanes 0-2 each draw one Philox block (lane 0: the O
+// step, lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA))
+// and turn the O block into the three Box-Muller normals; the lanes share the
+// atom's bonded terms; the first batch of proposals of both J half-steps is
+// evaluated together (J(n-1, JB)'s count is fixed by the velocity at entry and
+// J(n, JA)'s count is estimated from it: proposals depend on positions only,
+// and the chain later uses those with k <= the actual count and evaluates any
+// others).  Then the lanes run the atom's chain (J, kicks, J, drifts, O step)
+// together and lane 0 writes the results.  The pair part of F_0 at q_n comes
+// from the pair kernel.
 template <typename R, bool BOUNCE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
-    const TypePair<R> *tab = jump_table<R>(a);
+    __shared__ TypePair<R> ftab[MAXT * MAXT];
+    const int nt = a.pg.n_types;
+    if (BOUNCE) {
+        const TypePair<R> *tab = jump_table<R>(a);
+        for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) ftab[k] = tab[k];
+    }
+    __syncthreads();
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t s = t / LPA, sub = t % LPA;
-    const bool active = s < a.n;
     const int64_t n = a.st->step + a.step_off;
     const int32_t par = (int32_t)(n & 1);
     const double4 *__restrict__ X = a.ls.x[par];
     double4 *__restrict__ Y = a.ls.x[par ^ 1];
+    double F[3] = {0.0, 0.0, 0.0};
+
+    const int32_t s = t / PB, sub = t % PB;
+    const bool active = s < a.n;
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0, g = 0, lid = 0;
+    int32_t rep = 0, g = 0, lid = 0, c = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
+    double v[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
+    double km = 0.0, c2 = 0.0, L = 0.0;
     U4 w = {0, 0, 0, 0};
-    double fb[3] = {0.0, 0.0, 0.0};
     if (active) {
-        g = a.ls.perm[s];
-        rep = a.tp.rep_of[g];
+        const int2 si = a.ls.sinfo[s];
+        g = si.x;
+        rep = si.y;
+        xi = X[s];
+        F[0] = a.fpair[3 * (int64_t)s];
+        F[1] = a.fpair[3 * (int64_t)s + 1];
+        F[2] = a.fpair[3 * (int64_t)s + 2];
+        if (BOUNCE) c = min(a.ls.ccnt[s], a.ls.ccap);
         const RepInfo &ri = a.reps[rep];
         lid = g - (int32_t)ri.atom_off;
-        xi = X[s];
+        v[0] = a.vel[3 * (int64_t)g];
+        v[1] = a.vel[3 * (int64_t)g + 1];
+        v[2] = a.vel[3 * (int64_t)g + 2];
+        km = a.half_dt * a.tp.acc_m[g];
+        c2 = a.ou_c2[g];
+        if (BOUNCE) L = a.L_a[mirror_type(xi.w)];
         // one Philox block per lane
-        const int64_t dstep = sub == 1 ? n - 1 : n;
-        const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
-        w = draw(ri, dstep, dphase, lid, 0);
+        if (sub < 3) {
+            const int64_t dstep = sub == 1 ? n - 1 : n;
+            const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
+            w = draw(ri, dstep, dphase, lid, 0);
+        }
+    }
+    const RepInfo &ri = a.reps[rep];
+    const int ti = mirror_type(xi.w);
+    double q[3] = {xi.x, xi.y, xi.z};
+    const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
+    const double U_jb = u01(group_get_u64<PB>(w.x, 1)), U_ja = u01(group_get_u64<PB>(w.x, 2));
+    int32_t M_jb = 0, M_est = 0;
+    Proposal pb, pa;
+    pb.F[0] = pb.F[1] = pb.F[2] = pa.F[0] = pa.F[1] = pa.F[2] = 0.0;
+    pb.u = pa.u = 1.0;
+    pb.p = pa.p = 0;
+    if (BOUNCE && active) {
+        const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        bool capped_b = false, capped_a = false;
+        if (a.do_close) M_jb = poisson_count(a, c, v0, L, U_jb, capped_b);
+        if (a.do_open) M_est = poisson_count(a, c, v0, L, U_ja, capped_a);
+        if (1 + sub <= M_jb) eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n - 1, 2, lid, 1 + sub, pb);
+        if (1 + sub <= M_est) eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n, 0, lid, 1 + sub, pa);
+        if (capped_b && sub == 0) atomicOr(&a.st->status, ST_POISSON);
+    }
+    if (active) {
         // bonded terms shared by the lanes
         const int4 *brow = a.ls.bslot + (int64_t)s * BTMAX;
-        for (int k = sub; k < BTMAX; k += LPA) {
+        for (int k = sub; k < BTMAX; k += PB) {
             const int4 e = brow[k];
             if (e.x < 0) break;
             bonded_slot_grad(s, e, X, ri, a.tp, fb);
         }
     }
+#pragma unroll
+    for (int m = 1; m < PB; m <<= 1) {
+        fb[0] += __shfl_xor(fb[0], m, PB);
+        fb[1] += __shfl_xor(fb[1], m, PB);
+        fb[2] += __shfl_xor(fb[2], m, PB);
+    }
+    F[0] += fb[0];
+    F[1] += fb[1];
+    F[2] += fb[2];
     // Box-Muller on the O block: lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
-    const uint64_t ow0 = group_get_u64(w.x, 0), ow1 = group_get_u64(w.y, 0);
-    const uint64_t ow2 = group_get_u64(w.z, 0), ow3 = group_get_u64(w.w, 0);
+    const uint64_t ow0 = group_get_u64<PB>(w.x, 0), ow1 = group_get_u64<PB>(w.y, 0);
+    const uint64_t ow2 = group_get_u64<PB>(w.z, 0), ow3 = group_get_u64<PB>(w.w, 0);
     double gauss;
     {
         const double ua = u01(sub >= 2 ? ow2 : ow0), ub = u01(sub >= 2 ? ow3 : ow1);
@@ -236,49 +338,35 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         sincos(2.0 * M_PI * ub, &sn, &cs);
         gauss = rad * (sub == 1 ? sn : cs);
     }
-    const double G0 = group_get(gauss, 0), G1 = group_get(gauss, 1), G2 = group_get(gauss, 2);
-    const double U_jb = u01(group_get_u64(w.x, 1)), U_ja = u01(group_get_u64(w.x, 2));
-    double B0 = fb[0], B1 = fb[1], B2 = fb[2];
-#pragma unroll
-    for (int m = 1; m < LPA; m <<= 1) {
-        B0 += __shfl_xor(B0, m, LPA);
-        B1 += __shfl_xor(B1, m, LPA);
-        B2 += __shfl_xor(B2, m, LPA);
-    }
+    const double G0 = group_get<PB>(gauss, 0), G1 = group_get<PB>(gauss, 1), G2 = group_get<PB>(gauss, 2);
 
     // the atom's chain, on every lane of the group
-    const RepInfo &ri = a.reps[rep];
-    const int ti = mirror_type(xi.w);
-    double q[3] = {xi.x, xi.y, xi.z};
-    double F[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
-    double km = 0.0;
-    if (active) {
-        F[0] = a.fpair[3 * (int64_t)s] + B0;
-        F[1] = a.fpair[3 * (int64_t)s + 1] + B1;
-        F[2] = a.fpair[3 * (int64_t)s + 2] + B2;
-        v[0] = a.vel[3 * (int64_t)g];
-        v[1] = a.vel[3 * (int64_t)g + 1];
-        v[2] = a.vel[3 * (int64_t)g + 2];
-        km = a.half_dt * a.tp.acc_m[g];
-    }
     if (a.do_close) {
-        if (BOUNCE)
-            jump_group<R>(a, tab, X, active, s, lid, rep, ri, ti, q, v, n - 1, 2, U_jb, sub, tally);
+        if (BOUNCE) {
+            const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            jump_chain<R, PB>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2, M_jb, M_jb,
+                              pb, sub, tally);
+        }
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
     }
     if (a.do_open) {
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
-        if (BOUNCE)
-            jump_group<R>(a, tab, X, active, s, lid, rep, ri, ti, q, v, n, 0, U_ja, sub, tally);
+        if (BOUNCE) {
+            const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            bool capped = false;
+            const int32_t M = active ? poisson_count(a, c, v0, L, U_ja, capped) : 0;
+            if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
+            jump_chain<R, PB>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M, M_est, pa,
+                              sub, tally);
+        }
     }
     if (active && sub == 0) {
         if (a.do_open) {
-            for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
-            const double c2 = a.ou_c2[g];
+            for (int k = 0; k < 3; ++k) q[k] = q[k] + a.half_dt * v[k];
             v[0] = a.c1 * v[0] + c2 * G0;
             v[1] = a.c1 * v[1] + c2 * G1;
             v[2] = a.c1 * v[2] + c2 * G2;
-            for (int c = 0; c < 3; ++c) q[c] = q[c] + a.half_dt * v[c];
+            for (int k = 0; k < 3; ++k) q[k] = q[k] + a.half_dt * v[k];
             const double *qb = a.ls.q_build + 3 * (int64_t)g;
             const double ddx = q[0] - qb[0], ddy = q[1] - qb[1], ddz = q[2] - qb[2];
             if (ddx * ddx + ddy * ddy + ddz * ddz >= a.skin_half2) atomicOr(&a.st->status, ST_SKIN);
@@ -309,7 +397,7 @@ void launch_advance(hipStream_t sm, DevState *st, int32_t count)
 void launch_step(hipStream_t sm, const StepArgs &a)
 {
     if (a.n <= 0) return;
-    dim3 grid(((int64_t)a.n * LPA + 255) / 256), block(256);
+    dim3 grid(((int64_t)a.n * PB + 255) / 256), block(256);
     if (a.bounce) {
         if (a.pair_fp64) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, sm, a);
         else hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, sm, a);
@@ -325,29 +413,38 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     const StepArgs &a = ja.s;
     const TypePair<R> *tab = jump_table<R>(a);
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t s = t / LPA, sub = t % LPA;
+    const int32_t s = t / PB, sub = t % PB;
     const bool active = s < a.n;
     const int32_t par = (int32_t)((a.st->step + a.step_off) & 1);
     const double4 *X = a.ls.x[par];
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0, g = 0, lid = 0;
+    int32_t rep = 0, g = 0, lid = 0, c = 0, M = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-    double v[3] = {0.0, 0.0, 0.0};
-    double U = 0.0;
+    double v[3] = {0.0, 0.0, 0.0}, v0 = 0.0, L = 0.0;
     if (active) {
-        g = a.ls.perm[s];
-        rep = a.tp.rep_of[g];
+        const int2 si = a.ls.sinfo[s];
+        g = si.x;
+        rep = si.y;
         lid = g - (int32_t)a.reps[rep].atom_off;
         xi = X[s];
         v[0] = a.vel[3 * (int64_t)g];
         v[1] = a.vel[3 * (int64_t)g + 1];
         v[2] = a.vel[3 * (int64_t)g + 2];
-        U = u01(draw(a.reps[rep], ja.step, ja.phase, lid, 0).x);
+        c = min(a.ls.ccnt[s], a.ls.ccap);
+        L = a.L_a[mirror_type(xi.w)];
+        v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        bool capped = false;
+        M = poisson_count(a, c, v0, L, u01(draw(a.reps[rep], ja.step, ja.phase, lid, 0).x), capped);
+        if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
     }
     const RepInfo &ri = a.reps[rep];
     const double q[3] = {xi.x, xi.y, xi.z};
-    jump_group<R>(a, tab, X, active, s, lid, rep, ri, mirror_type(xi.w), q, v, ja.step, ja.phase, U,
-                  sub, tally);
+    Proposal none;
+    none.F[0] = none.F[1] = none.F[2] = 0.0;
+    none.u = 1.0;
+    none.p = 0;
+    jump_chain<R, PB>(a, tab, X, a.ls.clist + (int64_t)s * a.ls.ccap, c, lid, rep, ri,
+                  mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, none, sub, tally);
     if (active && sub == 0) {
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];
@@ -359,7 +456,7 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
 void launch_jump(hipStream_t sm, const JumpArgs &a)
 {
     if (a.s.n <= 0) return;
-    dim3 grid(((int64_t)a.s.n * LPA + 255) / 256), block(256);
+    dim3 grid(((int64_t)a.s.n * PB + 255) / 256), block(256);
     if (a.s.pair_fp64) hipLaunchKernelGGL((k_jump<double>), grid, block, 0, sm, a);
     else hipLaunchKernelGGL((k_jump<float>), grid, block, 0, sm, a);
 }
