@@ -146,6 +146,84 @@ def equilibrate(args, system, ff):
     return state
 
 
+def run_batch(args, ff):
+    """64 uneven non-periodic droplets in one context (every kernel spans all
+    replicas; the K-step schedule is one hipGraph)."""
+    import torch
+    import paper_2002_07109_amd as B
+    from workloads import droplet_batch
+    systems = droplet_batch(64)
+    mk = lambda integ, gamma, seed: B.make_params(
+        integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_BARE, periodic=0,
+        dt=args.batch_dt, gamma=gamma, temperature=300.0, r_on=7.0, r_off=8.0, r_cut=9.0,
+        skin=2.0, rebuild_interval=10, seed=seed, cell_size=systems[0].cell_size, use_graph=1)
+    # relax the lattice starts (BAOAB with strong friction, untimed)
+    sim = B.Simulation(systems, mk(B.BAOAB, 0.05, 99), ff["charge"], ff["eps"], ff["sigma"])
+    sim.step(800)
+    sim.sync()
+    pos, vel = sim.pos.cpu().numpy(), sim.vel.cpu().numpy()
+    sim.close()
+    sim = B.Simulation(systems, mk(B.BJAOAJB, 1e-3, 0), ff["charge"], ff["eps"], ff["sigma"])
+    sim.set_state(pos=pos, vel=vel, step=0)
+    sim.step(50)
+    sim.sync()
+    lanes, tune = sim.autotune(reps=10)
+    sim.step(10)
+    sim.sync()
+    c0 = [sim.counters(r)["proposals"] for r in range(len(systems))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.batch_steps)
+    sim.sync()
+    wall = time.perf_counter() - t0
+    c1 = [sim.counters(r)["proposals"] for r in range(len(systems))]
+    n = sim.n
+    sizes = [s.n_atoms for s in systems]
+    sim.close()
+    ms = 1e3 * wall / args.batch_steps
+    return {"workload": "64 non-periodic flexible-water droplets, %d-%d atoms (%d in all), bare "
+                        "Coulomb + LJ, rc 9 A, BOUNCE r'/r'' = 7/8 A, dt %g fs, FP32 pair arithmetic"
+                        % (min(sizes), max(sizes), n, args.batch_dt),
+            "steps": args.batch_steps, "ms_per_step": round(ms, 5),
+            "atom_steps_per_s": n * 1e3 / ms,
+            "proposals_per_step": (sum(c1) - sum(c0)) / args.batch_steps,
+            "pair_lanes": lanes}
+
+
+def run_accuracy(args, system, ff, state):
+    """<T_kin> and <E_pot> per water of BOUNCE and BAOAB at 1 fs against BAOAB at
+    0.25 fs (the reference), each over args.accuracy ps from the same state,
+    sampled every 100 fs; errors are block standard errors (10 blocks)."""
+    import paper_2002_07109_amd as B
+    out = {}
+    for name, integ, dt in (("bounce_1fs", B.BJAOAJB, 1.0), ("baoab_1fs", B.BAOAB, 1.0),
+                            ("baoab_0.25fs", B.BAOAB, 0.25)):
+        p = B.make_params(integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
+                          periodic=1, dt=dt, gamma=1e-3, temperature=300.0, r_on=args.r_on,
+                          r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
+                          rebuild_interval=args.rebuild if dt == 1.0 else 4 * args.rebuild,
+                          seed=7, cell_size=system.cell_size, use_graph=1)
+        sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
+        sim.set_state(pos=state[0], vel=state[1], step=0)
+        per = int(round(100.0 / dt))
+        n_samples = int(round(args.accuracy * 1000.0 / 100.0))
+        sim.step(int(round(2000.0 / dt)))        # 2 ps to decorrelate from the start
+        T, E = [], []
+        for _ in range(n_samples):
+            sim.step(per)
+            e = sim.energies()[0]
+            T.append(e["tkin"])
+            E.append((e["pair"] + e["bond"] + e["angle"]) / (system.n_atoms / 3))
+        sim.close()
+        res = {}
+        for key, x in (("t_kin_K", np.array(T)), ("e_pot_per_water", np.array(E))):
+            blocks = x[: len(x) // 10 * 10].reshape(10, -1).mean(1)
+            res[key] = [round(float(x.mean()), 4), round(float(blocks.std(ddof=1) / np.sqrt(10)), 4)]
+        out[name] = res
+        log(f"accuracy {name}: {res}")
+    return out
+
+
 def cpu_baseline(args, system):
     """The FP64 oracle on a bounded sample of the same workload (its seeded
     input state), on all host cores."""
@@ -161,8 +239,8 @@ def cpu_baseline(args, system):
     wall = time.perf_counter() - t0
     ns_day = args.cpu_steps * 1.0 * 1e-6 / wall * 86400.0
     return dict(value=ns_day, unit="ns/day", cores=cores, kind="oracle",
-                sample=f"{args.cpu_steps} BOUNCE steps of the 24,000-atom box from its seeded "
-                       f"input, including the O(N^2) list build ({wall:.1f} s wall)",
+                sample=f"{args.cpu_steps} BOUNCE steps (list rebuilt every {args.rebuild}, O(N^2) "
+                       f"search) of the 24,000-atom box from its seeded input, {wall:.1f} s wall",
                 status=o["status_name"])
 
 
@@ -178,8 +256,15 @@ def main():
     ap.add_argument("--rebuild", type=int, default=10)
     ap.add_argument("--alpha", type=float, default=0.45)
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time 64 uneven droplets in one context")
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--batch-dt", type=float, default=0.25)
+    ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
+                    help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
+                         "BAOAB at 0.25 fs over PS picoseconds each")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
@@ -261,6 +346,11 @@ def main():
                      "traffic": measured_traffic(bo["lanes"]),
                      "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs},
     }
+    if args.batch:
+        log("timing 64 uneven droplets")
+        line["batch"] = run_batch(args, ff)
+    if args.accuracy > 0:
+        line["accuracy"] = run_accuracy(args, system, ff, state)
     if not args.skip_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(args, system)

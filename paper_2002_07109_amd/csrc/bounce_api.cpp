@@ -386,7 +386,7 @@ struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep;
-    size_t ls[2][14];
+    size_t ls[2][15];
 };
 
 static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
@@ -438,6 +438,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
         q[13] = L.take(sizeof(int2) * n);                               // sinfo
+        q[14] = L.take(4 * ((size_t)c->n_cells / 1024 + 2));            // scan_part
     }
 }
 
@@ -550,6 +551,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
         ls.clist = at<int32_t>(ws, q[11]) + c->n;
         ls.bslot = k == 0 ? at<int4>(ws, q[12]) : nullptr;
         ls.sinfo = at<int2>(ws, q[13]);
+        ls.scan_part = at<int32_t>(ws, q[14]);
         ls.fcap = k == 0 ? c->fcap : c->acap;
         ls.ccap = k == 0 ? c->ccap : 0;
         ls.n_cells = c->n_cells;

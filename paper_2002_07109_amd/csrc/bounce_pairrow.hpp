@@ -23,20 +23,28 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
     const R alpha = (R)pg.alpha, r_on = (R)pg.r_on, inv_w = (R)pg.inv_w;
     const R lim = MODE == MODE_SHORT ? (R)pg.r_off : (R)pg.r_cut;
     const R lim2 = lim * lim;
-    // U entries per lane in flight: their index and position loads are issued
-    // together, which hides the gather latency
+    // U entries per lane in flight: their position gathers are issued together,
+    // and the row indices of the next block load during this block's arithmetic
     constexpr int U = 4;
+    int32_t pn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t e = lig + u * G;
+        pn[u] = e < cnt ? row[e] : -1;
+    }
     for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
         int32_t pj[U];
         double4 xj[U];
         R px = (R)0, py = (R)0, pz = (R)0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t e = e0 + u * G;
-            pj[u] = e < cnt ? row[e] : -1;
-        }
+        for (int u = 0; u < U; ++u) pj[u] = pn[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) xj[u] = X[pj[u] >= 0 ? pj[u] : self];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + (U + u) * G;
+            pn[u] = e < cnt ? row[e] : -1;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             // every loaded position is used (an empty slot gets r2 = lim2), so

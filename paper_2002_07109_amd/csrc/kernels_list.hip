@@ -51,30 +51,74 @@ __global__ void k_bin(int32_t n, const double *__restrict__ pos, const RepInfo *
     ls.q_build[3 * (int64_t)g + 2] = x[2];
 }
 
-// exclusive scan of the cell counts in one workgroup; clears the counts
-__global__ void __launch_bounds__(1024) k_scan(int32_t n_cells, ListSet ls)
+// Exclusive scan of the cell counts into cell_start (and the counts cleared
+// for the next build), in three launches: sums of blocks of 1024 cells, a scan
+// of those sums in one workgroup, and the scan inside each block.
+constexpr int SCAN_B = 1024;
+
+__device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t *wsum)
 {
-    __shared__ int32_t part[1024];
-    int32_t t = threadIdx.x;
-    int32_t chunk = (n_cells + 1023) / 1024;
-    int32_t b = t * chunk, e = min(n_cells, b + chunk);
-    int32_t s = 0;
-    for (int32_t k = b; k < e; ++k) s += ls.cell_count[k];
-    part[t] = s;
+    // inclusive scan over a 1024-thread workgroup: wavefront scans + their totals
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) wsum[w] = v;
     __syncthreads();
-    for (int32_t off = 1; off < 1024; off <<= 1) {
-        int32_t v = t >= off ? part[t - off] : 0;
+    if (w == 0) {
+        int32_t t = lane < SCAN_B / 64 ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int32_t o = __shfl_up(t, off, 64);
+            if (lane >= off) t += o;
+        }
+        if (lane < SCAN_B / 64) wsum[lane] = t;
+    }
+    __syncthreads();
+    return v + (w > 0 ? wsum[w - 1] : 0);
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_part(int32_t n_cells, ListSet ls)
+{
+    __shared__ int32_t wsum[SCAN_B / 64];
+    const int32_t k = blockIdx.x * SCAN_B + threadIdx.x;
+    const int32_t v = k < n_cells ? ls.cell_count[k] : 0;
+    const int32_t incl = block_incl_scan(v, wsum);
+    if (threadIdx.x == SCAN_B - 1) ls.scan_part[blockIdx.x] = incl;
+}
+
+// exclusive scan of the block sums (any number of blocks, SCAN_B at a time)
+__global__ void __launch_bounds__(SCAN_B) k_scan_top(int32_t n_blocks, ListSet ls)
+{
+    __shared__ int32_t wsum[SCAN_B / 64];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t b0 = 0; b0 < n_blocks; b0 += SCAN_B) {
+        const int32_t k = b0 + threadIdx.x;
+        const int32_t v = k < n_blocks ? ls.scan_part[k] : 0;
+        const int32_t c = carry;
+        const int32_t incl = block_incl_scan(v, wsum);
+        if (k < n_blocks) ls.scan_part[k] = c + incl - v;
         __syncthreads();
-        part[t] += v;
+        if (threadIdx.x == SCAN_B - 1) carry = c + incl;
         __syncthreads();
     }
-    int32_t run = part[t] - s;
-    for (int32_t k = b; k < e; ++k) {
-        ls.cell_start[k] = run;
-        run += ls.cell_count[k];
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_scan_fin(int32_t n_cells, ListSet ls)
+{
+    __shared__ int32_t wsum[SCAN_B / 64];
+    const int32_t k = blockIdx.x * SCAN_B + threadIdx.x;
+    const int32_t v = k < n_cells ? ls.cell_count[k] : 0;
+    const int32_t incl = block_incl_scan(v, wsum) + ls.scan_part[blockIdx.x];
+    if (k < n_cells) {
+        ls.cell_start[k] = incl - v;
         ls.cell_count[k] = 0;
     }
-    if (t == 1023) ls.cell_start[n_cells] = part[1023];
+    if (k == n_cells - 1) ls.cell_start[n_cells] = incl;
 }
 
 __global__ void k_scatter(int32_t n, ListSet ls)
@@ -389,7 +433,10 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     if (n <= 0) return;
     int32_t nb = (n + 255) / 256;
     hipLaunchKernelGGL(k_bin, dim3(nb), dim3(256), 0, sm, n, pos, reps, tp, ls, st);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, sm, ls.n_cells, ls);
+    const int32_t nsb = (ls.n_cells + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan_part, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, sm, nsb, ls);
+    hipLaunchKernelGGL(k_scan_fin, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
                        pos, tp, ls, st, bs.mirror_sel, bs.step_off);

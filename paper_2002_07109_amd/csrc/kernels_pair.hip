@@ -119,8 +119,9 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const double4 *__restrict__ X = a.ls.x[par];
         const double4 xi = X[s];
         const int ti = mirror_type(xi.w);
-        gi = a.ls.perm[s];
-        const BoxReg box(a.reps[a.tp.rep_of[gi]]);
+        const int2 si = a.ls.sinfo[s];
+        gi = si.x;
+        const BoxReg box(a.reps[si.y]);
         const int32_t *row;
         int32_t cnt;
         if (a.list_sel == 1) {

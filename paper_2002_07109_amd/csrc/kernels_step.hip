@@ -133,70 +133,85 @@ __device__ __forceinline__ void eval_proposal(const StepArgs &a, const TypePair<
     field_proposal<R>(a, tab, X, ri, ti, q, o);
 }
 
+// One proposal of the chain applied to v (every lane of the group runs the
+// same FP64 arithmetic, so the lanes keep identical v); lane 0 keeps the tally
+// and the event log.
+__device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo &ri, int32_t lid,
+                                               int32_t rep, double v[3], double v0, double L,
+                                               int64_t step, int32_t phase, int32_t k, double Fx,
+                                               double Fy, double Fz, double ut, int32_t pt, int sub,
+                                               JumpTally &tally)
+{
+    const double sdot = v[0] * Fx + v[1] * Fy + v[2] * Fz;
+    // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
+    const int acc = (ut * v0 * L) < sdot;
+    if (acc) {
+        const double f2 = Fx * Fx + Fy * Fy + Fz * Fz;
+        const double cf = 2.0 * sdot / f2;
+        v[0] = v[0] - cf * Fx;
+        v[1] = v[1] - cf * Fy;
+        v[2] = v[2] - cf * Fz;
+    }
+    if (sub == 0) {
+        if (sdot > v0 * L * (1.0 + 1e-9)) {
+            tally.bound++;
+            atomicOr(&a.st->status, ST_BOUND);
+        }
+        tally.acc += acc;
+        tally.prop++;
+        if (a.log_events) {
+            const unsigned long long slot = atomicAdd((unsigned long long *)&a.st->n_events, 1ull);
+            if ((int64_t)slot < a.event_cap) {
+                Event ev;
+                ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k;
+                ev.partner = a.ls.perm[pt] - (int32_t)ri.atom_off;
+                ev.accepted = acc; ev.replica = rep;
+                a.events[slot] = ev;
+            }
+        }
+    }
+}
+
 // The velocity chain of one atom over dt/2 at fixed positions, run by the
 // atom's GS lanes together.  Positions do not move during J, so the fields of
-// all proposals are independent of the chain: lane t < PB of the group
-// evaluates proposal k = k0 + t of a batch (the first batch may have been
-// evaluated ahead: pre holds proposal 1 + t if 1 + t <= M_pre), then every lane
-// walks the batch in order k = k0, k0+1, ... applying the accept test and
-// reflection (same FP64 arithmetic on every lane, so the lanes keep identical
-// v).  Every lane of the wavefront must call this (M = 0 for padding lanes).
-template <typename R, int GS>
+// all proposals are independent of the chain.  Proposals 1..n_pre (n_pre =
+// min(M, M_pre, NPRE)) were evaluated ahead: lane pre_lane + k - 1 holds
+// proposal k in pre.  The others are evaluated PB at a time (lane t < PB takes
+// proposal k0 + t).  Every lane then walks the proposals in order k = 1, 2, ...
+// applying the accept test and reflection.  Every lane of the wavefront must
+// call this (M = 0 for padding lanes).
+template <typename R, int GS, int NPRE>
 __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const double4 *X,
                            const int32_t *crow, int32_t c, int32_t lid, int32_t rep,
                            const RepInfo &ri, int ti, const double q[3], double v[3], double v0,
                            double L, int64_t step, int32_t phase, int32_t M, int32_t M_pre,
-                           const Proposal &pre, int sub, JumpTally &tally)
+                           int pre_lane, const Proposal &pre, int sub, JumpTally &tally)
 {
-    for (int32_t k0 = 1; __any(k0 <= M); k0 += PB) {
+    const int32_t n_pre = min(min(M, M_pre), NPRE);
+#pragma unroll
+    for (int t = 0; t < NPRE; ++t) {
+        const double Fx = group_get<GS>(pre.F[0], pre_lane + t), Fy = group_get<GS>(pre.F[1], pre_lane + t),
+                     Fz = group_get<GS>(pre.F[2], pre_lane + t);
+        const double ut = group_get<GS>(pre.u, pre_lane + t);
+        const int32_t pt = group_get_i32<GS>(pre.p, pre_lane + t);
+        if (t < n_pre)
+            apply_proposal(a, ri, lid, rep, v, v0, L, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+    }
+    for (int32_t k0 = n_pre + 1; __any(k0 <= M); k0 += PB) {
         const int32_t k = k0 + sub;
         Proposal P;
-        if (k0 == 1 && k <= M_pre && sub < PB) {
-            P = pre;
-        } else {
-            P.F[0] = P.F[1] = P.F[2] = 0.0;
-            P.u = 1.0;
-            P.p = 0;
-            if (k <= M && sub < PB)
-                eval_proposal<R>(a, tab, X, crow, c, ri, ti, q, step, phase, lid, k, P);
-        }
+        P.F[0] = P.F[1] = P.F[2] = 0.0;
+        P.u = 1.0;
+        P.p = 0;
+        if (k <= M && sub < PB) eval_proposal<R>(a, tab, X, crow, c, ri, ti, q, step, phase, lid, k, P);
 #pragma unroll
         for (int t = 0; t < PB; ++t) {
             const double Fx = group_get<GS>(P.F[0], t), Fy = group_get<GS>(P.F[1], t),
                          Fz = group_get<GS>(P.F[2], t);
             const double ut = group_get<GS>(P.u, t);
             const int32_t pt = group_get_i32<GS>(P.p, t);
-            if (k0 + t <= M) {
-                const double sdot = v[0] * Fx + v[1] * Fy + v[2] * Fz;
-                // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
-                const int acc = (ut * v0 * L) < sdot;
-                if (acc) {
-                    const double f2 = Fx * Fx + Fy * Fy + Fz * Fz;
-                    const double cf = 2.0 * sdot / f2;
-                    v[0] = v[0] - cf * Fx;
-                    v[1] = v[1] - cf * Fy;
-                    v[2] = v[2] - cf * Fz;
-                }
-                if (sub == 0) {
-                    if (sdot > v0 * L * (1.0 + 1e-9)) {
-                        tally.bound++;
-                        atomicOr(&a.st->status, ST_BOUND);
-                    }
-                    tally.acc += acc;
-                    tally.prop++;
-                    if (a.log_events) {
-                        const unsigned long long slot =
-                            atomicAdd((unsigned long long *)&a.st->n_events, 1ull);
-                        if ((int64_t)slot < a.event_cap) {
-                            Event ev;
-                            ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k0 + t;
-                            ev.partner = a.ls.perm[pt] - (int32_t)ri.atom_off;
-                            ev.accepted = acc; ev.replica = rep;
-                            a.events[slot] = ev;
-                        }
-                    }
-                }
-            }
+            if (k0 + t <= M)
+                apply_proposal(a, ri, lid, rep, v, v0, L, step, phase, k0 + t, Fx, Fy, Fz, ut, pt, sub, tally);
         }
     }
 }
@@ -231,16 +246,19 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
     }
 }
 
-// PB = 4 lanes per atom.  Lanes 0-2 each draw one Philox block (lane 0: the O
-// step, lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA))
+// LPA = 4 lanes per atom.  Lanes 0-2 each draw one Philox block (lane 0: the
+// O step, lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA))
 // and turn the O block into the three Box-Muller normals; the lanes share the
-// atom's bonded terms; the first batch of proposals of both J half-steps is
-// evaluated together (J(n-1, JB)'s count is fixed by the velocity at entry and
-// J(n, JA)'s count is estimated from it: proposals depend on positions only,
-// and the chain later uses those with k <= the actual count and evaluates any
-// others).  Then the lanes run the atom's chain (J, kicks, J, drifts, O step)
-// together and lane 0 writes the results.  The pair part of F_0 at q_n comes
-// from the pair kernel.
+// atom's bonded terms.  Right after the Poisson counts, lanes 0-1 evaluate
+// proposals 1-2 of J(n-1, JB) (its count is fixed by the velocity at entry)
+// and lanes 2-3 proposals 1-2 of J(n, JA), whose count is estimated from the
+// same velocity (proposals depend on positions only; the chain later uses
+// those with k <= the actual count and evaluates any others).  Then the lanes
+// run the atom's chain (J, kicks, J, drifts, O step) together and lane 0 writes
+// the results.  The pair part of F_0 at q_n comes from the pair kernel.
+constexpr int LPA = 4;
+constexpr int JB_LANE = 0, JB_PRE = 2, JA_LANE = 2, JA_PRE = 2;
+
 template <typename R, bool BOUNCE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
@@ -258,7 +276,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     double4 *__restrict__ Y = a.ls.x[par ^ 1];
     double F[3] = {0.0, 0.0, 0.0};
 
-    const int32_t s = t / PB, sub = t % PB;
+    const int32_t s = t / LPA, sub = t % LPA;
     const bool active = s < a.n;
     JumpTally tally = {0, 0, 0};
     int32_t rep = 0, g = 0, lid = 0, c = 0;
@@ -294,42 +312,45 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     const int ti = mirror_type(xi.w);
     double q[3] = {xi.x, xi.y, xi.z};
     const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
-    const double U_jb = u01(group_get_u64<PB>(w.x, 1)), U_ja = u01(group_get_u64<PB>(w.x, 2));
+    const double U_jb = u01(group_get_u64<LPA>(w.x, 1)), U_ja = u01(group_get_u64<LPA>(w.x, 2));
     int32_t M_jb = 0, M_est = 0;
-    Proposal pb, pa;
-    pb.F[0] = pb.F[1] = pb.F[2] = pa.F[0] = pa.F[1] = pa.F[2] = 0.0;
-    pb.u = pa.u = 1.0;
-    pb.p = pa.p = 0;
+    Proposal pp;     // lanes 0-1: proposals 1-2 of J(n-1, JB); lanes 2-3: 1-2 of J(n, JA)
+    pp.F[0] = pp.F[1] = pp.F[2] = 0.0;
+    pp.u = 1.0;
+    pp.p = 0;
     if (BOUNCE && active) {
         const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         bool capped_b = false, capped_a = false;
         if (a.do_close) M_jb = poisson_count(a, c, v0, L, U_jb, capped_b);
         if (a.do_open) M_est = poisson_count(a, c, v0, L, U_ja, capped_a);
-        if (1 + sub <= M_jb) eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n - 1, 2, lid, 1 + sub, pb);
-        if (1 + sub <= M_est) eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n, 0, lid, 1 + sub, pa);
+        const int kb = sub - JB_LANE + 1, ka = sub - JA_LANE + 1;
+        if (sub >= JB_LANE && kb <= JB_PRE && kb <= M_jb)
+            eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n - 1, 2, lid, kb, pp);
+        else if (sub >= JA_LANE && ka <= JA_PRE && ka <= M_est)
+            eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n, 0, lid, ka, pp);
         if (capped_b && sub == 0) atomicOr(&a.st->status, ST_POISSON);
     }
     if (active) {
         // bonded terms shared by the lanes
         const int4 *brow = a.ls.bslot + (int64_t)s * BTMAX;
-        for (int k = sub; k < BTMAX; k += PB) {
+        for (int k = sub; k < BTMAX; k += LPA) {
             const int4 e = brow[k];
             if (e.x < 0) break;
             bonded_slot_grad(s, e, X, ri, a.tp, fb);
         }
     }
 #pragma unroll
-    for (int m = 1; m < PB; m <<= 1) {
-        fb[0] += __shfl_xor(fb[0], m, PB);
-        fb[1] += __shfl_xor(fb[1], m, PB);
-        fb[2] += __shfl_xor(fb[2], m, PB);
+    for (int m = 1; m < LPA; m <<= 1) {
+        fb[0] += __shfl_xor(fb[0], m, LPA);
+        fb[1] += __shfl_xor(fb[1], m, LPA);
+        fb[2] += __shfl_xor(fb[2], m, LPA);
     }
     F[0] += fb[0];
     F[1] += fb[1];
     F[2] += fb[2];
     // Box-Muller on the O block: lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
-    const uint64_t ow0 = group_get_u64<PB>(w.x, 0), ow1 = group_get_u64<PB>(w.y, 0);
-    const uint64_t ow2 = group_get_u64<PB>(w.z, 0), ow3 = group_get_u64<PB>(w.w, 0);
+    const uint64_t ow0 = group_get_u64<LPA>(w.x, 0), ow1 = group_get_u64<LPA>(w.y, 0);
+    const uint64_t ow2 = group_get_u64<LPA>(w.z, 0), ow3 = group_get_u64<LPA>(w.w, 0);
     double gauss;
     {
         const double ua = u01(sub >= 2 ? ow2 : ow0), ub = u01(sub >= 2 ? ow3 : ow1);
@@ -338,14 +359,14 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         sincos(2.0 * M_PI * ub, &sn, &cs);
         gauss = rad * (sub == 1 ? sn : cs);
     }
-    const double G0 = group_get<PB>(gauss, 0), G1 = group_get<PB>(gauss, 1), G2 = group_get<PB>(gauss, 2);
+    const double G0 = group_get<LPA>(gauss, 0), G1 = group_get<LPA>(gauss, 1), G2 = group_get<LPA>(gauss, 2);
 
     // the atom's chain, on every lane of the group
     if (a.do_close) {
         if (BOUNCE) {
             const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            jump_chain<R, PB>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2, M_jb, M_jb,
-                              pb, sub, tally);
+            jump_chain<R, LPA, JB_PRE>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2,
+                                       M_jb, M_jb, JB_LANE, pp, sub, tally);
         }
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
     }
@@ -356,8 +377,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             bool capped = false;
             const int32_t M = active ? poisson_count(a, c, v0, L, U_ja, capped) : 0;
             if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
-            jump_chain<R, PB>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M, M_est, pa,
-                              sub, tally);
+            jump_chain<R, LPA, JA_PRE>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M,
+                                       M_est, JA_LANE, pp, sub, tally);
         }
     }
     if (active && sub == 0) {
@@ -397,7 +418,7 @@ void launch_advance(hipStream_t sm, DevState *st, int32_t count)
 void launch_step(hipStream_t sm, const StepArgs &a)
 {
     if (a.n <= 0) return;
-    dim3 grid(((int64_t)a.n * PB + 255) / 256), block(256);
+    dim3 grid(((int64_t)a.n * LPA + 255) / 256), block(256);
     if (a.bounce) {
         if (a.pair_fp64) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, sm, a);
         else hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, sm, a);
@@ -443,8 +464,8 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     none.F[0] = none.F[1] = none.F[2] = 0.0;
     none.u = 1.0;
     none.p = 0;
-    jump_chain<R, PB>(a, tab, X, a.ls.clist + (int64_t)s * a.ls.ccap, c, lid, rep, ri,
-                  mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, none, sub, tally);
+    jump_chain<R, PB, 1>(a, tab, X, a.ls.clist + (int64_t)s * a.ls.ccap, c, lid, rep, ri,
+                         mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, 0, none, sub, tally);
     if (active && sub == 0) {
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];

@@ -32,12 +32,12 @@ def relax(sys_, steps=3000):
 def main():
     out = {}
     for name, nw, seed, stream in DROPLETS:
-        s = water_droplet(n_waters=nw, seed=seed, stream=stream)
+        s = water_droplet(n_waters=nw, seed=seed, stream=stream, cell_size=4.4)
         q, v = relax(s)
         out[name + "_pos"], out[name + "_vel"] = q, v
         print(name, nw, "waters relaxed")
     for name, n_side, edge, seed in BOXES:
-        s = water_box(n_side=n_side, box_len=edge, seed=seed)
+        s = water_box(n_side=n_side, box_len=edge, seed=seed, cell_size=4.4)
         q, v = relax(s, steps=2000)
         out[name + "_pos"], out[name + "_vel"] = q, v
         print(name, n_side ** 3, "waters relaxed")
