@@ -224,6 +224,31 @@ def run_accuracy(args, system, ff, state):
     return out
 
 
+def run_big(args, ff):
+    """The same model on a 4x larger periodic box (32^3 = 32,768 waters in a
+    98.3 A cube, 98,304 atoms): BOUNCE and BAOAB ms/step after the same
+    relaxation, showing how the latency-bound kernels fill the GPU."""
+    from workloads import water_box
+    system = water_box(n_side=32, box_len=98.3, seed=3)
+    sub_args = argparse.Namespace(**vars(args))
+    sub_args.equil = 600
+    sub_args.steps = args.big_steps
+    sub_args.warmup = 50
+    state = equilibrate(sub_args, system, ff)
+    import paper_2002_07109_amd as B
+    out = {"workload": "periodic 98,304-atom flexible water box (98.3 A cube), same model and "
+                       "settings as the 24,000-atom box", "steps": args.big_steps}
+    for name, integ in (("baoab", B.BAOAB), ("bounce", B.BJAOAJB)):
+        r = run_gpu(sub_args, system, ff, integ, state)
+        out[name] = {"ms_per_step": round(r["ms_per_step"], 5),
+                     "ns_per_day": round(1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
+                     "pair_kernel_us": round(r["pair_kernel_ms"] * 1e3, 3),
+                     "list_build_us": round(r["build_ms"] * 1e3, 3), "pair_lanes": r["lanes"]}
+        log(f"98k box {name}: {out[name]}")
+    out["speedup_vs_baoab"] = round(out["baoab"]["ms_per_step"] / out["bounce"]["ms_per_step"], 4)
+    return out
+
+
 def cpu_baseline(args, system):
     """The FP64 oracle on a bounded sample of the same workload (its seeded
     input state), on all host cores."""
@@ -262,6 +287,9 @@ def main():
                     help="also time 64 uneven droplets in one context")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-dt", type=float, default=0.25)
+    ap.add_argument("--big", action="store_true",
+                    help="also time a 98,304-atom box with the same model")
+    ap.add_argument("--big-steps", type=int, default=500)
     ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
                     help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
                          "BAOAB at 0.25 fs over PS picoseconds each")
@@ -349,6 +377,9 @@ def main():
     if args.batch:
         log("timing 64 uneven droplets")
         line["batch"] = run_batch(args, ff)
+    if args.big:
+        log("timing the 98,304-atom box")
+        line["big_box"] = run_big(args, ff)
     if args.accuracy > 0:
         line["accuracy"] = run_accuracy(args, system, ff, state)
     if not args.skip_cpu:
