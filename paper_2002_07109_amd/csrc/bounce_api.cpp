@@ -673,6 +673,7 @@ static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
     PairArgs a{};
     a.n = c->n;
     a.mirror_sel = mirror_sel;
+    a.single_rep = c->R == 1;
     a.reps = c->d_reps;
     a.tp = c->tp;
     a.ls = ls;
@@ -700,6 +701,7 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     StepArgs a{};
     a.n = c->n;
     a.step_off = step_off;
+    a.single_rep = c->R == 1;
     a.do_close = close;
     a.do_open = open;
     a.bounce = c->p.integrator == BOUNCE_BJAOAJB;

@@ -214,6 +214,16 @@ __device__ __forceinline__ void min_image(const RepInfo &ri, double &dx, double 
     }
 }
 
+// a replica's parameters; with one replica the index is the constant 0, so the
+// load is uniform and need not wait for the per-atom replica index
+__device__ __forceinline__ RepInfo load_rep(const RepInfo *reps, int single, int32_t rep)
+{
+    RepInfo r;
+    if (single) r = reps[0];
+    else r = reps[rep];
+    return r;
+}
+
 // the periodic box of one replica, held in registers by the pair loops
 struct BoxReg {
     double L[3], iL[3];

@@ -10,6 +10,8 @@ struct PairArgs {
     int32_t n;
     int32_t mirror_sel;           // -1: parity of step (device counter + step_off), 0/1 fixed
     int32_t step_off;
+    int32_t single_rep;           // 1: one replica (its RepInfo read as reps[0])
+    int32_t pad0;
     const RepInfo *reps;
     Topo tp;
     ListSet ls;
@@ -37,6 +39,8 @@ struct StepArgs {
     int32_t log_events;
     int32_t max_proposals;
     int32_t step_off;             // step n = device counter + step_off
+    int32_t single_rep;           // 1: one replica (its RepInfo read as reps[0])
+    int32_t pad0;
     const RepInfo *reps;
     Topo tp;
     ListSet ls;

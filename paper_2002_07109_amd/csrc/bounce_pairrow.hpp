@@ -16,7 +16,7 @@ namespace bnc {
 template <typename R, int MODE, int G>
 __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, const double4 &xi,
                                                const BoxReg &box, const int32_t *__restrict__ row,
-                                               int32_t cnt, int lig, int32_t self,
+                                               int32_t cnt, int32_t cap, int lig, int32_t self,
                                                const TypePair<R> *tab_i, const PairGlobals &pg,
                                                double &ax, double &ay, double &az)
 {
@@ -26,12 +26,17 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
     // U entries per lane in flight: their position gathers are issued together,
     // and the row indices of the next block load during this block's arithmetic
     constexpr int U = 4;
+    // the first block is read within the row's capacity without waiting for
+    // its length, then masked
     int32_t pn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t e = lig + u * G;
-        pn[u] = e < cnt ? row[e] : -1;
+        pn[u] = e < cap ? row[e] : -1;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (lig + u * G >= cnt) pn[u] = -1;
     for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
         int32_t pj[U];
         double4 xj[U];

@@ -121,18 +121,20 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const int ti = mirror_type(xi.w);
         const int2 si = a.ls.sinfo[s];
         gi = si.x;
-        const BoxReg box(a.reps[si.y]);
+        const BoxReg box(load_rep(a.reps, a.single_rep, si.y));
         const int32_t *row;
-        int32_t cnt;
+        int32_t cnt, cap;
         if (a.list_sel == 1) {
             row = a.ls.clist + (int64_t)s * a.ls.ccap;
-            cnt = min(a.ls.ccnt[s], a.ls.ccap);
+            cap = a.ls.ccap;
+            cnt = min(a.ls.ccnt[s], cap);
         } else {
             row = a.ls.flist + (int64_t)s * a.ls.fcap;
-            cnt = min(a.ls.fcnt[s], a.ls.fcap);
+            cap = a.ls.fcap;
+            cnt = min(a.ls.fcnt[s], cap);
         }
         if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
-            pair_force_row<R, MODE, G>(X, xi, box, row, cnt, lig, s, tab + ti * nt, a.pg, ax, ay, az);
+            pair_force_row<R, MODE, G>(X, xi, box, row, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
         } else {
         // energies and parameter-gradient bases: U entries per lane in flight
         constexpr int U = 4;

@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         F[1] = a.fpair[3 * (int64_t)s + 1];
         F[2] = a.fpair[3 * (int64_t)s + 2];
         if (BOUNCE) c = min(a.ls.ccnt[s], a.ls.ccap);
-        const RepInfo &ri = a.reps[rep];
+        const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
         lid = g - (int32_t)ri.atom_off;
         v[0] = a.vel[3 * (int64_t)g];
         v[1] = a.vel[3 * (int64_t)g + 1];
@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             w = draw(ri, dstep, dphase, lid, 0);
         }
     }
-    const RepInfo &ri = a.reps[rep];
+    const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
     const int ti = mirror_type(xi.w);
     double q[3] = {xi.x, xi.y, xi.z};
     const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
