@@ -99,6 +99,7 @@ struct bounce_ctx {
     RepInfo *d_reps = nullptr;
     DevState *d_st = nullptr;
     RepCounters *d_cnt = nullptr;
+    unsigned long long *d_wave_cnt = nullptr;
     Event *d_events = nullptr;
     const TypePair<float> *d_tab_f = nullptr;
     const TypePair<double> *d_tab_d = nullptr;
@@ -384,10 +385,13 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
-        angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, rep_off, one_seg, st, cnt, events, fpair, atom,
+        angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep;
     size_t ls[2][15];
 };
+
+// wavefront slots of the integrator and jump kernels (4 lanes per atom)
+static int64_t wave_slots(const bounce_ctx *c) { return ((int64_t)c->n * 4 + 63) / 64 + 1; }
 
 static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
 {
@@ -415,6 +419,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.one_seg = L.take(16);
     o.st = L.take(sizeof(DevState));
     o.cnt = L.take(sizeof(RepCounters) * CNT_SPREAD * R);
+    o.wave_cnt = L.take(8 * 3 * (size_t)wave_slots(c));
     o.events = L.take(sizeof(Event) * std::max<int64_t>(1, c->p.log_events ? c->p.event_capacity : 1));
     o.fpair = L.take(24 * n);
     o.atom = L.take(8 * n * std::max(5, 3 * MAXT));
@@ -503,6 +508,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     HIPCHK(c, up(sm, ws, o.one_seg, one));
     HIPCHK(c, hipMemsetAsync(ws + o.st, 0, sizeof(DevState), sm));
     HIPCHK(c, hipMemsetAsync(ws + o.cnt, 0, sizeof(RepCounters) * CNT_SPREAD * c->R, sm));
+    HIPCHK(c, hipMemsetAsync(ws + o.wave_cnt, 0, 8 * 3 * (size_t)wave_slots(c), sm));
     Topo &t = c->tp;
     t.type = at<int32_t>(ws, o.type);
     t.rep_of = at<int32_t>(ws, o.rep_of);
@@ -526,6 +532,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     c->d_one_seg = at<int64_t>(ws, o.one_seg);
     c->d_st = at<DevState>(ws, o.st);
     c->d_cnt = at<RepCounters>(ws, o.cnt);
+    c->d_wave_cnt = at<unsigned long long>(ws, o.wave_cnt);
     c->d_events = at<Event>(ws, o.events);
     c->d_fpair = at<double>(ws, o.fpair);
     c->d_atom = at<double>(ws, o.atom);
@@ -713,6 +720,7 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     a.ls = c->main;
     a.st = c->d_st;
     a.cnt = c->d_cnt;
+    a.wave_cnt = c->d_wave_cnt;
     a.events = c->d_events;
     a.event_cap = c->p.log_events ? c->p.event_capacity : 0;
     a.fpair = c->d_fpair;
@@ -924,6 +932,15 @@ bounce_status bounce_get_counters(bounce_ctx *c, int32_t replica, bounce_counter
         out->proposals += (int64_t)k.proposals;
         out->accepted += (int64_t)k.accepted;
         out->bound_violations += (int64_t)k.bound_violations;
+    }
+    if (c->R == 1) {
+        std::vector<unsigned long long> wc(3 * (size_t)wave_slots(c));
+        HIPCHK(c, hipMemcpy(wc.data(), c->d_wave_cnt, 8 * wc.size(), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < wc.size(); k += 3) {
+            out->proposals += (int64_t)wc[k];
+            out->accepted += (int64_t)wc[k + 1];
+            out->bound_violations += (int64_t)wc[k + 2];
+        }
     }
     out->rebuilds = c->host_rebuilds;
     out->steps = c->host_steps;

@@ -78,28 +78,29 @@ __device__ __forceinline__ void bonded_term_grad(int32_t g, int32_t code, const 
 }
 
 // the same gradient from a resolved term e = (code, slot of each atom) of the
-// atom at sorted position s, positions from the sorted mirror X
-__device__ __forceinline__ void bonded_slot_grad(int32_t s, int4 e, const double4 *X,
-                                                 const RepInfo &ri, const Topo &tp, double out[3])
+// atom at sorted position s, with the positions of the term's atoms given
+// (xa, xb, xc: slots e.y, e.z, e.w; xc unused for a bond)
+__device__ __forceinline__ void bonded_slot_grad_pos(int32_t s, int4 e, const double4 &xa,
+                                                     const double4 &xb, const double4 &xc,
+                                                     const RepInfo &ri, const Topo &tp, double out[3])
 {
     const int32_t kind = e.x >> 28, idx = e.x & 0x0fffffff;
-    auto disp = [&](int32_t a, int32_t b, double d[3]) {
-        const double4 xa = X[a], xb = X[b];
-        double dx = xa.x - xb.x, dy = xa.y - xb.y, dz = xa.z - xb.z;
+    auto disp = [&](const double4 &p, const double4 &r, double d[3]) {
+        double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
         min_image(ri, dx, dy, dz);
         d[0] = dx; d[1] = dy; d[2] = dz;
     };
     if (kind == 0) {
         double d[3];
-        disp(e.y, e.z, d);
+        disp(xa, xb, d);
         const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const double c = 2.0 * tp.bond_kr[2 * idx] * (r - tp.bond_kr[2 * idx + 1]) / r;
         const double sg = (s == e.y) ? c : -c;
         out[0] += sg * d[0]; out[1] += sg * d[1]; out[2] += sg * d[2];
     } else {
         double e1[3], e2[3];
-        disp(e.y, e.z, e1);
-        disp(e.w, e.z, e2);
+        disp(xa, xb, e1);
+        disp(xc, xb, e2);
         const double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
         const double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
         const double il = 1.0 / (l1 * l2);
@@ -107,6 +108,7 @@ __device__ __forceinline__ void bonded_slot_grad(int32_t s, int4 e, const double
         cs = fmin(1.0, fmax(-1.0, cs));
         const double th = acos(cs);
         const double sn = sqrt(1.0 - cs * cs);
+        // dE/dtheta * dtheta/dcos, with dtheta/dcos = -1/sin
         const double w = -2.0 * tp.angle_kt[2 * idx] * (th - tp.angle_kt[2 * idx + 1]) / sn;
         for (int c = 0; c < 3; ++c) {
             const double gx = w * (e2[c] * il - cs * e1[c] / (l1 * l1));
@@ -116,6 +118,14 @@ __device__ __forceinline__ void bonded_slot_grad(int32_t s, int4 e, const double
             if (s == e.z) out[c] -= gx + gy;
         }
     }
+}
+
+// the same, loading the term's positions from the sorted mirror X
+__device__ __forceinline__ void bonded_slot_grad(int32_t s, int4 e, const double4 *X,
+                                                 const RepInfo &ri, const Topo &tp, double out[3])
+{
+    const double4 xa = X[e.y], xb = X[e.z], xc = X[(e.x >> 28) ? e.w : e.y];
+    bonded_slot_grad_pos(s, e, xa, xb, xc, ri, tp, out);
 }
 
 template <class PosF>

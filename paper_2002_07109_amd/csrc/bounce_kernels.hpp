@@ -46,6 +46,7 @@ struct StepArgs {
     ListSet ls;
     DevState *st;
     RepCounters *cnt;
+    unsigned long long *wave_cnt; // one replica: [wavefronts][3] jump counters
     Event *events;
     int64_t event_cap;
     const double *fpair;          // [N][3] sorted order, pair part of F_0

@@ -99,15 +99,19 @@ struct Proposal {
     int32_t p;
 };
 
-// first stage: the draw, the partner and the uniform
+// first stage: the partner and the uniform from the proposal's Philox block
+__device__ __forceinline__ void block_proposal(const U4 &w, const int32_t *crow, int32_t c, Proposal &o)
+{
+    const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
+    o.p = crow[J];
+    o.u = u01(w.y);
+}
+
 __device__ __forceinline__ void draw_proposal(const int32_t *crow, int32_t c, const RepInfo &ri,
                                               int64_t step, int32_t phase, int32_t lid, int32_t k,
                                               Proposal &o)
 {
-    const U4 w = draw(ri, step, phase, lid, (uint64_t)k);
-    const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
-    o.p = crow[J];
-    o.u = u01(w.y);
+    block_proposal(draw(ri, step, phase, lid, (uint64_t)k), crow, c, o);
 }
 
 // second stage: the partner's long-range field on the atom
@@ -175,8 +179,8 @@ __device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo 
 // The velocity chain of one atom over dt/2 at fixed positions, run by the
 // atom's GS lanes together.  Positions do not move during J, so the fields of
 // all proposals are independent of the chain.  Proposals 1..n_pre (n_pre =
-// min(M, M_pre, NPRE)) were evaluated ahead: lane pre_lane + k - 1 holds
-// proposal k in pre.  The others are evaluated PB at a time (lane t < PB takes
+// min(M, M_pre, NPRE), NPRE <= 2) were evaluated ahead: lane pre_lane1 holds
+// proposal 1 and lane pre_lane2 proposal 2 in pre.  The others are evaluated PB at a time (lane t < PB takes
 // proposal k0 + t).  Every lane then walks the proposals in order k = 1, 2, ...
 // applying the accept test and reflection.  Every lane of the wavefront must
 // call this (M = 0 for padding lanes).
@@ -185,15 +189,17 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
                            const int32_t *crow, int32_t c, int32_t lid, int32_t rep,
                            const RepInfo &ri, int ti, const double q[3], double v[3], double v0,
                            double L, int64_t step, int32_t phase, int32_t M, int32_t M_pre,
-                           int pre_lane, const Proposal &pre, int sub, JumpTally &tally)
+                           int pre_lane1, int pre_lane2, const Proposal &pre, int sub,
+                           JumpTally &tally)
 {
     const int32_t n_pre = min(min(M, M_pre), NPRE);
 #pragma unroll
     for (int t = 0; t < NPRE; ++t) {
-        const double Fx = group_get<GS>(pre.F[0], pre_lane + t), Fy = group_get<GS>(pre.F[1], pre_lane + t),
-                     Fz = group_get<GS>(pre.F[2], pre_lane + t);
-        const double ut = group_get<GS>(pre.u, pre_lane + t);
-        const int32_t pt = group_get_i32<GS>(pre.p, pre_lane + t);
+        const int src = t == 0 ? pre_lane1 : pre_lane2;
+        const double Fx = group_get<GS>(pre.F[0], src), Fy = group_get<GS>(pre.F[1], src),
+                     Fz = group_get<GS>(pre.F[2], src);
+        const double ut = group_get<GS>(pre.u, src);
+        const int32_t pt = group_get_i32<GS>(pre.p, src);
         if (t < n_pre)
             apply_proposal(a, ri, lid, rep, v, v0, L, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
     }
@@ -225,6 +231,20 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t)
 {
+    if (a.single_rep) {
+        // one replica: each wavefront owns a slot of the per-wavefront counters
+        // (launches of one stream never overlap), so no atomics are needed
+        const unsigned long long p = wave_sum(active ? t.prop : 0), c = wave_sum(active ? t.acc : 0),
+                                 b = wave_sum(active ? t.bound : 0);
+        if ((threadIdx.x & 63) == 0 && (p | c | b)) {
+            unsigned long long *wc =
+                a.wave_cnt + 3 * ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+            wc[0] += p;
+            wc[1] += c;
+            wc[2] += b;
+        }
+        return;
+    }
     // this wavefront's copy of the counters
     const int32_t copy = (int32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (CNT_SPREAD - 1));
     const int32_t first = __shfl(rep, 0, 64);
@@ -246,18 +266,20 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
     }
 }
 
-// LPA = 4 lanes per atom.  Lanes 0-2 each draw one Philox block (lane 0: the
-// O step, lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of J(n, JA))
-// and turn the O block into the three Box-Muller normals; the lanes share the
-// atom's bonded terms.  Right after the Poisson counts, lanes 0-1 evaluate
-// proposals 1-2 of J(n-1, JB) (its count is fixed by the velocity at entry)
-// and lanes 2-3 proposals 1-2 of J(n, JA), whose count is estimated from the
-// same velocity (proposals depend on positions only; the chain later uses
-// those with k <= the actual count and evaluates any others).  Then the lanes
-// run the atom's chain (J, kicks, J, drifts, O step) together and lane 0 writes
-// the results.  The pair part of F_0 at q_n comes from the pair kernel.
+// LPA = 4 lanes per atom.  Each lane draws one Philox block at entry (lane 0:
+// the O step, lane 1: the Poisson uniform of J(n-1, JB), lane 2: that of
+// J(n, JA), lane 3: proposal 1 of J(n-1, JB), used only if that count is at
+// least 1); lanes 0-2 turn the O block into the three Box-Muller normals and
+// the lanes share the atom's bonded terms.  Right after the Poisson counts the
+// first proposals of both J half-steps are evaluated side by side: J(n-1, JB)
+// (count fixed by the velocity at entry) on lanes 3 and 1, J(n, JA) (count
+// estimated from the same velocity; proposals depend on positions only, and
+// the chain later uses those with k <= the actual count and evaluates any
+// others) on lanes 2 and 0.  Then the lanes run the atom's chain (J, kicks, J,
+// drifts, O step) together and lane 0 writes the results.  The pair part of
+// F_0 at q_n comes from the pair kernel.
 constexpr int LPA = 4;
-constexpr int JB_LANE = 0, JB_PRE = 2, JA_LANE = 2, JA_PRE = 2;
+constexpr int JB_L1 = 3, JB_L2 = 1, JA_L1 = 2, JA_L2 = 0;
 
 template <typename R, bool BOUNCE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
@@ -306,15 +328,29 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             const int64_t dstep = sub == 1 ? n - 1 : n;
             const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
             w = draw(ri, dstep, dphase, lid, 0);
+        } else if (BOUNCE && a.do_close) {
+            w = draw(ri, n - 1, 2, lid, 1);
         }
     }
     const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
     const int ti = mirror_type(xi.w);
     double q[3] = {xi.x, xi.y, xi.z};
     const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
+    // this lane's first bonded term and its atoms' positions, loaded ahead of
+    // the jump proposals so the two latency chains overlap
+    int4 e0 = make_int4(-1, 0, 0, 0);
+    double4 ba = make_double4(0.0, 0.0, 0.0, 0.0), bb = ba, bc = ba;
+    if (active) {
+        e0 = a.ls.bslot[(int64_t)s * BTMAX + sub];
+        if (e0.x >= 0) {
+            ba = X[e0.y];
+            bb = X[e0.z];
+            bc = X[(e0.x >> 28) ? e0.w : e0.y];
+        }
+    }
     const double U_jb = u01(group_get_u64<LPA>(w.x, 1)), U_ja = u01(group_get_u64<LPA>(w.x, 2));
     int32_t M_jb = 0, M_est = 0;
-    Proposal pp;     // lanes 0-1: proposals 1-2 of J(n-1, JB); lanes 2-3: 1-2 of J(n, JA)
+    Proposal pp;     // lanes 3, 1: proposals 1, 2 of J(n-1, JB); lanes 2, 0: 1, 2 of J(n, JA)
     pp.F[0] = pp.F[1] = pp.F[2] = 0.0;
     pp.u = 1.0;
     pp.p = 0;
@@ -323,17 +359,28 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         bool capped_b = false, capped_a = false;
         if (a.do_close) M_jb = poisson_count(a, c, v0, L, U_jb, capped_b);
         if (a.do_open) M_est = poisson_count(a, c, v0, L, U_ja, capped_a);
-        const int kb = sub - JB_LANE + 1, ka = sub - JA_LANE + 1;
-        if (sub >= JB_LANE && kb <= JB_PRE && kb <= M_jb)
-            eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n - 1, 2, lid, kb, pp);
-        else if (sub >= JA_LANE && ka <= JA_PRE && ka <= M_est)
-            eval_proposal<R>(a, ftab, X, crow, c, ri, ti, q, n, 0, lid, ka, pp);
+        bool ev = false;
+        if (sub == JB_L1 && M_jb >= 1) {
+            block_proposal(w, crow, c, pp);          // drawn at entry
+            ev = true;
+        } else if (sub == JB_L2 && M_jb >= 2) {
+            draw_proposal(crow, c, ri, n - 1, 2, lid, 2, pp);
+            ev = true;
+        } else if (sub == JA_L1 && M_est >= 1) {
+            draw_proposal(crow, c, ri, n, 0, lid, 1, pp);
+            ev = true;
+        } else if (sub == JA_L2 && M_est >= 2) {
+            draw_proposal(crow, c, ri, n, 0, lid, 2, pp);
+            ev = true;
+        }
+        if (ev) field_proposal<R>(a, ftab, X, ri, ti, q, pp);
         if (capped_b && sub == 0) atomicOr(&a.st->status, ST_POISSON);
     }
-    if (active) {
-        // bonded terms shared by the lanes
+    if (active && e0.x >= 0) {
+        // bonded terms shared by the lanes: k = sub, sub + LPA, ...
+        bonded_slot_grad_pos(s, e0, ba, bb, bc, ri, a.tp, fb);
         const int4 *brow = a.ls.bslot + (int64_t)s * BTMAX;
-        for (int k = sub; k < BTMAX; k += LPA) {
+        for (int k = sub + LPA; k < BTMAX; k += LPA) {
             const int4 e = brow[k];
             if (e.x < 0) break;
             bonded_slot_grad(s, e, X, ri, a.tp, fb);
@@ -365,8 +412,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     if (a.do_close) {
         if (BOUNCE) {
             const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            jump_chain<R, LPA, JB_PRE>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2,
-                                       M_jb, M_jb, JB_LANE, pp, sub, tally);
+            jump_chain<R, LPA, 2>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2, M_jb,
+                                  M_jb, JB_L1, JB_L2, pp, sub, tally);
         }
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
     }
@@ -377,8 +424,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             bool capped = false;
             const int32_t M = active ? poisson_count(a, c, v0, L, U_ja, capped) : 0;
             if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
-            jump_chain<R, LPA, JA_PRE>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M,
-                                       M_est, JA_LANE, pp, sub, tally);
+            jump_chain<R, LPA, 2>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M, M_est,
+                                  JA_L1, JA_L2, pp, sub, tally);
         }
     }
     if (active && sub == 0) {
@@ -465,7 +512,8 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     none.u = 1.0;
     none.p = 0;
     jump_chain<R, PB, 1>(a, tab, X, a.ls.clist + (int64_t)s * a.ls.ccap, c, lid, rep, ri,
-                         mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, 0, none, sub, tally);
+                         mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, 0, 0, none, sub,
+                         tally);
     if (active && sub == 0) {
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];

@@ -70,3 +70,10 @@ def test_argument_errors_need_no_gpu():
     assert L.bounce_workspace_size(ctx, C.byref(nb)) == _abi.E_STATE
     assert L.bounce_status_string(_abi.E_SKIN).decode().startswith("an atom moved")
     L.bounce_destroy(ctx)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libbounce.so the package refuses to run: there is no fallback."""
+    import paper_2002_07109_amd._abi as abi
+    with pytest.raises(ImportError):
+        abi.load(str(tmp_path / "libbounce.so"))
