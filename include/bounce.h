@@ -186,10 +186,12 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
 /* Kernel timing for measurement, with HIP events on the bound stream; returns
    the mean duration per launch in ms.  Synchronous.
      which = 0: the standalone F_0 pair kernel at the current positions,
-     which = 1: the list build,
      which = 2: the integrator kernel with its kicks, jumps and drifts off
                 (bonded terms and random draws; velocities rewritten unchanged),
-   each as reps back-to-back launches that leave the trajectory unchanged;
+                both as reps back-to-back launches that leave the trajectory
+                unchanged;
+     which = 1: the list build, reps times at the current positions (positions
+                and velocities stay; the following steps use these lists);
      which = 3: the integrator kernel of reps real steps (advances the
                 trajectory by reps + 1 steps; only that kernel is timed). */
 bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);

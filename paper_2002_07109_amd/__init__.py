@@ -217,10 +217,10 @@ class Simulation:
 
     def profile_kernel(self, which, reps):
         """Mean duration (ms) per launch, timed with HIP events on the bound stream:
-        0 the F_0 pair kernel, 1 the list build, 2 the integrator kernel with
-        kicks, jumps and drifts off (all three leave the trajectory unchanged),
-        3 the integrator kernel of `reps` real steps (advances the trajectory
-        by reps + 1 steps)."""
+        0 the F_0 pair kernel, 2 the integrator kernel with kicks, jumps and
+        drifts off (both leave the trajectory unchanged), 1 the list build at
+        the current positions (later steps use these lists), 3 the integrator
+        kernel of `reps` real steps (advances the trajectory by reps + 1 steps)."""
         ms = C.c_double()
         check(self.L.bounce_profile_kernel(self.ctx, int(which), int(reps), C.byref(ms)), self.ctx,
               "bounce_profile_kernel")

@@ -210,7 +210,7 @@ constexpr int LB = 4;          // wavefronts per cell
 constexpr int LCAP = 512;      // candidate atoms staged in LDS per batch
 constexpr int LMAXI = 64;      // atoms per cell handled
 constexpr int LDIM = 12;       // candidate cells per dimension
-constexpr int LCELLS = 320;    // candidate cells kept per cell
+constexpr int LCELLS = 352;    // candidate cells kept per cell
 constexpr int LEXCL = 8;       // exclusions per atom held in registers
 
 // One workgroup per cell.  (1) Wavefront 0 enumerates the candidate cells

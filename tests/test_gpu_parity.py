@@ -227,3 +227,42 @@ def test_autotuner_picks_a_lane_count_and_keeps_results(orc, box):
     assert rel_err(g1, g0) < 1e-13
     sim.step(20)
     sim.sync()
+
+
+def test_replicas_graph_replay_equals_direct_launches():
+    systems = [relaxed_droplet(name) for name in ("r0", "r1", "r2")]
+    sa = gpu_sim(systems, DROPLET, fp64=False, use_graph=False)
+    sb = gpu_sim(systems, DROPLET, fp64=False, use_graph=True)
+    for sim in (sa, sb):
+        sim.step(25)
+        sim.sync()
+    assert np.array_equal(sa.pos.cpu().numpy(), sb.pos.cpu().numpy())
+    assert np.array_equal(sa.vel.cpu().numpy(), sb.vel.cpu().numpy())
+    for r in range(3):
+        assert sa.counters(r)["proposals"] == sb.counters(r)["proposals"]
+
+
+def test_profiling_kinds_keep_or_advance_the_trajectory(box):
+    """Kinds 0 and 2 of bounce_profile_kernel leave the trajectory as it was,
+    kind 1 keeps positions and velocities; kind 3 advances the trajectory by
+    reps + 1 steps exactly as bounce_step would."""
+    a = gpu_sim(box, BOX, fp64=True)
+    b = gpu_sim(box, BOX, fp64=True)
+    c = gpu_sim(box, BOX, fp64=True)
+    for sim in (a, b, c):
+        sim.step(5)
+        sim.sync()
+    pos0, vel0 = a.pos.cpu().numpy().copy(), a.vel.cpu().numpy().copy()
+    assert c.profile_kernel(1, 2) > 0.0
+    assert np.array_equal(c.pos.cpu().numpy(), pos0)
+    assert np.array_equal(c.vel.cpu().numpy(), vel0)
+    for kind in (0, 2):
+        assert a.profile_kernel(kind, 3) > 0.0
+    assert np.array_equal(a.pos.cpu().numpy(), pos0)
+    assert np.array_equal(a.vel.cpu().numpy(), vel0)
+    assert a.profile_kernel(3, 4) > 0.0
+    b.step(5)
+    b.sync()
+    assert a.get_step() == b.get_step() == 10
+    assert np.array_equal(a.pos.cpu().numpy(), b.pos.cpu().numpy())
+    assert np.array_equal(a.vel.cpu().numpy(), b.vel.cpu().numpy())

@@ -152,7 +152,7 @@ def maxwell_velocities(mass, temperature, seed, stream=3):
     return rng.standard_normal((mass.shape[0], 3)) * sd[:, None]
 
 
-def water_box(n_side=20, box_len=62.0, temperature=300.0, seed=0, cell_size=4.4):
+def water_box(n_side=20, box_len=62.0, temperature=300.0, seed=0, cell_size=3.8):
     """Periodic cube of n_side^3 waters on a lattice (the 24,000-atom box is n_side=20)."""
     rng = _rng(seed, 4)
     spacing = box_len / n_side
@@ -182,7 +182,7 @@ def droplet_grid(pos, cell_size, margin=12.0):
     return lo, dims
 
 
-def water_droplet(n_waters=216, temperature=300.0, seed=0, cell_size=4.4, stream=5):
+def water_droplet(n_waters=216, temperature=300.0, seed=0, cell_size=3.8, stream=5):
     """Non-periodic droplet of the n_waters lattice waters nearest the centre
     (216 waters = the 648-atom droplet)."""
     rng = _rng(seed, stream)
@@ -196,7 +196,7 @@ def water_droplet(n_waters=216, temperature=300.0, seed=0, cell_size=4.4, stream
 
 
 def droplet_batch(n_replicas=64, min_atoms=300, max_atoms=6000, temperature=300.0, seed=0,
-                  cell_size=4.4):
+                  cell_size=3.8):
     """Uneven droplets: atom counts uniform in [min_atoms, max_atoms], rounded to whole waters."""
     rng = _rng(seed, 0xC2)
     n_atoms = rng.integers(min_atoms, max_atoms + 1, size=n_replicas)
