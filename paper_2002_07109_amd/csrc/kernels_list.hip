@@ -52,8 +52,8 @@ __global__ void k_bin(int32_t n, const double *__restrict__ pos, const RepInfo *
 }
 
 // Exclusive scan of the cell counts into cell_start (and the counts cleared
-// for the next build), in three launches: sums of blocks of 1024 cells, a scan
-// of those sums in one workgroup, and the scan inside each block.
+// for the next build), in two launches: the totals of blocks of 1024 cells,
+// then the scan inside each block offset by the totals of the blocks before it.
 constexpr int SCAN_B = 1024;
 
 __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t *wsum)
@@ -89,31 +89,26 @@ __global__ void __launch_bounds__(SCAN_B) k_scan_part(int32_t n_cells, ListSet l
     if (threadIdx.x == SCAN_B - 1) ls.scan_part[blockIdx.x] = incl;
 }
 
-// exclusive scan of the block sums (any number of blocks, SCAN_B at a time)
-__global__ void __launch_bounds__(SCAN_B) k_scan_top(int32_t n_blocks, ListSet ls)
-{
-    __shared__ int32_t wsum[SCAN_B / 64];
-    __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int32_t b0 = 0; b0 < n_blocks; b0 += SCAN_B) {
-        const int32_t k = b0 + threadIdx.x;
-        const int32_t v = k < n_blocks ? ls.scan_part[k] : 0;
-        const int32_t c = carry;
-        const int32_t incl = block_incl_scan(v, wsum);
-        if (k < n_blocks) ls.scan_part[k] = c + incl - v;
-        __syncthreads();
-        if (threadIdx.x == SCAN_B - 1) carry = c + incl;
-        __syncthreads();
-    }
-}
-
+// the scan inside each block, offset by the sum of the earlier blocks' totals
 __global__ void __launch_bounds__(SCAN_B) k_scan_fin(int32_t n_cells, ListSet ls)
 {
     __shared__ int32_t wsum[SCAN_B / 64];
+    __shared__ int32_t s_off;
+    int32_t o = 0;
+    for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += SCAN_B) o += ls.scan_part[b];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) o += __shfl_xor(o, m, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = o;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < SCAN_B / 64; ++w) t += wsum[w];
+        s_off = t;
+    }
+    __syncthreads();
     const int32_t k = blockIdx.x * SCAN_B + threadIdx.x;
     const int32_t v = k < n_cells ? ls.cell_count[k] : 0;
-    const int32_t incl = block_incl_scan(v, wsum) + ls.scan_part[blockIdx.x];
+    const int32_t incl = block_incl_scan(v, wsum) + s_off;
     if (k < n_cells) {
         ls.cell_start[k] = incl - v;
         ls.cell_count[k] = 0;
@@ -172,12 +167,11 @@ __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double 
     }
 }
 
-// each atom's bonded terms with their atoms as sorted positions (after the sort)
-__global__ void k_bslots(int32_t n, Topo tp, ListSet ls)
+// the bonded terms of the atom at sorted position sl (caller id g) with their
+// atoms as sorted positions (needs the whole sort done)
+__device__ void bslot_row(int32_t g, int32_t sl, const Topo &tp, const ListSet &ls)
 {
-    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int4 *row = ls.bslot + (int64_t)ls.inv_perm[g] * BTMAX;
+    int4 *row = ls.bslot + (int64_t)sl * BTMAX;
     const int32_t b = tp.bt_ptr[g], e = tp.bt_ptr[g + 1];
     for (int32_t k = 0; k < BTMAX; ++k) {
         int4 t = make_int4(-1, 0, 0, 0);
@@ -238,6 +232,9 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     const int32_t ci = blockIdx.x;
     const int32_t bi = ls.cell_start[ci], ei_all = ls.cell_start[ci + 1];
     const int32_t ei = min(ei_all, bi + LMAXI), ni = ei - bi;
+    if (ls.bslot)     // this cell's rows of the bonded-term table
+        for (int32_t k = threadIdx.x; k < ei_all - bi; k += 64 * LB)
+            bslot_row(ls.perm[bi + k], bi + k, tp, ls);
     for (int32_t i = ei + threadIdx.x; i < ei_all; i += 64 * LB) {   // atoms beyond the limit
         ls.fcnt[i] = 0;
         ls.ccnt[i] = 0;
@@ -435,12 +432,10 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_bin, dim3(nb), dim3(256), 0, sm, n, pos, reps, tp, ls, st);
     const int32_t nsb = (ls.n_cells + SCAN_B - 1) / SCAN_B;
     hipLaunchKernelGGL(k_scan_part, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_B), 0, sm, nsb, ls);
     hipLaunchKernelGGL(k_scan_fin, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
                        pos, tp, ls, st, bs.mirror_sel, bs.step_off);
-    if (ls.bslot) hipLaunchKernelGGL(k_bslots, dim3(nb), dim3(256), 0, sm, n, tp, ls);
     hipLaunchKernelGGL(k_lists, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps, cell_rep,
                        tp, ls, bs, st);
 }

@@ -351,33 +351,47 @@ void launch_atom_energy(hipStream_t sm, int32_t n, const double *pos, const doub
 }
 
 // out[seg][c] = sum over rows of segment seg of vals[row * stride + col0 + c],
-// c < width; one block per segment, fixed-order tree (deterministic)
-__global__ void __launch_bounds__(256) k_segment_sum(const int64_t *seg_off, const double *vals,
-                                                     int32_t width, int32_t stride, int32_t col0,
-                                                     double *out)
+// c < width <= 8; one 1024-thread block per segment, all columns in one pass,
+// wavefront butterflies then a fixed-order sum over the wavefronts
+// (deterministic)
+constexpr int SEG_B = 1024, SEG_W = 8;
+
+__global__ void __launch_bounds__(SEG_B) k_segment_sum(const int64_t *seg_off, const double *vals,
+                                                      int32_t width, int32_t stride, int32_t col0,
+                                                      double *out)
 {
-    __shared__ double red[256];
-    int32_t seg = blockIdx.x;
-    int64_t b = seg_off[seg], e = seg_off[seg + 1];
-    for (int32_t c = 0; c < width; ++c) {
-        double s = 0.0;
-        for (int64_t r = b + threadIdx.x; r < e; r += 256) s += vals[r * stride + col0 + c];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int32_t off = 128; off > 0; off >>= 1) {
-            if ((int32_t)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[(int64_t)seg * width + c] = red[0];
-        __syncthreads();
+    __shared__ double red[SEG_B / 64][SEG_W];
+    const int32_t seg = blockIdx.x;
+    const int64_t b = seg_off[seg], e = seg_off[seg + 1];
+    double acc[SEG_W];
+#pragma unroll
+    for (int c = 0; c < SEG_W; ++c) acc[c] = 0.0;
+    for (int64_t r = b + threadIdx.x; r < e; r += SEG_B) {
+        const double *row = vals + r * stride + col0;
+#pragma unroll
+        for (int c = 0; c < SEG_W; ++c)
+            if (c < width) acc[c] += row[c];
+    }
+#pragma unroll
+    for (int c = 0; c < SEG_W; ++c) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) acc[c] += __shfl_xor(acc[c], m, 64);
+    }
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < SEG_W; ++c) red[threadIdx.x >> 6][c] = acc[c];
+    __syncthreads();
+    if ((int32_t)threadIdx.x < width) {
+        double t = 0.0;
+        for (int w = 0; w < SEG_B / 64; ++w) t += red[w][threadIdx.x];
+        out[(int64_t)seg * width + threadIdx.x] = t;
     }
 }
 
 void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, const double *vals,
                         int32_t width, int32_t stride, int32_t col0, double *out)
 {
-    if (n_seg <= 0) return;
-    hipLaunchKernelGGL(k_segment_sum, dim3(n_seg), dim3(256), 0, sm, seg_off, vals, width, stride,
+    if (n_seg <= 0 || width > SEG_W) return;
+    hipLaunchKernelGGL(k_segment_sum, dim3(n_seg), dim3(SEG_B), 0, sm, seg_off, vals, width, stride,
                        col0, out);
 }
 
