@@ -290,6 +290,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         const TypePair<R> *tab = jump_table<R>(a);
         for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) ftab[k] = tab[k];
     }
+    // at entry: a barrier later in the kernel would make the workgroup's
+    // wavefronts wait for each other's load chains
     __syncthreads();
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = a.st->step + a.step_off;
