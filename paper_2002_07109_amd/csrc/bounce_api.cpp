@@ -438,7 +438,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[6] = L.take(32 * n);                     // x[0]
         q[7] = L.take(32 * n);                     // x[1]
         q[8] = L.take(24 * n);                     // q_build
-        q[9] = L.take(4 * n);                      // fcnt
+        q[9] = L.take(8 * n);                      // fcnt (near, far)
         q[10] = L.take(4 * n * fcap);              // flist
         q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
@@ -552,7 +552,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
         ls.x[0] = at<double4>(ws, q[6]);
         ls.x[1] = at<double4>(ws, q[7]);
         ls.q_build = at<double>(ws, q[8]);
-        ls.fcnt = at<int32_t>(ws, q[9]);
+        ls.fcnt = at<int2>(ws, q[9]);
         ls.flist = at<int32_t>(ws, q[10]);
         ls.ccnt = at<int32_t>(ws, q[11]);
         ls.clist = at<int32_t>(ws, q[11]) + c->n;
@@ -649,17 +649,19 @@ static BuildSpec main_spec(const bounce_ctx *c)
     BuildSpec b{};
     const bounce_params &p = c->p;
     if (p.integrator == BOUNCE_BJAOAJB) {
-        double rf = p.r_off + p.skin;
+        double rf = p.r_off + p.skin, rn = p.r_off + 0.5 * p.skin;
         double rmin = p.r_on - p.skin, rmax = p.r_cut + p.skin;
         b.rf2 = rf * rf;
+        b.rfn2 = rn * rn;
         b.rcmin2 = rmin > 0.0 ? rmin * rmin : 0.0;
         b.rcmax2 = rmax * rmax;
         b.rsearch = std::max(rf, rmax);
         b.want_force = 1;
         b.want_cand = 1;
     } else {
-        double rf = p.r_cut + p.skin;
+        double rf = p.r_cut + p.skin, rn = p.r_cut + 0.5 * p.skin;
         b.rf2 = rf * rf;
+        b.rfn2 = rn * rn;
         b.rsearch = rf;
         b.want_force = 1;
         b.want_cand = 0;
@@ -855,6 +857,7 @@ static BuildSpec aux_spec(const bounce_ctx *c)
     BuildSpec b{};
     double r = c->p.r_cut + 0.01;
     b.rf2 = r * r;
+    b.rfn2 = b.rf2;       // used at the build positions only: every entry near
     b.rsearch = r;
     b.want_force = 1;
     b.want_cand = 0;

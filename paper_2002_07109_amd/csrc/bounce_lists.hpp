@@ -15,8 +15,10 @@ struct ListSet {
     int2 *sinfo;          // sorted position -> (caller id, replica)
     double4 *x[2];        // sorted positions (x, y, z, type), double-buffered by step parity
     double *q_build;      // [N][3] positions at the build (skin guard)
-    int32_t *fcnt;        // force list: row length per sorted atom
-    int32_t *flist;       // [N][fcap] sorted partner positions
+    int2 *fcnt;           // force list: (near, far) entries of each sorted atom's row
+    int32_t *flist;       // [N][fcap] sorted partner positions: the near entries fill
+                          //   the row from the front, the far ones from the back
+                          //   (each part ascending in canonical order from its end)
     int32_t *ccnt;        // candidate list (jump partners)
     int32_t *clist;       // [N][ccap]
     int4 *bslot;          // [N][BTMAX] bonded terms of each sorted atom with their
@@ -30,8 +32,16 @@ struct ListSet {
 constexpr int BTMAX = 8;
 
 // what one build produces
+// A force-list row holds every partner within the list radius.  Partners
+// beyond the near radius (the force cutoff plus half the skin) at build time
+// come within the cutoff only if the pair closes by more than half the skin
+// before the next build, which is rare; a pair kernel that walks the near
+// entries first therefore finds the wavefront blocks over far entries
+// almost always out of range and skips their pair arithmetic.  Every entry is
+// still tested, so the order is a matter of speed only.
 struct BuildSpec {
     double rf2;           // force-list radius squared
+    double rfn2;          // force-list entries with r^2 < rfn2 are near, the others far
     double rcmin2;        // candidate lower radius squared (0: none)
     double rcmax2;        // candidate upper radius squared
     double rsearch;       // cell-search radius (max of the radii)

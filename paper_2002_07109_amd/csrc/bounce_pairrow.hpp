@@ -1,5 +1,7 @@
 // The pair-force sum of one atom over its list row, walked by a group of G
-// lanes (lane lig takes entries lig, lig + G, ...).
+// lanes (lane lig takes entries lig, lig + G, ...).  A row has nn entries
+// from its front and cnt - nn more from its back (slot cap - 1 downwards):
+// entry e sits at row_slot(e, nn, cap - 1 + nn).
 //
 // MODE_SHORT: (1 - chi(r)) W'_sf(r) d/r for r < r''  (F_0 pair part, Sec. IV.A)
 // MODE_FULL:  W'_sf(r) d/r for r < rc                 (BAOAB)
@@ -13,10 +15,15 @@
 
 namespace bnc {
 
+__device__ __forceinline__ int32_t row_slot(int32_t e, int32_t nn, int32_t tail)
+{
+    return e < nn ? e : tail - e;
+}
+
 template <typename R, int MODE, int G>
 __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, const double4 &xi,
                                                const BoxReg &box, const int32_t *__restrict__ row,
-                                               int32_t cnt, int32_t cap, int lig, int32_t self,
+                                               int32_t nn, int32_t cnt, int32_t cap, int lig, int32_t self,
                                                const TypePair<R> *tab_i, const PairGlobals &pg,
                                                double &ax, double &ay, double &az)
 {
@@ -26,8 +33,10 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
     // U entries per lane in flight: their position gathers are issued together,
     // and the row indices of the next block load during this block's arithmetic
     constexpr int U = 4;
-    // the first block is read within the row's capacity without waiting for
-    // its length, then masked
+    // the first block is read from the row's front within its capacity
+    // without waiting for the lengths, then masked (and, past the near part,
+    // read again from the back)
+    const int32_t tail = cap - 1 + nn;
     int32_t pn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -35,8 +44,11 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
         pn[u] = e < cap ? row[e] : -1;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (lig + u * G >= cnt) pn[u] = -1;
+    for (int u = 0; u < U; ++u) {
+        const int32_t e = lig + u * G;
+        if (e >= cnt) pn[u] = -1;
+        else if (e >= nn) pn[u] = row[tail - e];
+    }
     for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
         int32_t pj[U];
         double4 xj[U];
@@ -48,7 +60,7 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t e = e0 + (U + u) * G;
-            pn[u] = e < cnt ? row[e] : -1;
+            pn[u] = e < cnt ? row[row_slot(e, nn, tail)] : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -220,8 +220,9 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                                                    ListSet ls, BuildSpec bs, DevState *st)
 {
     __shared__ double cx[LCAP], cy[LCAP], cz[LCAP];
-    __shared__ int32_t cj[LCAP], cg[LCAP];
-    __shared__ int32_t rowf[LMAXI], rowc[LMAXI];
+    __shared__ int32_t cj[LCAP];
+    __shared__ int32_t rowf[LMAXI], rowg[LMAXI], rowc[LMAXI];
+    __shared__ double iexr2[LMAXI];
     __shared__ int32_t dcell[3][LDIM];
     __shared__ double dgap[3][LDIM];
     __shared__ int32_t cbeg[LCELLS], cnum[LCELLS], cpre[LCELLS + 1];
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
         for (int32_t k = threadIdx.x; k < ei_all - bi; k += 64 * LB)
             bslot_row(ls.perm[bi + k], bi + k, tp, ls);
     for (int32_t i = ei + threadIdx.x; i < ei_all; i += 64 * LB) {   // atoms beyond the limit
-        ls.fcnt[i] = 0;
+        ls.fcnt[i] = make_int2(0, 0);
         ls.ccnt[i] = 0;
     }
     if (ni == 0) return;                             // uniform per workgroup
@@ -247,15 +248,32 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     const double rmax2 = fmax(bs.want_force ? bs.rf2 : 0.0, bs.want_cand ? bs.rcmax2 : 0.0);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     bool overflow = ei_all > ei;
-    for (int32_t k = threadIdx.x; k < ni; k += 64 * LB) {
-        rowf[k] = rowc[k] = 0;
-        // the cell's own atoms: positions and exclusions
-        const double4 x = X[bi + k];
-        ipos[k] = x;
-        const int32_t g = mirror_id(x.w);
-        const int32_t e_b = tp.excl_ptr[g], e_n = tp.excl_ptr[g + 1] - e_b;
-        for (int32_t t = 0; t < LEXCL; ++t) iex[k][t] = t < e_n ? tp.excl_idx[e_b + t] : -1;
-        if (e_n > LEXCL) overflow = true;
+    // the cell's own atoms (on the last wavefront, while the first enumerates
+    // the candidate cells): positions, exclusions, and the largest squared
+    // distance to the atom itself or an excluded partner, computed exactly as
+    // the predicate below computes it; no candidate farther than that can be
+    // excluded, so the exclusion test runs only at or below it
+    if (w == LB - 1) {
+        for (int32_t k = lane; k < ni; k += 64) {
+            rowf[k] = rowg[k] = rowc[k] = 0;
+            const double4 x = X[bi + k];
+            ipos[k] = x;
+            const int32_t g = mirror_id(x.w);
+            const int32_t e_b = tp.excl_ptr[g], e_n = tp.excl_ptr[g + 1] - e_b;
+            double m2 = 0.0;
+            for (int32_t t = 0; t < LEXCL; ++t) {
+                const int32_t se = t < e_n ? ls.inv_perm[tp.excl_idx[e_b + t]] : -1;
+                iex[k][t] = se;     // excluded partners as sorted positions
+                if (se >= 0) {
+                    const double4 xe = X[se];
+                    double dx = x.x - xe.x, dy = x.y - xe.y, dz = x.z - xe.z;
+                    box.apply(dx, dy, dz);
+                    m2 = fmax(m2, norm2_exact(dx, dy, dz));
+                }
+            }
+            iexr2[k] = m2;
+            if (e_n > LEXCL) overflow = true;
+        }
     }
     if (w == 0) {
         const int32_t loc = ci - ri.cell_off;
@@ -356,69 +374,80 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             for (int32_t t = t_lo; t < t_hi; ++t) cj[p0 + t - lo] = jb + t;
         }
         __syncthreads();
-        // (2b) their positions and caller ids
+        // (2b) their positions
         for (int32_t f = threadIdx.x; f < nb; f += 64 * LB) {
             const double4 x = X[cj[f]];
             cx[f] = x.x;
             cy[f] = x.y;
             cz[f] = x.z;
-            cg[f] = mirror_id(x.w);
         }
         __syncthreads();
         // (3) this wavefront's atoms of the cell against the batch
         for (int32_t k = w; k < ni; k += LB) {
             const int32_t i = bi + k;
             const double4 xi = ipos[k];
+            const double exr2 = iexr2[k];
             int32_t ex_id[LEXCL];
 #pragma unroll
             for (int t = 0; t < LEXCL; ++t) ex_id[t] = iex[k][t];
-            int32_t nf = rowf[k], nc = rowc[k];
+            int32_t nf = rowf[k], ng = rowg[k], nc = rowc[k];
             int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
             int32_t *crow = ls.clist + (int64_t)i * ls.ccap;
             for (int32_t f0 = 0; f0 < nb; f0 += 64) {
                 const int32_t f = f0 + lane;
-                bool hf = false, hc = false;
+                bool hf = false, hg = false, hc = false;
                 int32_t j = -1;
                 if (f < nb) {
                     j = cj[f];
                     double dx = xi.x - cx[f], dy = xi.y - cy[f], dz = xi.z - cz[f];
                     box.apply(dx, dy, dz);
                     const double r2 = norm2_exact(dx, dy, dz);
-                    if (j != i && r2 < rmax2) {
-                        const int32_t gj = cg[f];
+                    if (r2 < rmax2) {
                         bool ex = false;
+                        if (r2 <= exr2) {      // the atom itself or possibly excluded
+                            ex = j == i;
 #pragma unroll
-                        for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == gj;
+                            for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == j;
+                        }
                         if (!ex) {
-                            hf = bs.want_force && r2 < bs.rf2;
+                            const bool in_f = bs.want_force && r2 < bs.rf2;
+                            hf = in_f && r2 < bs.rfn2;
+                            hg = in_f && !(r2 < bs.rfn2);
                             hc = bs.want_cand && r2 < bs.rcmax2 && !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
                         }
                     }
                 }
-                const uint64_t mf = __ballot(hf), mc = __ballot(hc);
-                if (hf) {
+                const uint64_t mf = __ballot(hf), mg = __ballot(hg), mc = __ballot(hc);
+                if (hf) {      // near: from the front of the row
                     const int32_t q = nf + __popcll(mf & below);
                     if (q < ls.fcap) frow[q] = j;
+                }
+                if (hg) {      // far: from the back
+                    const int32_t q = ng + __popcll(mg & below);
+                    if (q < ls.fcap) frow[ls.fcap - 1 - q] = j;
                 }
                 if (hc) {
                     const int32_t q = nc + __popcll(mc & below);
                     if (q < ls.ccap) crow[q] = j;
                 }
                 nf += __popcll(mf);
+                ng += __popcll(mg);
                 nc += __popcll(mc);
             }
             if (lane == 0) {
                 rowf[k] = nf;
+                rowg[k] = ng;
                 rowc[k] = nc;
             }
         }
         __syncthreads();
     }
     for (int32_t k = threadIdx.x; k < ni; k += 64 * LB) {
-        const int32_t nf = rowf[k], nc = rowc[k];
-        if (bs.want_force) ls.fcnt[bi + k] = min(nf, ls.fcap);
+        const int32_t nf = rowf[k], ng = rowg[k], nc = rowc[k];
+        const bool full = nf + ng > ls.fcap;     // the two ends met
+        if (bs.want_force) ls.fcnt[bi + k] = full ? make_int2(0, 0) : make_int2(nf, ng);
         if (bs.want_cand) ls.ccnt[bi + k] = min(nc, ls.ccap);
-        if (nf > ls.fcap || nc > ls.ccap) overflow = true;
+        if (full || nc > ls.ccap) overflow = true;
     }
     if (__syncthreads_or(overflow) && threadIdx.x == 0) atomicOr(&st->status, ST_CAPACITY);
 }

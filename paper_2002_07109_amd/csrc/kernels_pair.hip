@@ -75,8 +75,9 @@ __device__ __forceinline__ const TypePair<float> *pair_table<float>(const PairAr
 template <>
 __device__ __forceinline__ const TypePair<double> *pair_table<double>(const PairArgs &a) { return a.tab_d; }
 
-// G lanes per atom (4, 8, 16 or 32; chosen by the autotuner)
-template <typename R, int MODE, int G>
+// G lanes per atom (4, 8, 16 or 32; chosen by the autotuner).  ONE: a single
+// replica, whose box the force modes keep in scalar registers.
+template <typename R, int MODE, int G, bool ONE = false>
 __global__ void __launch_bounds__(256) k_pair(PairArgs a)
 {
     __shared__ TypePair<R> tab[MAXT * MAXT];
@@ -121,20 +122,23 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const int ti = mirror_type(xi.w);
         const int2 si = a.ls.sinfo[s];
         gi = si.x;
-        const BoxReg box(load_rep(a.reps, a.single_rep, si.y));
+        const BoxReg box(ONE ? a.reps[0] : load_rep(a.reps, a.single_rep, si.y));
         const int32_t *row;
-        int32_t cnt, cap;
+        int32_t nn, cnt, cap;
         if (a.list_sel == 1) {
             row = a.ls.clist + (int64_t)s * a.ls.ccap;
             cap = a.ls.ccap;
-            cnt = min(a.ls.ccnt[s], cap);
+            nn = cnt = min(a.ls.ccnt[s], cap);
         } else {
             row = a.ls.flist + (int64_t)s * a.ls.fcap;
             cap = a.ls.fcap;
-            cnt = min(a.ls.fcnt[s], cap);
+            const int2 fc = a.ls.fcnt[s];   // the list build keeps fc.x + fc.y <= cap
+            nn = fc.x;
+            cnt = fc.x + fc.y;
         }
+        const int32_t tail = cap - 1 + nn;
         if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
-            pair_force_row<R, MODE, G>(X, xi, box, row, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
+            pair_force_row<R, MODE, G>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
         } else {
         // energies and parameter-gradient bases: U entries per lane in flight
         constexpr int U = 4;
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int32_t e = e0 + u * G;
-                pj[u] = e < cnt ? row[e] : -1;
+                pj[u] = e < cnt ? row[row_slot(e, nn, tail)] : -1;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) xj[u] = X[pj[u] >= 0 ? pj[u] : s];
@@ -257,9 +261,18 @@ static void launch_pair_g(hipStream_t sm, int mode, const PairArgs &a)
 {
     dim3 grid(((int64_t)a.n * G + 255) / 256), block(256);
     switch (mode) {
-        case MODE_SHORT: hipLaunchKernelGGL((k_pair<R, MODE_SHORT, G>), grid, block, 0, sm, a); break;
-        case MODE_FULL: hipLaunchKernelGGL((k_pair<R, MODE_FULL, G>), grid, block, 0, sm, a); break;
-        case MODE_LONG: hipLaunchKernelGGL((k_pair<R, MODE_LONG, G>), grid, block, 0, sm, a); break;
+        case MODE_SHORT:
+            if (a.single_rep) hipLaunchKernelGGL((k_pair<R, MODE_SHORT, G, true>), grid, block, 0, sm, a);
+            else hipLaunchKernelGGL((k_pair<R, MODE_SHORT, G>), grid, block, 0, sm, a);
+            break;
+        case MODE_FULL:
+            if (a.single_rep) hipLaunchKernelGGL((k_pair<R, MODE_FULL, G, true>), grid, block, 0, sm, a);
+            else hipLaunchKernelGGL((k_pair<R, MODE_FULL, G>), grid, block, 0, sm, a);
+            break;
+        case MODE_LONG:
+            if (a.single_rep) hipLaunchKernelGGL((k_pair<R, MODE_LONG, G, true>), grid, block, 0, sm, a);
+            else hipLaunchKernelGGL((k_pair<R, MODE_LONG, G>), grid, block, 0, sm, a);
+            break;
         case MODE_ENERGY: hipLaunchKernelGGL((k_pair<R, MODE_ENERGY, G>), grid, block, 0, sm, a); break;
         case MODE_DBWD: hipLaunchKernelGGL((k_pair<R, MODE_DBWD, G>), grid, block, 0, sm, a); break;
     }
@@ -402,10 +415,26 @@ __global__ void k_list_to_global(int32_t n, ListSet ls, int32_t which, int32_t *
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int32_t g = ls.perm[s];
-    const int32_t *row = which == 0 ? ls.flist + (int64_t)s * ls.fcap : ls.clist + (int64_t)s * ls.ccap;
-    int32_t c = which == 0 ? ls.fcnt[s] : ls.ccnt[s];
-    cnt_global[g] = c;
-    for (int32_t k = 0; k < c && k < cap; ++k) col_global[(int64_t)g * cap + k] = ls.perm[row[k]];
+    int32_t *out = col_global + (int64_t)g * cap;
+    if (which != 0) {
+        const int32_t *row = ls.clist + (int64_t)s * ls.ccap;
+        const int32_t c = ls.ccnt[s];
+        cnt_global[g] = c;
+        for (int32_t k = 0; k < c && k < cap; ++k) out[k] = ls.perm[row[k]];
+        return;
+    }
+    // force rows: merge the near part (front, ascending) and the far part
+    // (back, ascending from the last slot) back into canonical order
+    const int32_t *row = ls.flist + (int64_t)s * ls.fcap;
+    const int2 c = ls.fcnt[s];
+    cnt_global[g] = c.x + c.y;
+    int32_t a = 0, b = 0, k = 0;
+    while ((a < c.x || b < c.y) && k < cap) {
+        const int32_t u = a < c.x ? row[a] : INT32_MAX;
+        const int32_t v = b < c.y ? row[ls.fcap - 1 - b] : INT32_MAX;
+        if (u < v) { out[k++] = ls.perm[u]; ++a; }
+        else { out[k++] = ls.perm[v]; ++b; }
+    }
 }
 
 void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
