@@ -63,6 +63,17 @@ enum { BOUNCE_PH_JA = 0, BOUNCE_PH_O = 1, BOUNCE_PH_JB = 2 };  /* random-stream 
 enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8 };
 /* lists for bounce_get_list */
 enum { BOUNCE_LIST_FORCE = 0, BOUNCE_LIST_CAND = 1 };
+/* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may
+   depend on the types of both atoms).  ATOM: every partner of an atom of type a
+   has the bound L_a = max_b L_ab (one Poisson count over all candidates, a
+   uniform partner).  PAIR: a partner of type b has its own bound L_ab; the
+   per-pair Poisson clocks are superposed (Sec. II.B), so one count has mean
+   beta |v| dt/2 sum_j L_ab and each proposal picks j with probability
+   proportional to its bound.  Both sample the same process; PAIR proposes
+   fewer jumps when the bounds differ by type.  Bounds are used as integer
+   multiples Lq_ab of a unit per atom type, 2^-20 bound_scale L_a, with
+   Lq_ab = ceil(2^20 L_ab / L_a) (ATOM: Lq_ab = 2^20). */
+enum { BOUNCE_RATE_ATOM = 0, BOUNCE_RATE_PAIR = 1 };
 
 typedef struct {
     int32_t integrator;        /* BOUNCE_BJAOAJB or BOUNCE_BAOAB                          */
@@ -85,7 +96,7 @@ typedef struct {
     uint64_t seed;             /* Philox key word 0                                        */
     int64_t event_capacity;    /* events kept when log_events = 1                          */
     int32_t pair_lanes;        /* lanes per atom in the pair kernel: 4, 8, 16, 32 (0 = 8)  */
-    int32_t reserved;
+    int32_t rate_mode;         /* BOUNCE_RATE_ATOM or BOUNCE_RATE_PAIR (fixed at create)   */
 } bounce_params;
 
 typedef struct {
@@ -167,6 +178,10 @@ bounce_status bounce_get_list(bounce_ctx *ctx, int32_t which, int64_t *row_ptr_h
                               int32_t *col_host, int64_t cap);
 /* Rate bounds: L_ab_host[n_types^2] and L_a_host[n_types] (before bound_scale). */
 bounce_status bounce_rate_bounds(const bounce_ctx *ctx, double *L_ab_host, double *L_a_host);
+/* The bounds the jump step uses (rate_mode): integer weights Lq_host[n_types^2]
+   and units unit_host[n_types] (bound_scale applied); the bound of a partner of
+   type b of an atom of type a is Lq[a][b] * unit[a].  Synchronous, host only. */
+bounce_status bounce_rate_weights(const bounce_ctx *ctx, uint32_t *Lq_host, double *unit_host);
 /* Apply one J half-step alone (Sec. IV.B step J) at the current positions with
    the current candidate lists, random stream (step, phase).  Synchronous. */
 bounce_status bounce_jump_halfstep(bounce_ctx *ctx, int64_t step, int32_t phase);

@@ -158,6 +158,30 @@ void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a)
             if (L_ab[a * nt + b] > L_a[a]) L_a[a] = L_ab[a * nt + b];
 }
 
+/* The bounds as integer weights per atom type a: ORC_RATE_ATOM gives every
+   partner type the weight 2^20 (bound L_a, Sec. IV.B); ORC_RATE_PAIR rounds
+   2^20 L_ab / L_a up to an integer (Sec. V: bounds per pair of types), after
+   taking off 1e-4, so that two computations of L_ab that agree to 1e-12 give
+   the same weight (the bound then falls short of L_ab by at most 1e-4 of a
+   unit, ~1e-10 L_a, far inside the margin L_ab already carries).  The unit
+   of row a is bound_scale L_a 2^-20. */
+void orc_rate_weights(const orc_params *p, uint32_t *Lq, double *unit)
+{
+    double L_ab[ORC_MAXT * ORC_MAXT], L_a[ORC_MAXT];
+    const int nt = p->n_types;
+    const double one = (double)(1u << ORC_WEIGHT_BITS);
+    orc_rate_bounds(p, L_ab, L_a);
+    for (int a = 0; a < nt; ++a) {
+        unit[a] = p->bound_scale * L_a[a] / one;
+        for (int b = 0; b < nt; ++b) {
+            uint32_t w = 1u << ORC_WEIGHT_BITS;
+            if (p->rate_mode == ORC_RATE_PAIR && L_a[a] > 0.0)
+                w = (uint32_t)ceil(L_ab[a * nt + b] / L_a[a] * one - ORC_WEIGHT_SLACK);
+            Lq[a * nt + b] = w;
+        }
+    }
+}
+
 /* Eq. R_i with a scalar mass: v - 2 (v.F)/|F|^2 F */
 void orc_reflect(const double v[3], const double F[3], double out[3])
 {
@@ -475,16 +499,15 @@ void orc_energies(const orc_params *p, const orc_topology *t, const double *q, c
 /* J step (Sec. IV.B, with Sec. V partners and Sec. III.D thinning)          */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    double L_a[ORC_MAXT];
+    uint32_t Lq[ORC_MAXT * ORC_MAXT];
+    double unit[ORC_MAXT];
     double beta;
 } jump_consts;
 
 static jump_consts make_jump_consts(const orc_params *p)
 {
     jump_consts jc;
-    double L_ab[ORC_MAXT * ORC_MAXT];
-    orc_rate_bounds(p, L_ab, jc.L_a);
-    for (int a = 0; a < p->n_types; ++a) jc.L_a[a] *= p->bound_scale;
+    orc_rate_weights(p, jc.Lq, jc.unit);
     jc.beta = 1.0 / (ORC_KB * p->temperature);
     return jc;
 }
@@ -496,11 +519,33 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
                      orc_counters *cnt)
 {
     int status = ORC_OK;
+    const int nt = p->n_types, a = t->type[i];
     double v0 = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
-    double L = jc->L_a[t->type[i]];
-    if (nc == 0 || v0 == 0.0 || L == 0.0) return status;
-    /* one Poisson count for all partners: they share the bound beta |v_i| L */
-    double mu = (double)nc * jc->beta * v0 * L * (0.5 * p->dt);
+    /* the candidates grouped by class -- the partner's type under ORC_RATE_PAIR,
+       a single class under ORC_RATE_ATOM -- each class in canonical order; a
+       partner of class b has the bound Lq[a][b] * unit[a] */
+    const int ncls = p->rate_mode == ORC_RATE_PAIR ? nt : 1;
+    int32_t ncl[ORC_MAXT] = {0};
+    int32_t *grp = (int32_t *)malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
+    int32_t *cls_start[ORC_MAXT];
+    {
+        int32_t k = 0;
+        for (int b = 0; b < ncls; ++b) {
+            cls_start[b] = grp + k;
+            for (int32_t m = 0; m < nc; ++m)
+                if (ncls == 1 || t->type[cand[m]] == b) grp[k++] = cand[m];
+            ncl[b] = (int32_t)(grp + k - cls_start[b]);
+        }
+    }
+    uint64_t W = 0;     /* sum over candidates of their integer weights */
+    for (int b = 0; b < ncls; ++b) W += (uint64_t)ncl[b] * jc->Lq[a * nt + b];
+    const double unit = jc->unit[a];
+    if (nc == 0 || v0 == 0.0 || W == 0 || unit == 0.0) {
+        free(grp);
+        return status;
+    }
+    /* superposed Poisson clocks: one count with mean beta |v_i| dt/2 sum_j L_ij */
+    double mu = (double)W * jc->beta * v0 * unit * (0.5 * p->dt);
     uint64_t w[4];
     draw(p, step, phase, i, 0, w);
     double U = orc_u01(w[0]);
@@ -508,14 +553,25 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
         ++M;
-        if (M > p->max_proposals) return ORC_E_POISSON_CAP;
+        if (M > p->max_proposals) {
+            free(grp);
+            return ORC_E_POISSON_CAP;
+        }
         term *= mu / (double)M;
         cdf += term;
     }
     for (int64_t k = 1; k <= M; ++k) {
         draw(p, step, phase, i, (uint64_t)k, w);
-        int32_t jidx = (int32_t)orc_umulh(w[0], (uint64_t)nc);
-        int32_t j = cand[jidx];
+        /* partner j with probability weight_j / W: X uniform on [0, W), then
+           the class whose weight range holds X and the member within it */
+        uint64_t X = orc_umulh(w[0], W), lo = 0;
+        int b = 0;
+        while (X >= lo + (uint64_t)ncl[b] * jc->Lq[a * nt + b]) {
+            lo += (uint64_t)ncl[b] * jc->Lq[a * nt + b];
+            ++b;
+        }
+        int32_t j = cls_start[b][(X - lo) / jc->Lq[a * nt + b]];
+        const double L = (double)jc->Lq[a * nt + b] * unit;   /* this proposal's bound */
         double u = orc_u01(w[1]);
         double d[3], F[3];
         min_image(p, q + 3 * i, q + 3 * j, d);
@@ -548,6 +604,7 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
         }
         if (ev) ++*n_ev;
     }
+    free(grp);
     return status;
 }
 

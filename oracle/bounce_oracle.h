@@ -36,6 +36,19 @@ enum { ORC_COUL_BARE = 0, ORC_COUL_EWALD = 1 };
 enum { ORC_PH_JA = 0, ORC_PH_O = 1, ORC_PH_JB = 2 };
 /* gradient components */
 enum { ORC_G_BONDED = 1, ORC_G_SHORT = 2, ORC_G_LONG = 4, ORC_G_FULL = 8 };
+/* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may
+   depend on the types of both atoms).  ATOM: every partner of an atom of type a
+   gets the bound L_a = max_b L_ab, one Poisson count over all candidates.
+   PAIR: partner j of type b gets the bound L_ab; the per-pair Poisson clocks
+   are superposed (Sec. II.B), so the count has mean beta |v| dt/2 sum_j L_ab
+   and each proposal picks j with probability proportional to its bound. */
+enum { ORC_RATE_ATOM = 0, ORC_RATE_PAIR = 1 };
+/* bounds are used as integer multiples of a unit per atom type: L_ab is
+   rounded up to Lq_ab / 2^20 of L_a (less a slack of 1e-4 of a unit), which
+   keeps it a bound and makes the weighted partner draw exact integer
+   arithmetic */
+#define ORC_WEIGHT_BITS 20
+#define ORC_WEIGHT_SLACK 1e-4
 /* status codes (same meaning as the GPU library's) */
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_SKIN = -4, ORC_E_BOUND = -5,
        ORC_E_POISSON_CAP = -6, ORC_E_NONFINITE = -7, ORC_E_GRID = -9 };
@@ -55,7 +68,7 @@ typedef struct {
     double cell_size;                       /* canonical-order cell grid            */
     double grid_origin[3];                  /* droplet grid                         */
     int32_t grid_dims[3];
-    int32_t pad0;
+    int32_t rate_mode;                      /* ORC_RATE_ATOM or ORC_RATE_PAIR       */
     uint64_t seed, replica;                 /* Philox key                           */
     double charge[ORC_MAXT], eps[ORC_MAXT], sigma[ORC_MAXT];
 } orc_params;
@@ -92,6 +105,10 @@ void orc_pair_wsf(const orc_params *p, int a, int b, double r, double *w, double
 double orc_chi(const orc_params *p, double r);
 /* L_ab >= sup |chi W'_sf| per type pair (n_types x n_types) and L_a = max_b L_ab */
 void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a);
+/* integer bound weights Lq_ab = ceil(2^20 L_ab / L_a - 1e-4) (n_types x n_types) and
+   the unit of each row, bound_scale L_a 2^-20: the bound of pair type ab is
+   Lq_ab * unit_a (ORC_RATE_ATOM uses Lq_ab = 2^20 for every b) */
+void orc_rate_weights(const orc_params *p, uint32_t *Lq, double *unit);
 /* reflection of v on F (scalar mass) */
 void orc_reflect(const double v[3], const double F[3], double out[3]);
 

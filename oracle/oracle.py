@@ -20,6 +20,8 @@ MAXT = 8
 BOUNCE, BAOAB = 0, 1
 COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
+RATE_ATOM, RATE_PAIR = 0, 1
+WEIGHT_BITS = 20
 G_BONDED, G_SHORT, G_LONG, G_FULL = 1, 2, 4, 8
 STATUS = {0: "OK", -1: "ARG", -4: "SKIN", -5: "BOUND", -6: "POISSON_CAP", -7: "NONFINITE",
           -9: "GRID"}
@@ -47,7 +49,7 @@ class Params(C.Structure):
                 ("skin", C.c_double), ("ewald_alpha", C.c_double), ("bound_scale", C.c_double),
                 ("box", C.c_double * 3), ("cell_size", C.c_double),
                 ("grid_origin", C.c_double * 3), ("grid_dims", C.c_int32 * 3),
-                ("pad0", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint64),
+                ("rate_mode", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("charge", C.c_double * MAXT), ("eps", C.c_double * MAXT),
                 ("sigma", C.c_double * MAXT)]
 
@@ -91,6 +93,7 @@ def lib():
         L.orc_pair_wsf.argtypes = [P, C.c_int, C.c_int, C.c_double, vp, vp]
         L.orc_chi.argtypes = [P, C.c_double]; L.orc_chi.restype = C.c_double
         L.orc_rate_bounds.argtypes = [P, vp, vp]
+        L.orc_rate_weights.argtypes = [P, vp, vp]
         L.orc_reflect.argtypes = [vp, vp, vp]
         L.orc_sort_order.argtypes = [P, i32, vp, vp, vp]; L.orc_sort_order.restype = C.c_int
         L.orc_build_list.argtypes = [P, T, vp, C.c_double, C.c_double, vp, vp, vp, i64]
@@ -119,7 +122,7 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
                 temperature=300.0, r_on=5.0, r_off=6.0, r_cut=9.0, skin=2.0, ewald_alpha=0.35,
                 rebuild_interval=10, seed=0, replica=0, bound_scale=1.0, max_proposals=100000,
                 charge=None, eps=None, sigma=None, periodic=None, box=None, cell_size=None,
-                grid_origin=None, grid_dims=None):
+                grid_origin=None, grid_dims=None, rate_mode=RATE_ATOM):
     """Parameters for the oracle; geometry defaults are taken from a WaterSystem."""
     p = Params()
     p.integrator = integrator
@@ -134,6 +137,7 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
     p.ewald_alpha, p.bound_scale = ewald_alpha, bound_scale
     p.rebuild_interval, p.max_proposals = rebuild_interval, max_proposals
     p.seed, p.replica = seed, replica
+    p.rate_mode = rate_mode
     if sys is not None:
         from workloads import tip3p_params
         ff = tip3p_params()
@@ -228,6 +232,14 @@ def rate_bounds(p):
     L_a = np.zeros(nt)
     lib().orc_rate_bounds(C.byref(p), _ptr(L_ab), _ptr(L_a))
     return L_ab.reshape(nt, nt), L_a
+
+
+def rate_weights(p):
+    nt = p.n_types
+    Lq = np.zeros(nt * nt, np.uint32)
+    unit = np.zeros(nt)
+    lib().orc_rate_weights(C.byref(p), _ptr(Lq), _ptr(unit))
+    return Lq.reshape(nt, nt), unit
 
 
 def reflect(v, F):

@@ -14,12 +14,14 @@ import numpy as np
 
 from . import _abi
 from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_SHORT,
-                   LIST_CAND, LIST_FORCE, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, BounceError,
+                   LIST_CAND, LIST_FORCE, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, RATE_ATOM,
+                   RATE_PAIR, BounceError,
                    bounce_counters, bounce_event, bounce_params, bounce_system, check)
 
 __all__ = ["lib", "Simulation", "DirectEnergy", "make_params", "BounceError", "BJAOAJB", "BAOAB",
            "PAIR_FP32", "PAIR_FP64", "COUL_BARE", "COUL_EWALD", "PH_JA", "PH_O", "PH_JB",
-           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "LIST_FORCE", "LIST_CAND"]
+           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
+           "RATE_PAIR"]
 
 
 def lib():
@@ -29,12 +31,13 @@ def lib():
 
 def make_params(**kw) -> bounce_params:
     """bounce_params with defaults: BOUNCE, FP32 pair math, dt = 1 fs, gamma = 1/ps,
-    300 K, r'/r'' = 6/7, rc = 9, skin 2, alpha 0.35, K = 10."""
+    300 K, r'/r'' = 6/7, rc = 9, skin 2, alpha 0.35, K = 10, one rate bound per
+    atom type (RATE_ATOM)."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
-             pair_lanes=0)
+             pair_lanes=0, rate_mode=RATE_ATOM)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():
@@ -210,6 +213,15 @@ class Simulation:
         check(self.L.bounce_rate_bounds(self.ctx, _ptr(lab), _ptr(la)), self.ctx,
               "bounce_rate_bounds")
         return lab.reshape(nt, nt), la
+
+    def rate_weights(self):
+        """Integer bound weights Lq[a][b] and units unit[a] of the jump step: the
+        bound of a partner of type b of an atom of type a is Lq[a][b] * unit[a]."""
+        nt = self.n_types
+        lq, unit = np.zeros(nt * nt, np.uint32), np.zeros(nt)
+        check(self.L.bounce_rate_weights(self.ctx, _ptr(lq), _ptr(unit)), self.ctx,
+              "bounce_rate_weights")
+        return lq.reshape(nt, nt), unit
 
     def jump_halfstep(self, step, phase):
         check(self.L.bounce_jump_halfstep(self.ctx, int(step), int(phase)), self.ctx,

@@ -20,6 +20,7 @@ COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
 G_BONDED, G_SHORT, G_LONG, G_FULL = 1, 2, 4, 8
 LIST_FORCE, LIST_CAND = 0, 1
+RATE_ATOM, RATE_PAIR = 0, 1
 
 
 class bounce_params(C.Structure):
@@ -30,7 +31,7 @@ class bounce_params(C.Structure):
                 ("r_on", C.c_double), ("r_off", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("ewald_alpha", C.c_double), ("bound_scale", C.c_double),
                 ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64),
-                ("pair_lanes", C.c_int32), ("reserved", C.c_int32)]
+                ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32)]
 
 
 class bounce_system(C.Structure):
@@ -76,6 +77,7 @@ SIGNATURES = {
     "bounce_get_events": (i32, [ctx_p, vp, i64, _P(i64)]),
     "bounce_get_list": (i32, [ctx_p, i32, vp, vp, i64]),
     "bounce_rate_bounds": (i32, [ctx_p, vp, vp]),
+    "bounce_rate_weights": (i32, [ctx_p, vp, vp]),
     "bounce_jump_halfstep": (i32, [ctx_p, i64, i32]),
     "bounce_direct_energy": (i32, [ctx_p, vp, vp, vp]),
     "bounce_direct_energy_bwd": (i32, [ctx_p, vp, vp, vp, vp, vp]),

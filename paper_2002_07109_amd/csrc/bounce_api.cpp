@@ -86,6 +86,8 @@ struct bounce_ctx {
     std::vector<int32_t> type, rep_of, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, angle_ijk;
     std::vector<double> mass, acc_m, inv_mass, ou_c2, bond_kr, angle_kt, tparams;
     std::vector<double> L_ab, L_a;
+    std::vector<uint32_t> Lq;     // [MAXT][MAXT] integer bound weights of the jump step
+    int32_t ncls = 1;             // candidate classes: n_types for BOUNCE_RATE_PAIR, else 1
     std::vector<TypePair<float>> tab_f;     // jump-field pair constants per type pair
     std::vector<TypePair<double>> tab_d;
     int32_t n_cells = 0, fcap = 0, ccap = 0, acap = 0, xcap = 0;
@@ -103,10 +105,11 @@ struct bounce_ctx {
     Event *d_events = nullptr;
     const TypePair<float> *d_tab_f = nullptr;
     const TypePair<double> *d_tab_d = nullptr;
-    double *d_La = nullptr, *d_tparams = nullptr, *d_fpair = nullptr, *d_atom = nullptr,
+    double *d_unit = nullptr, *d_tparams = nullptr, *d_fpair = nullptr, *d_atom = nullptr,
            *d_seg = nullptr, *d_ou_c2 = nullptr;
     int64_t *d_rep_off = nullptr, *d_one_seg = nullptr;
     int32_t *d_cell_rep = nullptr;
+    uint32_t *d_Lq = nullptr;
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
     // schedule
@@ -164,6 +167,7 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->integrator == BOUNCE_BJAOAJB && !(p->r_on > 0 && p->r_off > p->r_on)) return BOUNCE_E_ARG;
     if (p->rebuild_interval < 1 || p->max_proposals < 1) return BOUNCE_E_ARG;
     if (!(p->bound_scale > 0)) return BOUNCE_E_ARG;
+    if (p->rate_mode != BOUNCE_RATE_ATOM && p->rate_mode != BOUNCE_RATE_PAIR) return BOUNCE_E_ARG;
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
@@ -217,11 +221,34 @@ static void make_bounds(bounce_ctx *c)
             tf.qq = (float)qq; tf.eps4 = (float)(4.0 * eps); tf.sig2 = (float)(sig * sig);
             tf.du_rc = (float)drc;
         }
+    c->Lq.assign(MAXT * MAXT, 1u << WEIGHT_BITS);
+    c->ncls = 1;
     if (c->p.integrator != BOUNCE_BJAOAJB) return;
     for (int a = 0; a < c->nt; ++a)
         for (int b = a; b < c->nt; ++b) c->L_ab[a * c->nt + b] = c->L_ab[b * c->nt + a] = ff.bound(a, b);
     for (int a = 0; a < c->nt; ++a)
         for (int b = 0; b < c->nt; ++b) c->L_a[a] = std::max(c->L_a[a], c->L_ab[a * c->nt + b]);
+    // per-type-pair bounds as integer weights of the row unit L_a 2^-20, rounded
+    // up after a slack of 1e-4 of a unit (bounds that agree to 1e-12 with
+    // another computation of them give the same weights)
+    if (c->p.rate_mode == BOUNCE_RATE_PAIR) {
+        c->ncls = c->nt;
+        const double one = (double)(1u << WEIGHT_BITS);
+        for (int a = 0; a < c->nt; ++a)
+            for (int b = 0; b < c->nt; ++b)
+                if (c->L_a[a] > 0.0)
+                    c->Lq[a * c->nt + b] =
+                        (uint32_t)std::ceil(c->L_ab[a * c->nt + b] / c->L_a[a] * one - WEIGHT_SLACK);
+    }
+}
+
+// unit of each atom type's bound weights: bound_scale L_a 2^-20
+static std::vector<double> bound_units(const bounce_ctx *c)
+{
+    std::vector<double> u(MAXT, 0.0);
+    for (int a = 0; a < c->nt && a < (int)c->L_a.size(); ++a)
+        u[a] = c->p.bound_scale * c->L_a[a] / (double)(1u << WEIGHT_BITS);
+    return u;
 }
 
 bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
@@ -385,7 +412,7 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
-        angle_ijk, angle_kt, reps, La, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
+        angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep;
     size_t ls[2][15];
 };
@@ -410,7 +437,8 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.angle_ijk = L.take(4 * std::max<size_t>(1, c->angle_ijk.size()));
     o.angle_kt = L.take(8 * std::max<size_t>(1, c->angle_kt.size()));
     o.reps = L.take(sizeof(RepInfo) * R);
-    o.La = L.take(8 * MAXT);
+    o.unit = L.take(8 * MAXT);
+    o.Lq = L.take(4 * MAXT * MAXT);
     o.tparams = L.take(8 * 3 * MAXT);
     o.tab_f = L.take(sizeof(TypePair<float>) * MAXT * MAXT);
     o.tab_d = L.take(sizeof(TypePair<double>) * MAXT * MAXT);
@@ -440,7 +468,8 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[8] = L.take(24 * n);                     // q_build
         q[9] = L.take(8 * n);                      // fcnt (near, far)
         q[10] = L.take(4 * n * fcap);              // flist
-        q[11] = L.take(4 * n * std::max<size_t>(1, ccap) + 4 * n);  // ccnt + clist
+        const size_t ncls = k == 0 ? (size_t)c->ncls : 1;
+        q[11] = L.take(4 * n * ncls * std::max<size_t>(1, ccap) + 4 * n * ncls);  // ccnt + clist
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
         q[13] = L.take(sizeof(int2) * n);                               // sinfo
         q[14] = L.take(4 * ((size_t)c->n_cells / 1024 + 2));            // scan_part
@@ -496,9 +525,8 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     HIPCHK(c, up(sm, ws, o.angle_ijk, c->angle_ijk));
     HIPCHK(c, up(sm, ws, o.angle_kt, c->angle_kt));
     HIPCHK(c, up(sm, ws, o.reps, c->reps));
-    std::vector<double> La(MAXT, 0.0);
-    for (int a = 0; a < c->nt; ++a) La[a] = c->L_a[a] * c->p.bound_scale;
-    HIPCHK(c, up(sm, ws, o.La, La));
+    HIPCHK(c, up(sm, ws, o.unit, bound_units(c)));
+    HIPCHK(c, up(sm, ws, o.Lq, c->Lq));
     HIPCHK(c, up(sm, ws, o.tparams, c->tparams));
     HIPCHK(c, up(sm, ws, o.tab_f, c->tab_f));
     HIPCHK(c, up(sm, ws, o.tab_d, c->tab_d));
@@ -523,7 +551,8 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     t.angle_ijk = at<int32_t>(ws, o.angle_ijk);
     t.angle_kt = at<double>(ws, o.angle_kt);
     c->d_reps = at<RepInfo>(ws, o.reps);
-    c->d_La = at<double>(ws, o.La);
+    c->d_unit = at<double>(ws, o.unit);
+    c->d_Lq = at<uint32_t>(ws, o.Lq);
     c->d_tparams = at<double>(ws, o.tparams);
     c->d_tab_f = at<TypePair<float>>(ws, o.tab_f);
     c->d_tab_d = at<TypePair<double>>(ws, o.tab_d);
@@ -555,7 +584,8 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
         ls.fcnt = at<int2>(ws, q[9]);
         ls.flist = at<int32_t>(ws, q[10]);
         ls.ccnt = at<int32_t>(ws, q[11]);
-        ls.clist = at<int32_t>(ws, q[11]) + c->n;
+        ls.ncls = k == 0 ? c->ncls : 1;
+        ls.clist = at<int32_t>(ws, q[11]) + (int64_t)c->n * ls.ncls;
         ls.bslot = k == 0 ? at<int4>(ws, q[12]) : nullptr;
         ls.sinfo = at<int2>(ws, q[13]);
         ls.scan_part = at<int32_t>(ws, q[14]);
@@ -592,9 +622,7 @@ bounce_status bounce_update_params(bounce_ctx *c, const bounce_params *p)
         Offsets o;
         plan(c, L, o);
         HIPCHK(c, up(c->stream, c->ws, o.ou_c2, c->ou_c2));
-        std::vector<double> La(MAXT, 0.0);
-        for (int a = 0; a < c->nt; ++a) La[a] = c->L_a[a] * c->p.bound_scale;
-        HIPCHK(c, up(c->stream, c->ws, o.La, La));
+        HIPCHK(c, up(c->stream, c->ws, o.unit, bound_units(c)));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
         if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
@@ -729,7 +757,8 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     a.pos = c->pos;
     a.vel = c->vel;
     a.ou_c2 = c->d_ou_c2;
-    a.L_a = c->d_La;
+    a.Lunit = c->d_unit;
+    a.Lq = c->d_Lq;
     a.tab_f = c->d_tab_f;
     a.tab_d = c->d_tab_d;
     a.pg = pair_globals(c);
@@ -996,6 +1025,18 @@ bounce_status bounce_rate_bounds(const bounce_ctx *c, double *L_ab, double *L_a)
     if (!c->have_system) return BOUNCE_E_STATE;
     std::memcpy(L_ab, c->L_ab.data(), 8 * c->L_ab.size());
     std::memcpy(L_a, c->L_a.data(), 8 * c->L_a.size());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_rate_weights(const bounce_ctx *c, uint32_t *Lq, double *unit)
+{
+    if (!c || !Lq || !unit) return BOUNCE_E_ARG;
+    if (!c->have_system) return BOUNCE_E_STATE;
+    const std::vector<double> u = bound_units(c);
+    for (int a = 0; a < c->nt; ++a) {
+        unit[a] = u[a];
+        for (int b = 0; b < c->nt; ++b) Lq[a * c->nt + b] = c->Lq[a * c->nt + b];
+    }
     return BOUNCE_OK;
 }
 

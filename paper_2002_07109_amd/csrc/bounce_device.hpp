@@ -12,6 +12,9 @@ constexpr double KB = 0.0019872041;    // kcal / (mol K)
 constexpr double ACC = 4.184e-4;       // (kcal/mol/A)/amu -> A/fs^2
 constexpr double TWO_OVER_SQRTPI = 1.1283791670955126;
 constexpr int MAXT = 8;
+// jump bounds as integer weights: 2^WEIGHT_BITS units make the bound of an atom type
+constexpr int WEIGHT_BITS = 20;
+constexpr double WEIGHT_SLACK = 1e-4;
 
 // latched device conditions
 enum : uint32_t {

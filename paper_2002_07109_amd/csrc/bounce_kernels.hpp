@@ -24,7 +24,7 @@ struct PairArgs {
     int32_t out_global;           // 1: caller order, 0: sorted order
     int32_t accumulate;           // 1: out += g
     double *atom_out;             // ENERGY: per-atom energies; DBWD: [N][3*MAXT] basis sums
-    int32_t list_sel;             // 0: force list rows, 1: candidate rows
+    int32_t pad1;
     int32_t energy_total;         // ENERGY: 1 -> atom_out[g] = coul + lj (stride 1)
     int32_t atom_stride;          // ENERGY with energy_total = 0: (coul, lj) at
     int32_t atom_col;             //   atom_out[g * atom_stride + atom_col + {0,1}]
@@ -53,7 +53,8 @@ struct StepArgs {
     double *pos;                  // [N][3] caller order
     double *vel;                  // [N][3] caller order
     const double *ou_c2;          // [N] O-step noise amplitude
-    const double *L_a;            // [n_types] rate bounds (bound_scale applied)
+    const double *Lunit;          // [MAXT] unit of each atom type's bound weights (bound_scale applied)
+    const uint32_t *Lq;           // [n_types][n_types] integer bound weights of the partner types
     const TypePair<float> *tab_f; // [MAXT][MAXT] pair constants of the jump field
     const TypePair<double> *tab_d;
     PairGlobals pg;

@@ -19,13 +19,13 @@ struct ListSet {
     int32_t *flist;       // [N][fcap] sorted partner positions: the near entries fill
                           //   the row from the front, the far ones from the back
                           //   (each part ascending in canonical order from its end)
-    int32_t *ccnt;        // candidate list (jump partners)
-    int32_t *clist;       // [N][ccap]
+    int32_t *ccnt;        // candidate list (jump partners): [N][ncls] members per class
+    int32_t *clist;       // [N][ncls][ccap], each class in canonical order
     int4 *bslot;          // [N][BTMAX] bonded terms of each sorted atom with their
                           //   atoms as sorted positions (x = term code, -1: none); or NULL
     int32_t fcap, ccap;
     int32_t n_cells;
-    int32_t pad;
+    int32_t ncls;         // candidate classes: the partner's type (per-type-pair bounds) or one
 };
 
 // most bonded terms (bonds + angles) touching one atom

@@ -215,13 +215,15 @@ constexpr int LEXCL = 8;       // exclusions per atom held in registers
 // wavefront takes every LB-th atom i of the cell; its 64 lanes test 64
 // consecutive staged candidates at a time and a ballot appends the hits in
 // candidate order, so every row comes out in canonical order.
+template <int KC>
 __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInfo *__restrict__ reps,
                                                    const int32_t *__restrict__ cell_rep, Topo tp,
                                                    ListSet ls, BuildSpec bs, DevState *st)
 {
     __shared__ double cx[LCAP], cy[LCAP], cz[LCAP];
     __shared__ int32_t cj[LCAP];
-    __shared__ int32_t rowf[LMAXI], rowg[LMAXI], rowc[LMAXI];
+    __shared__ uint8_t ct[LCAP];
+    __shared__ int32_t rowf[LMAXI], rowg[LMAXI], rowc[LMAXI * MAXT];
     __shared__ double iexr2[LMAXI];
     __shared__ int32_t dcell[3][LDIM];
     __shared__ double dgap[3][LDIM];
@@ -238,7 +240,8 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             bslot_row(ls.perm[bi + k], bi + k, tp, ls);
     for (int32_t i = ei + threadIdx.x; i < ei_all; i += 64 * LB) {   // atoms beyond the limit
         ls.fcnt[i] = make_int2(0, 0);
-        ls.ccnt[i] = 0;
+        if (bs.want_cand)
+            for (int b = 0; b < ls.ncls; ++b) ls.ccnt[(int64_t)i * ls.ncls + b] = 0;
     }
     if (ni == 0) return;                             // uniform per workgroup
     const RepInfo &ri = reps[cell_rep[ci]];
@@ -255,7 +258,8 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     // excluded, so the exclusion test runs only at or below it
     if (w == LB - 1) {
         for (int32_t k = lane; k < ni; k += 64) {
-            rowf[k] = rowg[k] = rowc[k] = 0;
+            rowf[k] = rowg[k] = 0;
+            for (int b = 0; b < MAXT; ++b) rowc[k * MAXT + b] = 0;
             const double4 x = X[bi + k];
             ipos[k] = x;
             const int32_t g = mirror_id(x.w);
@@ -374,12 +378,13 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             for (int32_t t = t_lo; t < t_hi; ++t) cj[p0 + t - lo] = jb + t;
         }
         __syncthreads();
-        // (2b) their positions
+        // (2b) their positions and types
         for (int32_t f = threadIdx.x; f < nb; f += 64 * LB) {
             const double4 x = X[cj[f]];
             cx[f] = x.x;
             cy[f] = x.y;
             cz[f] = x.z;
+            ct[f] = (uint8_t)mirror_type(x.w);
         }
         __syncthreads();
         // (3) this wavefront's atoms of the cell against the batch
@@ -390,9 +395,11 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             int32_t ex_id[LEXCL];
 #pragma unroll
             for (int t = 0; t < LEXCL; ++t) ex_id[t] = iex[k][t];
-            int32_t nf = rowf[k], ng = rowg[k], nc = rowc[k];
+            int32_t nf = rowf[k], ng = rowg[k], nc[KC];
+#pragma unroll
+            for (int b = 0; b < KC; ++b) nc[b] = rowc[k * MAXT + b];
             int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
-            int32_t *crow = ls.clist + (int64_t)i * ls.ccap;
+            int32_t *crow = ls.clist + (int64_t)i * ls.ncls * ls.ccap;
             for (int32_t f0 = 0; f0 < nb; f0 += 64) {
                 const int32_t f = f0 + lane;
                 bool hf = false, hg = false, hc = false;
@@ -417,7 +424,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                         }
                     }
                 }
-                const uint64_t mf = __ballot(hf), mg = __ballot(hg), mc = __ballot(hc);
+                const uint64_t mf = __ballot(hf), mg = __ballot(hg);
                 if (hf) {      // near: from the front of the row
                     const int32_t q = nf + __popcll(mf & below);
                     if (q < ls.fcap) frow[q] = j;
@@ -426,28 +433,43 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                     const int32_t q = ng + __popcll(mg & below);
                     if (q < ls.fcap) frow[ls.fcap - 1 - q] = j;
                 }
-                if (hc) {
-                    const int32_t q = nc + __popcll(mc & below);
-                    if (q < ls.ccap) crow[q] = j;
+                // candidates by class (the partner's type when the rate
+                // bounds are per type pair, else one class), each in candidate order
+                const int cls = KC > 1 && f < nb ? (int)ct[f] : 0;
+#pragma unroll
+                for (int b = 0; b < KC; ++b) {
+                    if (b >= ls.ncls) break;
+                    const bool hb = hc && cls == b;
+                    const uint64_t mb = __ballot(hb);
+                    if (hb) {
+                        const int32_t q = nc[b] + __popcll(mb & below);
+                        if (q < ls.ccap) crow[b * ls.ccap + q] = j;
+                    }
+                    nc[b] += __popcll(mb);
                 }
                 nf += __popcll(mf);
                 ng += __popcll(mg);
-                nc += __popcll(mc);
             }
             if (lane == 0) {
                 rowf[k] = nf;
                 rowg[k] = ng;
-                rowc[k] = nc;
+#pragma unroll
+                for (int b = 0; b < KC; ++b) rowc[k * MAXT + b] = nc[b];
             }
         }
         __syncthreads();
     }
     for (int32_t k = threadIdx.x; k < ni; k += 64 * LB) {
-        const int32_t nf = rowf[k], ng = rowg[k], nc = rowc[k];
+        const int32_t nf = rowf[k], ng = rowg[k];
         const bool full = nf + ng > ls.fcap;     // the two ends met
         if (bs.want_force) ls.fcnt[bi + k] = full ? make_int2(0, 0) : make_int2(nf, ng);
-        if (bs.want_cand) ls.ccnt[bi + k] = min(nc, ls.ccap);
-        if (full || nc > ls.ccap) overflow = true;
+        if (full) overflow = true;
+        if (bs.want_cand)
+            for (int b = 0; b < ls.ncls; ++b) {
+                const int32_t nc = rowc[k * MAXT + b];
+                ls.ccnt[(int64_t)(bi + k) * ls.ncls + b] = min(nc, ls.ccap);
+                if (nc > ls.ccap) overflow = true;
+            }
     }
     if (__syncthreads_or(overflow) && threadIdx.x == 0) atomicOr(&st->status, ST_CAPACITY);
 }
@@ -465,8 +487,13 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
                        pos, tp, ls, st, bs.mirror_sel, bs.step_off);
-    hipLaunchKernelGGL(k_lists, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps, cell_rep,
-                       tp, ls, bs, st);
+    // one candidate class (or none) needs no per-class appends
+    if (ls.ncls > 1 && bs.want_cand)
+        hipLaunchKernelGGL(k_lists<MAXT>, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps,
+                           cell_rep, tp, ls, bs, st);
+    else
+        hipLaunchKernelGGL(k_lists<1>, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps,
+                           cell_rep, tp, ls, bs, st);
 }
 
 }  // namespace bnc

@@ -123,19 +123,10 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const int2 si = a.ls.sinfo[s];
         gi = si.x;
         const BoxReg box(ONE ? a.reps[0] : load_rep(a.reps, a.single_rep, si.y));
-        const int32_t *row;
-        int32_t nn, cnt, cap;
-        if (a.list_sel == 1) {
-            row = a.ls.clist + (int64_t)s * a.ls.ccap;
-            cap = a.ls.ccap;
-            nn = cnt = min(a.ls.ccnt[s], cap);
-        } else {
-            row = a.ls.flist + (int64_t)s * a.ls.fcap;
-            cap = a.ls.fcap;
-            const int2 fc = a.ls.fcnt[s];   // the list build keeps fc.x + fc.y <= cap
-            nn = fc.x;
-            cnt = fc.x + fc.y;
-        }
+        const int32_t *row = a.ls.flist + (int64_t)s * a.ls.fcap;
+        const int32_t cap = a.ls.fcap;
+        const int2 fc = a.ls.fcnt[s];   // the list build keeps fc.x + fc.y <= cap
+        const int32_t nn = fc.x, cnt = fc.x + fc.y;
         const int32_t tail = cap - 1 + nn;
         if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
             pair_force_row<R, MODE, G>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
@@ -417,10 +408,26 @@ __global__ void k_list_to_global(int32_t n, ListSet ls, int32_t which, int32_t *
     int32_t g = ls.perm[s];
     int32_t *out = col_global + (int64_t)g * cap;
     if (which != 0) {
-        const int32_t *row = ls.clist + (int64_t)s * ls.ccap;
-        const int32_t c = ls.ccnt[s];
-        cnt_global[g] = c;
-        for (int32_t k = 0; k < c && k < cap; ++k) out[k] = ls.perm[row[k]];
+        // candidate rows: merge the classes (each ascending) into canonical order
+        const int32_t *row = ls.clist + (int64_t)s * ls.ncls * ls.ccap;
+        const int32_t *cnt = ls.ccnt + (int64_t)s * ls.ncls;
+        int32_t head[MAXT], total = 0;
+        for (int b = 0; b < ls.ncls; ++b) {
+            head[b] = 0;
+            total += cnt[b];
+        }
+        cnt_global[g] = total;
+        for (int32_t k = 0; k < total && k < cap; ++k) {
+            int best = -1;
+            int32_t v = INT32_MAX;
+            for (int b = 0; b < ls.ncls; ++b)
+                if (head[b] < cnt[b] && row[b * ls.ccap + head[b]] < v) {
+                    v = row[b * ls.ccap + head[b]];
+                    best = b;
+                }
+            ++head[best];
+            out[k] = ls.perm[v];
+        }
         return;
     }
     // force rows: merge the near part (front, ascending) and the far part

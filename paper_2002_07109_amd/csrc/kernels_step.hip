@@ -69,14 +69,94 @@ __device__ __forceinline__ int32_t group_get_i32(int32_t v, int src)
     return __shfl(v, group_base<GS>() + src, 64);
 }
 
+// The atom's jump partners: KC classes in its candidate row (the partner's
+// type when the rate bounds are per type pair, else one class), c[b] members
+// in class b, each with the bound w[b] * unit (integer weight w[b]).
+template <int KC>
+struct Partners {
+    const int32_t *row;     // class b at row + b * cap, in canonical order
+    int32_t cap;
+    int32_t c[KC];
+    uint32_t w[KC];
+    uint64_t W;             // sum of the members' weights
+    double unit;            // bound of one weight unit: bound_scale L_a 2^-20
+};
+
+template <int KC>
+__device__ __forceinline__ void no_partners(const StepArgs &a, Partners<KC> &P)
+{
+    P.row = a.ls.clist;
+    P.cap = a.ls.ccap;
+    P.W = 0;
+    P.unit = 0.0;
+#pragma unroll
+    for (int b = 0; b < KC; ++b) {
+        P.c[b] = 0;
+        P.w[b] = 0;
+    }
+}
+
+template <int KC>
+__device__ __forceinline__ void load_partners(const StepArgs &a, int32_t s, int ti, Partners<KC> &P)
+{
+    const int32_t nc = a.ls.ncls;
+    P.row = a.ls.clist + (int64_t)s * nc * a.ls.ccap;
+    P.cap = a.ls.ccap;
+    P.unit = a.Lunit[ti];
+    P.W = 0;
+#pragma unroll
+    for (int b = 0; b < KC; ++b) {
+        const bool on = b < nc;
+        P.c[b] = on ? min(a.ls.ccnt[(int64_t)s * nc + b], a.ls.ccap) : 0;
+        P.w[b] = KC == 1 ? (1u << WEIGHT_BITS) : (on ? a.Lq[ti * a.pg.n_types + b] : 0u);
+        P.W += (uint64_t)P.c[b] * P.w[b];
+    }
+}
+
+// The partner of one proposal: j with probability weight_j / W, from the first
+// word of its Philox block (X uniform on [0, W), the class whose weight range
+// holds X, the member within it), and that partner's bound.  With one class
+// of weight 2^20 this is the uniform draw umulh(w0, c).
+template <int KC>
+__device__ __forceinline__ void pick_partner(const Partners<KC> &P, uint64_t w0, int32_t &slot,
+                                             double &lb)
+{
+    if (KC == 1) {
+        slot = P.row[(int32_t)__umul64hi(w0, (uint64_t)P.c[0])];
+        lb = (double)(1u << WEIGHT_BITS) * P.unit;
+        return;
+    }
+    const uint64_t X = __umul64hi(w0, P.W);
+    uint64_t lo = 0;
+    uint32_t wb = 1;
+    int32_t off = 0;
+    bool found = false;
+#pragma unroll
+    for (int b = 0; b < KC; ++b) {
+        const uint64_t hi = lo + (uint64_t)P.c[b] * P.w[b];
+        if (!found && X < hi) {
+            found = true;
+            wb = P.w[b];
+            off = b * P.cap;
+        }
+        if (!found) lo = hi;
+    }
+    // X - lo < 2^53 and the quotient is below 2^20, so the FP64 quotient of
+    // the two integers floors to the exact integer quotient
+    const int32_t idx = (int32_t)floor((double)(X - lo) / (double)wb);
+    slot = P.row[off + idx];
+    lb = (double)wb * P.unit;
+}
+
 // Poisson count of proposals for one atom and J half-step: inversion of the
-// CDF of Poisson(|C_i| beta |v_i| L dt/2) with the uniform U (Sec. IV.B, Sec. V)
-__device__ __forceinline__ int32_t poisson_count(const StepArgs &a, int32_t c, double v0, double L,
-                                                 double U, bool &capped)
+// CDF of Poisson(beta |v_i| dt/2 sum_j L_ij) with the uniform U (Sec. IV.B,
+// Sec. V; the sum is W weight units)
+__device__ __forceinline__ int32_t poisson_count(const StepArgs &a, uint64_t W, double v0,
+                                                 double unit, double U, bool &capped)
 {
     capped = false;
-    if (c == 0 || v0 == 0.0 || L == 0.0) return 0;
-    const double mu = (double)c * a.beta * v0 * L * a.half_dt;
+    if (W == 0 || v0 == 0.0 || unit == 0.0) return 0;
+    const double mu = (double)W * a.beta * v0 * unit * a.half_dt;
     int32_t M = 0;
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
@@ -96,22 +176,24 @@ __device__ __forceinline__ int32_t poisson_count(const StepArgs &a, int32_t c, d
 struct Proposal {
     double F[3];
     double u;
+    double lb;      // the rate bound of this partner
     int32_t p;
 };
 
 // first stage: the partner and the uniform from the proposal's Philox block
-__device__ __forceinline__ void block_proposal(const U4 &w, const int32_t *crow, int32_t c, Proposal &o)
+template <int KC>
+__device__ __forceinline__ void block_proposal(const U4 &w, const Partners<KC> &P, Proposal &o)
 {
-    const int32_t J = (int32_t)__umul64hi(w.x, (uint64_t)c);
-    o.p = crow[J];
+    pick_partner<KC>(P, w.x, o.p, o.lb);
     o.u = u01(w.y);
 }
 
-__device__ __forceinline__ void draw_proposal(const int32_t *crow, int32_t c, const RepInfo &ri,
+template <int KC>
+__device__ __forceinline__ void draw_proposal(const Partners<KC> &P, const RepInfo &ri,
                                               int64_t step, int32_t phase, int32_t lid, int32_t k,
                                               Proposal &o)
 {
-    block_proposal(draw(ri, step, phase, lid, (uint64_t)k), crow, c, o);
+    block_proposal<KC>(draw(ri, step, phase, lid, (uint64_t)k), P, o);
 }
 
 // second stage: the partner's long-range field on the atom
@@ -126,14 +208,14 @@ __device__ __forceinline__ void field_proposal(const StepArgs &a, const TypePair
     long_field<R>(tab[ti * a.pg.n_types + mirror_type(xj.w)], a.pg, dx, dy, dz, o.F);
 }
 
-template <typename R>
+template <typename R, int KC>
 __device__ __forceinline__ void eval_proposal(const StepArgs &a, const TypePair<R> *tab,
-                                              const double4 *X, const int32_t *crow, int32_t c,
+                                              const double4 *X, const Partners<KC> &P,
                                               const RepInfo &ri, int ti, const double q[3],
                                               int64_t step, int32_t phase, int32_t lid, int32_t k,
                                               Proposal &o)
 {
-    draw_proposal(crow, c, ri, step, phase, lid, k, o);
+    draw_proposal<KC>(P, ri, step, phase, lid, k, o);
     field_proposal<R>(a, tab, X, ri, ti, q, o);
 }
 
@@ -141,7 +223,7 @@ __device__ __forceinline__ void eval_proposal(const StepArgs &a, const TypePair<
 // same FP64 arithmetic, so the lanes keep identical v); lane 0 keeps the tally
 // and the event log.
 __device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo &ri, int32_t lid,
-                                               int32_t rep, double v[3], double v0, double L,
+                                               int32_t rep, double v[3], double v0, double L,   // L: the partner's bound
                                                int64_t step, int32_t phase, int32_t k, double Fx,
                                                double Fy, double Fz, double ut, int32_t pt, int sub,
                                                JumpTally &tally)
@@ -184,14 +266,16 @@ __device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo 
 // proposal k0 + t).  Every lane then walks the proposals in order k = 1, 2, ...
 // applying the accept test and reflection.  Every lane of the wavefront must
 // call this (M = 0 for padding lanes).
-template <typename R, int GS, int NPRE>
+template <typename R, int GS, int NPRE, int KC>
 __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const double4 *X,
-                           const int32_t *crow, int32_t c, int32_t lid, int32_t rep,
+                           const Partners<KC> &PT, int32_t lid, int32_t rep,
                            const RepInfo &ri, int ti, const double q[3], double v[3], double v0,
-                           double L, int64_t step, int32_t phase, int32_t M, int32_t M_pre,
+                           int64_t step, int32_t phase, int32_t M, int32_t M_pre,
                            int pre_lane1, int pre_lane2, const Proposal &pre, int sub,
                            JumpTally &tally)
 {
+    // one class: every partner has the atom's bound, no need to pass it around
+    const double L1 = (double)(1u << WEIGHT_BITS) * PT.unit;
     const int32_t n_pre = min(min(M, M_pre), NPRE);
 #pragma unroll
     for (int t = 0; t < NPRE; ++t) {
@@ -199,25 +283,28 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
         const double Fx = group_get<GS>(pre.F[0], src), Fy = group_get<GS>(pre.F[1], src),
                      Fz = group_get<GS>(pre.F[2], src);
         const double ut = group_get<GS>(pre.u, src);
+        const double lb = KC == 1 ? L1 : group_get<GS>(pre.lb, src);
         const int32_t pt = group_get_i32<GS>(pre.p, src);
         if (t < n_pre)
-            apply_proposal(a, ri, lid, rep, v, v0, L, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+            apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
     }
     for (int32_t k0 = n_pre + 1; __any(k0 <= M); k0 += PB) {
         const int32_t k = k0 + sub;
         Proposal P;
         P.F[0] = P.F[1] = P.F[2] = 0.0;
         P.u = 1.0;
+        P.lb = 1.0;
         P.p = 0;
-        if (k <= M && sub < PB) eval_proposal<R>(a, tab, X, crow, c, ri, ti, q, step, phase, lid, k, P);
+        if (k <= M && sub < PB) eval_proposal<R, KC>(a, tab, X, PT, ri, ti, q, step, phase, lid, k, P);
 #pragma unroll
         for (int t = 0; t < PB; ++t) {
             const double Fx = group_get<GS>(P.F[0], t), Fy = group_get<GS>(P.F[1], t),
                          Fz = group_get<GS>(P.F[2], t);
             const double ut = group_get<GS>(P.u, t);
+            const double lb = KC == 1 ? L1 : group_get<GS>(P.lb, t);
             const int32_t pt = group_get_i32<GS>(P.p, t);
             if (k0 + t <= M)
-                apply_proposal(a, ri, lid, rep, v, v0, L, step, phase, k0 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, k0 + t, Fx, Fy, Fz, ut, pt, sub, tally);
         }
     }
 }
@@ -281,7 +368,7 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
 constexpr int LPA = 4;
 constexpr int JB_L1 = 3, JB_L2 = 1, JA_L1 = 2, JA_L2 = 0;
 
-template <typename R, bool BOUNCE>
+template <typename R, bool BOUNCE, int KC = 1>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
     __shared__ TypePair<R> ftab[MAXT * MAXT];
@@ -303,10 +390,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     const int32_t s = t / LPA, sub = t % LPA;
     const bool active = s < a.n;
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0, g = 0, lid = 0, c = 0;
+    int32_t rep = 0, g = 0, lid = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
     double v[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
-    double km = 0.0, c2 = 0.0, L = 0.0;
+    double km = 0.0, c2 = 0.0;
+    Partners<KC> PT;
+    no_partners<KC>(a, PT);
     U4 w = {0, 0, 0, 0};
     if (active) {
         const int2 si = a.ls.sinfo[s];
@@ -316,7 +405,6 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         F[0] = a.fpair[3 * (int64_t)s];
         F[1] = a.fpair[3 * (int64_t)s + 1];
         F[2] = a.fpair[3 * (int64_t)s + 2];
-        if (BOUNCE) c = min(a.ls.ccnt[s], a.ls.ccap);
         const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
         lid = g - (int32_t)ri.atom_off;
         v[0] = a.vel[3 * (int64_t)g];
@@ -324,7 +412,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         v[2] = a.vel[3 * (int64_t)g + 2];
         km = a.half_dt * a.tp.acc_m[g];
         c2 = a.ou_c2[g];
-        if (BOUNCE) L = a.L_a[mirror_type(xi.w)];
+        if (BOUNCE) load_partners<KC>(a, s, mirror_type(xi.w), PT);
         // one Philox block per lane
         if (sub < 3) {
             const int64_t dstep = sub == 1 ? n - 1 : n;
@@ -337,7 +425,6 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
     const int ti = mirror_type(xi.w);
     double q[3] = {xi.x, xi.y, xi.z};
-    const int32_t *crow = a.ls.clist + (int64_t)s * a.ls.ccap;
     // this lane's first bonded term and its atoms' positions, loaded ahead of
     // the jump proposals so the two latency chains overlap
     int4 e0 = make_int4(-1, 0, 0, 0);
@@ -355,24 +442,25 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     Proposal pp;     // lanes 3, 1: proposals 1, 2 of J(n-1, JB); lanes 2, 0: 1, 2 of J(n, JA)
     pp.F[0] = pp.F[1] = pp.F[2] = 0.0;
     pp.u = 1.0;
+    pp.lb = 1.0;
     pp.p = 0;
     if (BOUNCE && active) {
         const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         bool capped_b = false, capped_a = false;
-        if (a.do_close) M_jb = poisson_count(a, c, v0, L, U_jb, capped_b);
-        if (a.do_open) M_est = poisson_count(a, c, v0, L, U_ja, capped_a);
+        if (a.do_close) M_jb = poisson_count(a, PT.W, v0, PT.unit, U_jb, capped_b);
+        if (a.do_open) M_est = poisson_count(a, PT.W, v0, PT.unit, U_ja, capped_a);
         bool ev = false;
         if (sub == JB_L1 && M_jb >= 1) {
-            block_proposal(w, crow, c, pp);          // drawn at entry
+            block_proposal<KC>(w, PT, pp);          // drawn at entry
             ev = true;
         } else if (sub == JB_L2 && M_jb >= 2) {
-            draw_proposal(crow, c, ri, n - 1, 2, lid, 2, pp);
+            draw_proposal<KC>(PT, ri, n - 1, 2, lid, 2, pp);
             ev = true;
         } else if (sub == JA_L1 && M_est >= 1) {
-            draw_proposal(crow, c, ri, n, 0, lid, 1, pp);
+            draw_proposal<KC>(PT, ri, n, 0, lid, 1, pp);
             ev = true;
         } else if (sub == JA_L2 && M_est >= 2) {
-            draw_proposal(crow, c, ri, n, 0, lid, 2, pp);
+            draw_proposal<KC>(PT, ri, n, 0, lid, 2, pp);
             ev = true;
         }
         if (ev) field_proposal<R>(a, ftab, X, ri, ti, q, pp);
@@ -414,8 +502,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     if (a.do_close) {
         if (BOUNCE) {
             const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            jump_chain<R, LPA, 2>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n - 1, 2, M_jb,
-                                  M_jb, JB_L1, JB_L2, pp, sub, tally);
+            jump_chain<R, LPA, 2, KC>(a, ftab, X, PT, lid, rep, ri, ti, q, v, v0, n - 1, 2, M_jb,
+                                      M_jb, JB_L1, JB_L2, pp, sub, tally);
         }
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
     }
@@ -424,10 +512,10 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         if (BOUNCE) {
             const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
             bool capped = false;
-            const int32_t M = active ? poisson_count(a, c, v0, L, U_ja, capped) : 0;
+            const int32_t M = active ? poisson_count(a, PT.W, v0, PT.unit, U_ja, capped) : 0;
             if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
-            jump_chain<R, LPA, 2>(a, ftab, X, crow, c, lid, rep, ri, ti, q, v, v0, L, n, 0, M, M_est,
-                                  JA_L1, JA_L2, pp, sub, tally);
+            jump_chain<R, LPA, 2, KC>(a, ftab, X, PT, lid, rep, ri, ti, q, v, v0, n, 0, M, M_est,
+                                      JA_L1, JA_L2, pp, sub, tally);
         }
     }
     if (active && sub == 0) {
@@ -469,15 +557,25 @@ void launch_step(hipStream_t sm, const StepArgs &a)
     if (a.n <= 0) return;
     dim3 grid(((int64_t)a.n * LPA + 255) / 256), block(256);
     if (a.bounce) {
-        if (a.pair_fp64) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, sm, a);
-        else hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, sm, a);
+        // classes of jump partners rounded up to 1, 2, 4 or 8
+        const int kc = a.ls.ncls <= 1 ? 1 : (a.ls.ncls <= 2 ? 2 : (a.ls.ncls <= 4 ? 4 : 8));
+        switch (kc * 2 + a.pair_fp64) {
+            case 2: hipLaunchKernelGGL((k_step<float, true, 1>), grid, block, 0, sm, a); break;
+            case 3: hipLaunchKernelGGL((k_step<double, true, 1>), grid, block, 0, sm, a); break;
+            case 4: hipLaunchKernelGGL((k_step<float, true, 2>), grid, block, 0, sm, a); break;
+            case 5: hipLaunchKernelGGL((k_step<double, true, 2>), grid, block, 0, sm, a); break;
+            case 8: hipLaunchKernelGGL((k_step<float, true, 4>), grid, block, 0, sm, a); break;
+            case 9: hipLaunchKernelGGL((k_step<double, true, 4>), grid, block, 0, sm, a); break;
+            case 16: hipLaunchKernelGGL((k_step<float, true, 8>), grid, block, 0, sm, a); break;
+            default: hipLaunchKernelGGL((k_step<double, true, 8>), grid, block, 0, sm, a); break;
+        }
     } else {
         hipLaunchKernelGGL((k_step<float, false>), grid, block, 0, sm, a);
     }
 }
 
 // J half-step alone at the current positions (diagnostics and parity tests)
-template <typename R>
+template <typename R, int KC>
 __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
 {
     const StepArgs &a = ja.s;
@@ -488,9 +586,11 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     const int32_t par = (int32_t)((a.st->step + a.step_off) & 1);
     const double4 *X = a.ls.x[par];
     JumpTally tally = {0, 0, 0};
-    int32_t rep = 0, g = 0, lid = 0, c = 0, M = 0;
+    int32_t rep = 0, g = 0, lid = 0, M = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-    double v[3] = {0.0, 0.0, 0.0}, v0 = 0.0, L = 0.0;
+    double v[3] = {0.0, 0.0, 0.0}, v0 = 0.0;
+    Partners<KC> PT;
+    no_partners<KC>(a, PT);
     if (active) {
         const int2 si = a.ls.sinfo[s];
         g = si.x;
@@ -500,11 +600,11 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
         v[0] = a.vel[3 * (int64_t)g];
         v[1] = a.vel[3 * (int64_t)g + 1];
         v[2] = a.vel[3 * (int64_t)g + 2];
-        c = min(a.ls.ccnt[s], a.ls.ccap);
-        L = a.L_a[mirror_type(xi.w)];
+        load_partners<KC>(a, s, mirror_type(xi.w), PT);
         v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         bool capped = false;
-        M = poisson_count(a, c, v0, L, u01(draw(a.reps[rep], ja.step, ja.phase, lid, 0).x), capped);
+        M = poisson_count(a, PT.W, v0, PT.unit, u01(draw(a.reps[rep], ja.step, ja.phase, lid, 0).x),
+                          capped);
         if (capped && sub == 0) atomicOr(&a.st->status, ST_POISSON);
     }
     const RepInfo &ri = a.reps[rep];
@@ -512,10 +612,10 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     Proposal none;
     none.F[0] = none.F[1] = none.F[2] = 0.0;
     none.u = 1.0;
+    none.lb = 1.0;
     none.p = 0;
-    jump_chain<R, PB, 1>(a, tab, X, a.ls.clist + (int64_t)s * a.ls.ccap, c, lid, rep, ri,
-                         mirror_type(xi.w), q, v, v0, L, ja.step, ja.phase, M, 0, 0, 0, none, sub,
-                         tally);
+    jump_chain<R, PB, 1, KC>(a, tab, X, PT, lid, rep, ri, mirror_type(xi.w), q, v, v0, ja.step,
+                             ja.phase, M, 0, 0, 0, none, sub, tally);
     if (active && sub == 0) {
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];
@@ -528,8 +628,18 @@ void launch_jump(hipStream_t sm, const JumpArgs &a)
 {
     if (a.s.n <= 0) return;
     dim3 grid(((int64_t)a.s.n * PB + 255) / 256), block(256);
-    if (a.s.pair_fp64) hipLaunchKernelGGL((k_jump<double>), grid, block, 0, sm, a);
-    else hipLaunchKernelGGL((k_jump<float>), grid, block, 0, sm, a);
+    const int nc = a.s.ls.ncls;
+    const int kc = nc <= 1 ? 1 : (nc <= 2 ? 2 : (nc <= 4 ? 4 : 8));
+    switch (kc * 2 + a.s.pair_fp64) {
+        case 2: hipLaunchKernelGGL((k_jump<float, 1>), grid, block, 0, sm, a); break;
+        case 3: hipLaunchKernelGGL((k_jump<double, 1>), grid, block, 0, sm, a); break;
+        case 4: hipLaunchKernelGGL((k_jump<float, 2>), grid, block, 0, sm, a); break;
+        case 5: hipLaunchKernelGGL((k_jump<double, 2>), grid, block, 0, sm, a); break;
+        case 8: hipLaunchKernelGGL((k_jump<float, 4>), grid, block, 0, sm, a); break;
+        case 9: hipLaunchKernelGGL((k_jump<double, 4>), grid, block, 0, sm, a); break;
+        case 16: hipLaunchKernelGGL((k_jump<float, 8>), grid, block, 0, sm, a); break;
+        default: hipLaunchKernelGGL((k_jump<double, 8>), grid, block, 0, sm, a); break;
+    }
 }
 
 }  // namespace bnc

@@ -14,7 +14,7 @@ FF = tip3p_params()
 # droplet trajectories run at dt = 0.25 fs, where the scheme is stable
 DROPLET = dict(integrator=0, periodic=0, coulomb=0, dt=0.25, gamma=1e-3, temperature=300.0,
                r_on=5.0, r_off=6.0, r_cut=9.0, skin=2.0, ewald_alpha=0.35, rebuild_interval=10,
-               seed=0, bound_scale=1.0)
+               seed=0, bound_scale=1.0, rate_mode=0)
 # periodic boxes: Ewald real-space erfc with alpha = 0.45/A (the benchmark's model)
 BOX = dict(DROPLET, periodic=1, coulomb=1, r_on=6.0, r_off=7.0, dt=1.0, ewald_alpha=0.45)
 
@@ -26,7 +26,7 @@ def oracle_params(orc, sys, cfg, replica=0):
                            skin=cfg["skin"], ewald_alpha=cfg["ewald_alpha"],
                            rebuild_interval=cfg["rebuild_interval"], seed=cfg["seed"],
                            replica=replica, bound_scale=cfg["bound_scale"],
-                           periodic=bool(cfg["periodic"]))
+                           periodic=bool(cfg["periodic"]), rate_mode=cfg.get("rate_mode", 0))
 
 
 def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_graph=False):
@@ -40,7 +40,7 @@ def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_gr
                       bound_scale=cfg["bound_scale"], cell_size=cell,
                       pair_precision=B.PAIR_FP64 if fp64 else B.PAIR_FP32,
                       log_events=int(log_events), event_capacity=event_capacity,
-                      use_graph=int(use_graph))
+                      use_graph=int(use_graph), rate_mode=cfg.get("rate_mode", 0))
     return B.Simulation(systems, p, FF["charge"], FF["eps"], FF["sigma"])
 
 
