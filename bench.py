@@ -85,14 +85,17 @@ def pair_count(pos, box, r, n_excl_within):
     return int(t.count_neighbors(t, r) - pos.shape[0]) // 2 - n_excl_within
 
 
-def run_gpu(args, system, ff, integrator, state):
+RATE_MODES = {"atom": 0, "pair": 1}
+
+
+def run_gpu(args, system, ff, integrator, state, rate_mode=0):
     import torch
     import paper_2002_07109_amd as B
     p = B.make_params(integrator=integrator, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
                       periodic=1, dt=1.0, gamma=1e-3, temperature=300.0, r_on=args.r_on,
                       r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
                       rebuild_interval=args.rebuild, seed=0, cell_size=system.cell_size,
-                      use_graph=0 if args.no_graph else 1)
+                      use_graph=0 if args.no_graph else 1, rate_mode=rate_mode)
     sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
     sim.set_state(pos=state[0], vel=state[1], step=0)
     sim.step(args.warmup)
@@ -153,41 +156,47 @@ def run_batch(args, ff):
     import paper_2002_07109_amd as B
     from workloads import droplet_batch
     systems = droplet_batch(64)
-    mk = lambda integ, gamma, seed: B.make_params(
+    mk = lambda integ, gamma, seed, mode=0: B.make_params(
         integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_BARE, periodic=0,
         dt=args.batch_dt, gamma=gamma, temperature=300.0, r_on=7.0, r_off=8.0, r_cut=9.0,
-        skin=2.0, rebuild_interval=10, seed=seed, cell_size=systems[0].cell_size, use_graph=1)
+        skin=2.0, rebuild_interval=10, seed=seed, cell_size=systems[0].cell_size, use_graph=1,
+        rate_mode=mode)
     # relax the lattice starts (BAOAB with strong friction, untimed)
     sim = B.Simulation(systems, mk(B.BAOAB, 0.05, 99), ff["charge"], ff["eps"], ff["sigma"])
     sim.step(800)
     sim.sync()
     pos, vel = sim.pos.cpu().numpy(), sim.vel.cpu().numpy()
     sim.close()
-    sim = B.Simulation(systems, mk(B.BJAOAJB, 1e-3, 0), ff["charge"], ff["eps"], ff["sigma"])
-    sim.set_state(pos=pos, vel=vel, step=0)
-    sim.step(50)
-    sim.sync()
-    lanes, tune = sim.autotune(reps=10)
-    sim.step(10)
-    sim.sync()
-    c0 = [sim.counters(r)["proposals"] for r in range(len(systems))]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.batch_steps)
-    sim.sync()
-    wall = time.perf_counter() - t0
-    c1 = [sim.counters(r)["proposals"] for r in range(len(systems))]
-    n = sim.n
     sizes = [s.n_atoms for s in systems]
-    sim.close()
-    ms = 1e3 * wall / args.batch_steps
-    return {"workload": "64 non-periodic flexible-water droplets, %d-%d atoms (%d in all), bare "
-                        "Coulomb + LJ, rc 9 A, BOUNCE r'/r'' = 7/8 A, dt %g fs, FP32 pair arithmetic"
-                        % (min(sizes), max(sizes), n, args.batch_dt),
-            "steps": args.batch_steps, "ms_per_step": round(ms, 5),
-            "atom_steps_per_s": n * 1e3 / ms,
-            "proposals_per_step": (sum(c1) - sum(c0)) / args.batch_steps,
-            "pair_lanes": lanes}
+    out = {"workload": "64 non-periodic flexible-water droplets, %d-%d atoms (%d in all), bare "
+                       "Coulomb + LJ, rc 9 A, BOUNCE r'/r'' = 7/8 A, dt %g fs, FP32 pair arithmetic"
+                       % (min(sizes), max(sizes), sum(sizes), args.batch_dt),
+           "steps": args.batch_steps}
+    for mode_name, mode in (("atom_bounds", 0), ("pair_bounds", 1)):
+        sim = B.Simulation(systems, mk(B.BJAOAJB, 1e-3, 0, mode), ff["charge"], ff["eps"],
+                           ff["sigma"])
+        sim.set_state(pos=pos, vel=vel, step=0)
+        sim.step(50)
+        sim.sync()
+        lanes, tune = sim.autotune(reps=10)
+        sim.step(10)
+        sim.sync()
+        c0 = [sim.counters(r) for r in range(len(systems))]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.batch_steps)
+        sim.sync()
+        wall = time.perf_counter() - t0
+        c1 = [sim.counters(r) for r in range(len(systems))]
+        n = sim.n
+        sim.close()
+        ms = 1e3 * wall / args.batch_steps
+        diff = lambda k: (sum(c[k] for c in c1) - sum(c[k] for c in c0)) / args.batch_steps
+        out[mode_name] = {"ms_per_step": round(ms, 5), "atom_steps_per_s": n * 1e3 / ms,
+                          "proposals_per_step": diff("proposals"),
+                          "accepted_per_step": diff("accepted"), "pair_lanes": lanes}
+        log(f"batch {mode_name}: {out[mode_name]}")
+    return out
 
 
 def run_accuracy(args, system, ff, state):
@@ -281,6 +290,9 @@ def main():
     ap.add_argument("--rebuild", type=int, default=10)
     ap.add_argument("--alpha", type=float, default=0.45)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--rate-mode", choices=sorted(RATE_MODES), default="atom",
+                    help="jump rate bounds of the headline BOUNCE run: one per atom type "
+                         "(atom) or per type pair, superposed (pair); the other is also timed")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--batch", action="store_true",
@@ -310,9 +322,12 @@ def main():
 
     import paper_2002_07109_amd as B
     res = {}
-    for name, integ in (("baoab", B.BAOAB), ("bounce", B.BJAOAJB)):
+    mode = RATE_MODES[args.rate_mode]
+    other = "pair" if args.rate_mode == "atom" else "atom"
+    for name, integ, rm in (("baoab", B.BAOAB, 0), ("bounce", B.BJAOAJB, mode),
+                            ("bounce_" + other, B.BJAOAJB, RATE_MODES[other])):
         log(f"timing {name}: {args.warmup} warmup + {args.steps} steps")
-        res[name] = run_gpu(args, system, ff, integ, state)
+        res[name] = run_gpu(args, system, ff, integ, state, rate_mode=rm)
         log(f"{name}: {res[name]['ms_per_step']:.4f} ms/step, step kernel "
             f"{res[name]['step_kernel_ms']*1e3:.1f} us, T_kin {res[name]['t_kin']:.1f} K")
 
@@ -356,7 +371,15 @@ def main():
                    "pair_kernel_us": round(bo["pair_kernel_ms"] * 1e3, 3),
                    "list_build_us": round(bo["build_ms"] * 1e3, 3),
                    "pair_lanes": bo["lanes"], "autotune_ms": bo["tune_ms"],
+                   "rate_bounds": args.rate_mode,
                    "t_kin_K": round(bo["t_kin"], 2), "e_pot": round(bo["e_pot"], 2)},
+        "bounce_%s_bounds" % other: {
+            "ms_per_step": round(res["bounce_" + other]["ms_per_step"], 5),
+            "ns_per_day": round(ns_day(res["bounce_" + other]["ms_per_step"]), 3),
+            "proposals_per_step": res["bounce_" + other]["proposals_per_step"],
+            "accepted_per_step": res["bounce_" + other]["accepted_per_step"],
+            "step_kernel_us": round(res["bounce_" + other]["step_kernel_ms"] * 1e3, 3),
+            "list_build_us": round(res["bounce_" + other]["build_ms"] * 1e3, 3)},
         "baoab": {"ns_per_day": round(ns_day(ba["ms_per_step"]), 3),
                   "ms_per_step": round(ba["ms_per_step"], 5),
                   "pair_evals_per_s": full_pairs_ba * steps_s_ba,

@@ -217,13 +217,14 @@ constexpr int LEXCL = 8;       // exclusions per atom held in registers
 // candidate order, so every row comes out in canonical order.
 template <int KC>
 __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInfo *__restrict__ reps,
-                                                   const int32_t *__restrict__ cell_rep, Topo tp,
+                                                   const int32_t *__restrict__ cell_rep,
+                                                   const double *__restrict__ pos, Topo tp,
                                                    ListSet ls, BuildSpec bs, DevState *st)
 {
     __shared__ double cx[LCAP], cy[LCAP], cz[LCAP];
     __shared__ int32_t cj[LCAP];
-    __shared__ uint8_t ct[LCAP];
-    __shared__ int32_t rowf[LMAXI], rowg[LMAXI], rowc[LMAXI * MAXT];
+    __shared__ uint8_t ct[KC > 1 ? LCAP : 1];
+    __shared__ int32_t rowf[LMAXI], rowg[LMAXI], rowc[LMAXI * KC];
     __shared__ double iexr2[LMAXI];
     __shared__ int32_t dcell[3][LDIM];
     __shared__ double dgap[3][LDIM];
@@ -254,23 +255,25 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     // the cell's own atoms (on the last wavefront, while the first enumerates
     // the candidate cells): positions, exclusions, and the largest squared
     // distance to the atom itself or an excluded partner, computed exactly as
-    // the predicate below computes it; no candidate farther than that can be
-    // excluded, so the exclusion test runs only at or below it
+    // the predicate below computes it (the mirror holds the caller's positions
+    // bit for bit); no candidate farther than that can be excluded, so the
+    // exclusion test runs only at or below it
     if (w == LB - 1) {
         for (int32_t k = lane; k < ni; k += 64) {
             rowf[k] = rowg[k] = 0;
-            for (int b = 0; b < MAXT; ++b) rowc[k * MAXT + b] = 0;
-            const double4 x = X[bi + k];
+            for (int b = 0; b < KC; ++b) rowc[k * KC + b] = 0;
+            const int32_t g = ls.perm[bi + k];
+            const double4 x = make_double4(pos[3 * (int64_t)g], pos[3 * (int64_t)g + 1],
+                                           pos[3 * (int64_t)g + 2], 0.0);
             ipos[k] = x;
-            const int32_t g = mirror_id(x.w);
             const int32_t e_b = tp.excl_ptr[g], e_n = tp.excl_ptr[g + 1] - e_b;
             double m2 = 0.0;
             for (int32_t t = 0; t < LEXCL; ++t) {
-                const int32_t se = t < e_n ? ls.inv_perm[tp.excl_idx[e_b + t]] : -1;
-                iex[k][t] = se;     // excluded partners as sorted positions
-                if (se >= 0) {
-                    const double4 xe = X[se];
-                    double dx = x.x - xe.x, dy = x.y - xe.y, dz = x.z - xe.z;
+                const int32_t ge = t < e_n ? tp.excl_idx[e_b + t] : -1;
+                iex[k][t] = ge;     // excluded partners' caller ids
+                if (ge >= 0) {
+                    const double *xe = pos + 3 * (int64_t)ge;
+                    double dx = x.x - xe[0], dy = x.y - xe[1], dz = x.z - xe[2];
                     box.apply(dx, dy, dz);
                     m2 = fmax(m2, norm2_exact(dx, dy, dz));
                 }
@@ -384,7 +387,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             cx[f] = x.x;
             cy[f] = x.y;
             cz[f] = x.z;
-            ct[f] = (uint8_t)mirror_type(x.w);
+            if (KC > 1) ct[f] = (uint8_t)mirror_type(x.w);
         }
         __syncthreads();
         // (3) this wavefront's atoms of the cell against the batch
@@ -397,7 +400,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             for (int t = 0; t < LEXCL; ++t) ex_id[t] = iex[k][t];
             int32_t nf = rowf[k], ng = rowg[k], nc[KC];
 #pragma unroll
-            for (int b = 0; b < KC; ++b) nc[b] = rowc[k * MAXT + b];
+            for (int b = 0; b < KC; ++b) nc[b] = rowc[k * KC + b];
             int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
             int32_t *crow = ls.clist + (int64_t)i * ls.ncls * ls.ccap;
             for (int32_t f0 = 0; f0 < nb; f0 += 64) {
@@ -412,9 +415,10 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                     if (r2 < rmax2) {
                         bool ex = false;
                         if (r2 <= exr2) {      // the atom itself or possibly excluded
+                            const int32_t gj = ls.perm[j];
                             ex = j == i;
 #pragma unroll
-                            for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == j;
+                            for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == gj;
                         }
                         if (!ex) {
                             const bool in_f = bs.want_force && r2 < bs.rf2;
@@ -454,7 +458,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                 rowf[k] = nf;
                 rowg[k] = ng;
 #pragma unroll
-                for (int b = 0; b < KC; ++b) rowc[k * MAXT + b] = nc[b];
+                for (int b = 0; b < KC; ++b) rowc[k * KC + b] = nc[b];
             }
         }
         __syncthreads();
@@ -466,7 +470,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
         if (full) overflow = true;
         if (bs.want_cand)
             for (int b = 0; b < ls.ncls; ++b) {
-                const int32_t nc = rowc[k * MAXT + b];
+                const int32_t nc = rowc[k * KC + b];
                 ls.ccnt[(int64_t)(bi + k) * ls.ncls + b] = min(nc, ls.ccap);
                 if (nc > ls.ccap) overflow = true;
             }
@@ -487,13 +491,17 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
                        pos, tp, ls, st, bs.mirror_sel, bs.step_off);
-    // one candidate class (or none) needs no per-class appends
-    if (ls.ncls > 1 && bs.want_cand)
-        hipLaunchKernelGGL(k_lists<MAXT>, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps,
-                           cell_rep, tp, ls, bs, st);
+    // candidate classes rounded up to 1, 2, 4 or 8 (one class: no per-class appends)
+    const int nc = bs.want_cand ? ls.ncls : 1;
+    const dim3 grid(ls.n_cells), block(64 * LB);
+    if (nc <= 1)
+        hipLaunchKernelGGL(k_lists<1>, grid, block, 0, sm, ls.n_cells, reps, cell_rep, pos, tp, ls, bs, st);
+    else if (nc <= 2)
+        hipLaunchKernelGGL(k_lists<2>, grid, block, 0, sm, ls.n_cells, reps, cell_rep, pos, tp, ls, bs, st);
+    else if (nc <= 4)
+        hipLaunchKernelGGL(k_lists<4>, grid, block, 0, sm, ls.n_cells, reps, cell_rep, pos, tp, ls, bs, st);
     else
-        hipLaunchKernelGGL(k_lists<1>, dim3(ls.n_cells), dim3(64 * LB), 0, sm, ls.n_cells, reps,
-                           cell_rep, tp, ls, bs, st);
+        hipLaunchKernelGGL(k_lists<8>, grid, block, 0, sm, ls.n_cells, reps, cell_rep, pos, tp, ls, bs, st);
 }
 
 }  // namespace bnc
