@@ -199,12 +199,36 @@ def run_batch(args, ff):
     return out
 
 
+RDF_RMAX, RDF_BINS = 8.0, 160
+
+
+def structure_summary(counts, n_samples, n_o, volume):
+    """O-O radial distribution from accumulated pair counts: first peak position
+    and height, first minimum, and the coordination number up to that minimum."""
+    dr = RDF_RMAX / RDF_BINS
+    edges = np.arange(RDF_BINS + 1) * dr
+    shell = 4.0 / 3.0 * np.pi * np.diff(edges ** 3)
+    rho = n_o / volume
+    g = counts[0, 0] / (n_samples * n_o * rho * shell)
+    mid = 0.5 * (edges[1:] + edges[:-1])
+    k1 = int(np.argmax(g))
+    kmin = k1 + int(np.argmin(g[k1:k1 + int(2.0 / dr)]))
+    coord = float(counts[0, 0, :kmin + 1].sum() / (n_samples * n_o))
+    return {"oo_peak_r": round(float(mid[k1]), 3), "oo_peak_g": round(float(g[k1]), 3),
+            "oo_min_r": round(float(mid[kmin]), 3), "oo_coordination": round(coord, 3)}
+
+
 def run_accuracy(args, system, ff, state):
     """<T_kin> and <E_pot> per water of BOUNCE and BAOAB at 1 fs against BAOAB at
     0.25 fs (the reference), each over args.accuracy ps from the same state,
-    sampled every 100 fs; errors are block standard errors (10 blocks)."""
+    sampled every 100 fs; errors are block standard errors (10 blocks).  Also
+    the O-O radial distribution (first peak, coordination) accumulated over the
+    samples and the O self-diffusion coefficient from the slope of the
+    unwrapped mean squared displacement over the second half of the run."""
     import paper_2002_07109_amd as B
     out = {}
+    n_o = int((system.atom_type == 0).sum())
+    volume = float(np.prod(system.box))
     for name, integ, dt in (("bounce_1fs", B.BJAOAJB, 1.0), ("baoab_1fs", B.BAOAB, 1.0),
                             ("baoab_0.25fs", B.BAOAB, 0.25)):
         p = B.make_params(integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
@@ -217,17 +241,26 @@ def run_accuracy(args, system, ff, state):
         per = int(round(100.0 / dt))
         n_samples = int(round(args.accuracy * 1000.0 / 100.0))
         sim.step(int(round(2000.0 / dt)))        # 2 ps to decorrelate from the start
-        T, E = [], []
+        ref = sim.pos.clone()
+        T, E, msd = [], [], []
+        counts = np.zeros((2, 2, RDF_BINS))
         for _ in range(n_samples):
             sim.step(per)
             e = sim.energies()[0]
             T.append(e["tkin"])
             E.append((e["pair"] + e["bond"] + e["angle"]) / (system.n_atoms / 3))
+            counts += sim.rdf_counts(RDF_RMAX, RDF_BINS)
+            msd.append(sim.msd(ref)[0, 0])
         sim.close()
         res = {}
         for key, x in (("t_kin_K", np.array(T)), ("e_pot_per_water", np.array(E))):
             blocks = x[: len(x) // 10 * 10].reshape(10, -1).mean(1)
             res[key] = [round(float(x.mean()), 4), round(float(blocks.std(ddof=1) / np.sqrt(10)), 4)]
+        res.update(structure_summary(counts, n_samples, n_o, volume))
+        t_fs = 100.0 * np.arange(1, n_samples + 1)
+        half = n_samples // 2
+        slope = np.polyfit(t_fs[half:], np.array(msd)[half:], 1)[0]    # A^2 / fs
+        res["d_o_1e-5_cm2_s"] = round(float(slope / 6.0 * 1e4), 3)
         out[name] = res
         log(f"accuracy {name}: {res}")
     return out

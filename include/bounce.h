@@ -186,6 +186,23 @@ bounce_status bounce_rate_weights(const bounce_ctx *ctx, uint32_t *Lq_host, doub
    the current candidate lists, random stream (step, phase).  Synchronous. */
 bounce_status bounce_jump_halfstep(bounce_ctx *ctx, int64_t step, int32_t phase);
 
+/* Pair-structure diagnostic (the radial distribution functions that Sec. VI
+   compares between integrators) at the current positions: ordered
+   non-excluded pairs (i != j) of every replica with r < r_max, counted per
+   type pair and bin into counts_host[n_types][n_types][n_bins]; a pair is in
+   bin k when (k dr)^2 <= r^2 < ((k+1) dr)^2, dr = r_max / n_bins, with the
+   displacement minimum-imaged and squared in FP64 (the oracle's rule, so the
+   counts are exact).  Needs 0 < r_max <= r_cut and n_types^2 n_bins <= 8192
+   (BOUNCE_E_ARG otherwise).  Rebuilds the auxiliary list.  Synchronous. */
+bounce_status bounce_rdf_counts(bounce_ctx *ctx, double r_max, int32_t n_bins,
+                                uint64_t *counts_host);
+/* Mean squared displacement from reference positions ref_dev ([N][3] float64,
+   caller order, device memory owned by the caller) per replica and atom type:
+   out_host[n_replicas][n_types] (0 where a replica has no atom of a type).
+   Positions are never wrapped into the box, so this is the unwrapped MSD of
+   the Einstein relation.  Synchronous. */
+bounce_status bounce_msd(bounce_ctx *ctx, const double *ref_dev, double *out_host);
+
 /* Direct-space energy E = sum_{i<j, not excluded, r<rc} W_sf,ij of replica 0's
    topology at positions pos_dev ([N][3]) with per-type parameters
    params_dev = [charge[nt], eps[nt], sigma[nt]] (device); writes the scalar to

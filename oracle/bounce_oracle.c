@@ -789,6 +789,31 @@ done:
 /* ------------------------------------------------------------------------ */
 /* Differentiable direct-space energy (Sec. V E_direct + E_VdW, full cutoff) */
 /* ------------------------------------------------------------------------ */
+/* Structure diagnostic (the paper compares pair structure of BOUNCE and
+   reference runs, Sec. VI): ordered non-excluded pairs (i != j) with
+   r^2 < r_max^2 counted per type pair in bins of width dr = r_max / nbins,
+   pair (i, j) in bin k when (k dr)^2 <= r^2 < ((k + 1) dr)^2.  Brute force. */
+void orc_rdf_counts(const orc_params *p, const orc_topology *t, const double *q, double r_max,
+                    int32_t nbins, int64_t *counts)
+{
+    const int nt = p->n_types;
+    const double dr = r_max / (double)nbins, rmax2 = r_max * r_max;
+    excl_table ex = make_excl(t);
+    memset(counts, 0, sizeof(int64_t) * (size_t)nt * nt * nbins);
+    for (int32_t i = 0; i < t->n_atoms; ++i)
+        for (int32_t j = 0; j < t->n_atoms; ++j) {
+            if (j == i || excluded(&ex, i, j)) continue;
+            double d[3];
+            min_image(p, q + 3 * i, q + 3 * j, d);
+            const double r2 = norm2(d);
+            if (!(r2 < rmax2)) continue;
+            int32_t k = 0;
+            while (k + 1 < nbins && ((double)(k + 1) * dr) * ((double)(k + 1) * dr) <= r2) ++k;
+            counts[((int64_t)t->type[i] * nt + t->type[j]) * nbins + k]++;
+        }
+    free_excl(&ex);
+}
+
 double orc_direct_energy(const orc_params *p, const orc_topology *t, const double *q,
                          double *grad_q, double *grad_charge, double *grad_eps, double *grad_sigma)
 {

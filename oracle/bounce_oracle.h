@@ -144,6 +144,12 @@ int orc_jump_halfstep(const orc_params *p, const orc_topology *t, const double *
 int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, int64_t step0,
             int32_t nsteps, orc_event *ev, int64_t ev_cap, int64_t *n_ev, orc_counters *cnt);
 
+/* ordered non-excluded pairs (i != j) with r < r_max per type pair and bin:
+   counts[(t_i * n_types + t_j) * nbins + k], (k dr)^2 <= r^2 < ((k+1) dr)^2,
+   dr = r_max / nbins */
+void orc_rdf_counts(const orc_params *p, const orc_topology *t, const double *q, double r_max,
+                    int32_t nbins, int64_t *counts);
+
 /* direct-space energy sum_{i<j, not excluded, r<rc} W_sf and its gradients with
    respect to positions and per-type charge, epsilon, sigma (NULL = skip). */
 double orc_direct_energy(const orc_params *p, const orc_topology *t, const double *q,

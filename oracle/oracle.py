@@ -108,6 +108,7 @@ def lib():
         L.orc_jump_halfstep.restype = C.c_int
         L.orc_run.argtypes = [P, T, vp, vp, i64, i32, vp, i64, vp, C.POINTER(Counters)]
         L.orc_run.restype = C.c_int
+        L.orc_rdf_counts.argtypes = [P, T, vp, C.c_double, i32, vp]
         L.orc_direct_energy.argtypes = [P, T, vp, vp, vp, vp, vp]
         L.orc_direct_energy.restype = C.c_double
         _lib = L
@@ -335,6 +336,16 @@ def run(p, topo, q, v, step0, nsteps, ev_cap=0):
     return dict(q=q, v=v, status=st, status_name=STATUS.get(st, str(st)),
                 counters=cnt.as_dict(), n_events=nev.value,
                 events=ev[:min(nev.value, ev_cap)] if ev_cap else None)
+
+
+def rdf_counts(p, topo, q, r_max, nbins):
+    """Ordered non-excluded pair counts [n_types, n_types, nbins] with r < r_max."""
+    q = np.ascontiguousarray(q, np.float64)
+    nt = p.n_types
+    counts = np.zeros(nt * nt * nbins, np.int64)
+    lib().orc_rdf_counts(C.byref(p), C.byref(topo.c), _ptr(q), float(r_max), int(nbins),
+                         _ptr(counts))
+    return counts.reshape(nt, nt, nbins)
 
 
 def direct_energy(p, topo, q, grads=True):

@@ -223,6 +223,26 @@ class Simulation:
               "bounce_rate_weights")
         return lq.reshape(nt, nt), unit
 
+    def rdf_counts(self, r_max, n_bins):
+        """Ordered non-excluded pair counts [n_types, n_types, n_bins] with r < r_max
+        at the current positions (all replicas)."""
+        nt = self.n_types
+        out = np.zeros(nt * nt * int(n_bins), np.uint64)
+        check(self.L.bounce_rdf_counts(self.ctx, float(r_max), int(n_bins), _ptr(out)), self.ctx,
+              "bounce_rdf_counts")
+        return out.reshape(nt, nt, int(n_bins))
+
+    def msd(self, ref):
+        """Mean squared displacement from ref (a float64 (N, 3) tensor on the device)
+        per replica and atom type: array [n_replicas, n_types]."""
+        ref = ref.contiguous()
+        if ref.dtype != self.torch.float64 or ref.device != self.pos.device or \
+                tuple(ref.shape) != tuple(self.pos.shape):
+            raise ValueError("ref must be a float64 (N, 3) tensor on the simulation's device")
+        out = np.zeros((len(self.offsets) - 1) * self.n_types, np.float64)
+        check(self.L.bounce_msd(self.ctx, _tptr(ref), _ptr(out)), self.ctx, "bounce_msd")
+        return out.reshape(-1, self.n_types)
+
     def jump_halfstep(self, step, phase):
         check(self.L.bounce_jump_halfstep(self.ctx, int(step), int(phase)), self.ctx,
               "bounce_jump_halfstep")

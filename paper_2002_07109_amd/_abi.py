@@ -78,6 +78,8 @@ SIGNATURES = {
     "bounce_get_list": (i32, [ctx_p, i32, vp, vp, i64]),
     "bounce_rate_bounds": (i32, [ctx_p, vp, vp]),
     "bounce_rate_weights": (i32, [ctx_p, vp, vp]),
+    "bounce_rdf_counts": (i32, [ctx_p, C.c_double, i32, vp]),
+    "bounce_msd": (i32, [ctx_p, vp, vp]),
     "bounce_jump_halfstep": (i32, [ctx_p, i64, i32]),
     "bounce_direct_energy": (i32, [ctx_p, vp, vp, vp]),
     "bounce_direct_energy_bwd": (i32, [ctx_p, vp, vp, vp, vp, vp]),

@@ -110,6 +110,7 @@ struct bounce_ctx {
     int64_t *d_rep_off = nullptr, *d_one_seg = nullptr;
     int32_t *d_cell_rep = nullptr;
     uint32_t *d_Lq = nullptr;
+    unsigned long long *d_rdf = nullptr;
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
     // schedule
@@ -413,7 +414,7 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
-        seg, xcnt, xcol, cell_rep;
+        seg, xcnt, xcol, cell_rep, rdf;
     size_t ls[2][15];
 };
 
@@ -452,6 +453,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.fpair = L.take(24 * n);
     o.atom = L.take(8 * n * std::max(5, 3 * MAXT));
     o.seg = L.take(8 * 8 * R);
+    o.rdf = L.take(8 * (size_t)RDF_MAX_BINS);
     o.xcnt = L.take(4 * n);
     o.xcol = L.take(4 * n * (size_t)c->xcap);
     for (int k = 0; k < 2; ++k) {
@@ -566,6 +568,7 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     c->d_fpair = at<double>(ws, o.fpair);
     c->d_atom = at<double>(ws, o.atom);
     c->d_seg = at<double>(ws, o.seg);
+    c->d_rdf = at<unsigned long long>(ws, o.rdf);
     c->d_ou_c2 = at<double>(ws, o.ou_c2);
     c->d_xcnt = at<int32_t>(ws, o.xcnt);
     c->d_xcol = at<int32_t>(ws, o.xcol);
@@ -1025,6 +1028,44 @@ bounce_status bounce_rate_bounds(const bounce_ctx *c, double *L_ab, double *L_a)
     if (!c->have_system) return BOUNCE_E_STATE;
     std::memcpy(L_ab, c->L_ab.data(), 8 * c->L_ab.size());
     std::memcpy(L_a, c->L_a.data(), 8 * c->L_a.size());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_rdf_counts(bounce_ctx *c, double r_max, int32_t n_bins, uint64_t *counts)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!counts || !(r_max > 0.0) || !(r_max <= c->p.r_cut) || n_bins < 1 ||
+        (int64_t)c->nt * c->nt * n_bins > RDF_MAX_BINS)
+        return fail(c, BOUNCE_E_ARG, "rdf: 0 < r_max <= r_cut and n_types^2 n_bins <= 8192");
+    hipStream_t sm = c->stream;
+    const size_t nh = (size_t)c->nt * c->nt * n_bins;
+    // the aux list set: every non-excluded pair within r_cut + 0.01 at the current positions
+    launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    HIPCHK(c, hipMemsetAsync(c->d_rdf, 0, 8 * nh, sm));
+    launch_rdf(sm, c->n, c->d_reps, c->R == 1, c->aux, r_max, n_bins, c->nt, c->d_rdf);
+    HIPCHK(c, hipMemcpyAsync(counts, c->d_rdf, 8 * nh, hipMemcpyDeviceToHost, sm));
+    return bounce_sync(c);
+}
+
+bounce_status bounce_msd(bounce_ctx *c, const double *ref, double *out)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!ref || !out) return BOUNCE_E_ARG;
+    hipStream_t sm = c->stream;
+    launch_msd_atom(sm, c->n, c->pos, ref, c->tp.type, c->d_atom);
+    launch_segment_sum(sm, c->R, c->d_rep_off, c->d_atom, c->nt, MAXT, 0, c->d_seg);
+    std::vector<double> seg((size_t)c->R * c->nt);
+    HIPCHK(c, hipMemcpyAsync(seg.data(), c->d_seg, 8 * seg.size(), hipMemcpyDeviceToHost, sm));
+    s = bounce_sync(c);
+    if (s) return s;
+    for (int32_t r = 0; r < c->R; ++r) {
+        std::vector<int64_t> cnt(c->nt, 0);
+        for (int64_t g = c->rep_off[r]; g < c->rep_off[r + 1]; ++g) cnt[c->type[g]]++;
+        for (int a = 0; a < c->nt; ++a)
+            out[(int64_t)r * c->nt + a] = cnt[a] ? seg[(size_t)r * c->nt + a] / (double)cnt[a] : 0.0;
+    }
     return BOUNCE_OK;
 }
 

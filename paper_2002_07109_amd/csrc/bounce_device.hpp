@@ -15,6 +15,8 @@ constexpr int MAXT = 8;
 // jump bounds as integer weights: 2^WEIGHT_BITS units make the bound of an atom type
 constexpr int WEIGHT_BITS = 20;
 constexpr double WEIGHT_SLACK = 1e-4;
+// pair-structure histogram: at most this many (type pair, bin) counters
+constexpr int RDF_MAX_BINS = 8192;
 
 // latched device conditions
 enum : uint32_t {

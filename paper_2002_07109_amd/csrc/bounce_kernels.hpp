@@ -82,6 +82,11 @@ void launch_step(hipStream_t sm, const StepArgs &a);
 // device step counter += count (one thread; orders after the preceding launches)
 void launch_advance(hipStream_t sm, DevState *st, int32_t count);
 void launch_jump(hipStream_t sm, const JumpArgs &a);
+void launch_rdf(hipStream_t sm, int32_t n, const RepInfo *reps, int32_t single_rep,
+                const ListSet &ls, double r_max, int32_t nbins, int32_t nt,
+                unsigned long long *counts);
+void launch_msd_atom(hipStream_t sm, int32_t n, const double *pos, const double *ref,
+                     const int32_t *type, double *vals);
 void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
                            int32_t *cnt_global, int32_t *col_global, int32_t cap);
 void launch_dbwd_finish(hipStream_t sm, int32_t n, int32_t n_types, const double *atom_basis,

@@ -478,6 +478,61 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     if (__syncthreads_or(overflow) && threadIdx.x == 0) atomicOr(&st->status, ST_CAPACITY);
 }
 
+// Pair-structure histogram over the rows of a list set built at or beyond
+// r_max: each ordered pair (i, j) with r^2 < r_max^2 counted in bin k with
+// (k dr)^2 <= r^2 < ((k+1) dr)^2 of its type pair, the displacement
+// minimum-imaged and squared in FP64 as the list predicate is (this unit is
+// compiled without contraction).  RG lanes per atom, a workgroup histogram
+// in LDS flushed with 64-bit atomics.
+constexpr int RG = 16;
+
+__global__ void __launch_bounds__(256) k_rdf(int32_t n, const RepInfo *__restrict__ reps,
+                                             int32_t single_rep, ListSet ls, double rmax2, double dr,
+                                             int32_t nbins, int32_t nt,
+                                             unsigned long long *__restrict__ counts)
+{
+    extern __shared__ uint32_t hist[];
+    const int32_t nh = nt * nt * nbins;
+    for (int32_t k = threadIdx.x; k < nh; k += blockDim.x) hist[k] = 0u;
+    __syncthreads();
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = t / RG, lig = t % RG;
+    if (s < n) {
+        const double4 *__restrict__ X = ls.x[0];
+        const double4 xi = X[s];
+        const int ti = mirror_type(xi.w);
+        const BoxReg box(load_rep(reps, single_rep, ls.sinfo[s].y));
+        const int32_t *row = ls.flist + (int64_t)s * ls.fcap;
+        const int2 fc = ls.fcnt[s];
+        const int32_t nn = fc.x, cnt = fc.x + fc.y, tail = ls.fcap - 1 + nn;
+        for (int32_t e = lig; e < cnt; e += RG) {
+            const double4 xj = X[row[e < nn ? e : tail - e]];
+            double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+            box.apply(dx, dy, dz);
+            const double r2 = norm2_exact(dx, dy, dz);
+            if (!(r2 < rmax2)) continue;
+            int32_t k = min(max((int32_t)(sqrt(r2) / dr), 0), nbins - 1);
+            while (k > 0 && ((double)k * dr) * ((double)k * dr) > r2) --k;
+            while (k + 1 < nbins && ((double)(k + 1) * dr) * ((double)(k + 1) * dr) <= r2) ++k;
+            atomicAdd(&hist[(ti * nt + mirror_type(xj.w)) * nbins + k], 1u);
+        }
+    }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < nh; k += blockDim.x)
+        if (hist[k]) atomicAdd(&counts[k], (unsigned long long)hist[k]);
+}
+
+void launch_rdf(hipStream_t sm, int32_t n, const RepInfo *reps, int32_t single_rep,
+                const ListSet &ls, double r_max, int32_t nbins, int32_t nt,
+                unsigned long long *counts)
+{
+    if (n <= 0) return;
+    const double dr = r_max / (double)nbins;
+    const size_t lds = sizeof(uint32_t) * (size_t)nt * nt * nbins;
+    hipLaunchKernelGGL(k_rdf, dim3(((int64_t)n * RG + 255) / 256), dim3(256), lds, sm, n, reps,
+                       single_rep, ls, r_max * r_max, dr, nbins, nt, counts);
+}
+
 void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *reps,
                   const int32_t *cell_rep, const Topo &tp, const ListSet &ls, const BuildSpec &bs,
                   DevState *st)

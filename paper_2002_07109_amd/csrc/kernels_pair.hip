@@ -399,6 +399,28 @@ void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, c
                        col0, out);
 }
 
+// squared displacement |q_g - ref_g|^2 of each atom into its type's column of
+// vals[g][MAXT] (the other columns zero), for per-replica sums
+__global__ void k_msd_atom(int32_t n, const double *__restrict__ pos, const double *__restrict__ ref,
+                           const int32_t *__restrict__ type, double *__restrict__ vals)
+{
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const double dx = pos[3 * (int64_t)g] - ref[3 * (int64_t)g];
+    const double dy = pos[3 * (int64_t)g + 1] - ref[3 * (int64_t)g + 1];
+    const double dz = pos[3 * (int64_t)g + 2] - ref[3 * (int64_t)g + 2];
+    const int ty = type[g];
+    double *row = vals + (int64_t)g * MAXT;
+    for (int c = 0; c < MAXT; ++c) row[c] = c == ty ? dx * dx + dy * dy + dz * dz : 0.0;
+}
+
+void launch_msd_atom(hipStream_t sm, int32_t n, const double *pos, const double *ref,
+                     const int32_t *type, double *vals)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_msd_atom, dim3((n + 255) / 256), dim3(256), 0, sm, n, pos, ref, type, vals);
+}
+
 // lists in caller ids, rows indexed by caller id
 __global__ void k_list_to_global(int32_t n, ListSet ls, int32_t which, int32_t *cnt_global,
                                  int32_t *col_global, int32_t cap)
