@@ -375,6 +375,7 @@ def main():
     # the dominant kernel of a step is the F_0 pair kernel
     achieved = short_pairs * FLOPS_SHORT / (bo["pair_kernel_ms"] * 1e-3) / 1e12
     achieved_ba = full_pairs_ba * FLOPS_FULL / (ba["pair_kernel_ms"] * 1e-3) / 1e12
+    traffic = measured_traffic(bo["lanes"])
     line = {
         "metric": "ns/day & pair-evals/s, BOUNCE vs BAOAB 1fs on same GPU, 24k-atom box",
         "value": round(ns_day(bo["ms_per_step"]), 3),
@@ -427,8 +428,12 @@ def main():
         "roofline": {"kernel": "F_0 pair kernel (BOUNCE short range)", "bound": "alu",
                      "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32, 5),
-                     "traffic": measured_traffic(bo["lanes"]),
-                     "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs},
+                     "traffic": traffic,
+                     "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs,
+                     "peak_unpacked": PEAK_FP32 / 2,
+                     "frac_unpacked": round(achieved / (PEAK_FP32 / 2), 5),
+                     "hbm_frac": (round(traffic / (bo["pair_kernel_ms"] * 1e-3) / 8e12, 4)
+                                  if traffic else None)},
     }
     if args.batch:
         log("timing 64 uneven droplets")
