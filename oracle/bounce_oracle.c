@@ -15,6 +15,7 @@
  */
 #include "bounce_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -436,6 +437,12 @@ void orc_gradient(const orc_params *p, const orc_topology *t, const double *q, i
 #pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < t->n_atoms; ++i) gradient_atom(p, t, &ex, q, which, i, g + 3 * i);
     free_excl(&ex);
+    if ((which & ORC_G_RECIP) && p->periodic && p->pme_grid[0] > 0) {
+        double *gr = malloc(sizeof(double) * 3 * (size_t)t->n_atoms), e[3];
+        orc_pme(p, t, q, gr, e);
+        for (int64_t k = 0; k < 3 * (int64_t)t->n_atoms; ++k) g[k] += gr[k];
+        free(gr);
+    }
 }
 
 /* shifted-force Coulomb and LJ parts of one pair */
@@ -491,6 +498,11 @@ void orc_energies(const orc_params *p, const orc_topology *t, const double *q, c
         ek += 0.5 * t->mass[i] * (vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]) / ORC_ACC;
     }
     free_excl(&ex);
+    if (p->periodic && p->pme_grid[0] > 0) {   /* mesh, self and exclusion terms */
+        double e[3];
+        orc_pme(p, t, q, NULL, e);
+        ec += e[0] + e[1] + e[2];
+    }
     out[0] = eb; out[1] = ea; out[2] = ec; out[3] = el; out[4] = ec + el; out[5] = ek;
     out[6] = t->n_atoms > 0 ? 2.0 * ek / (3.0 * t->n_atoms * ORC_KB) : 0.0;
 }
@@ -722,6 +734,206 @@ static int finite_state(const orc_topology *t, const double *q, const double *v)
     return 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Reciprocal-space Ewald: smooth PME (Sec. V; Essmann et al. 1995)          */
+/* ------------------------------------------------------------------------ */
+/* cardinal B-spline of order n, by its recursion (Essmann et al., Eq. 4.1) */
+static double bspline(int n, double u)
+{
+    if (n == 2) return (u < 0.0 || u > 2.0) ? 0.0 : 1.0 - fabs(u - 1.0);
+    return (u * bspline(n - 1, u) + ((double)n - u) * bspline(n - 1, u - 1.0)) / (double)(n - 1);
+}
+
+/* its derivative, M_n'(u) = M_{n-1}(u) - M_{n-1}(u - 1) */
+static double bspline_d(int n, double u) { return bspline(n - 1, u) - bspline(n - 1, u - 1.0); }
+
+/* |b(k)|^2 of one axis (Essmann et al., Eq. 4.7); where the sum vanishes (odd
+   order at k = K/2) the mean of the two neighbouring values is used */
+static void bspline_moduli(int n, int K, double *bsq)
+{
+    for (int k = 0; k < K; ++k) {
+        double complex s = 0.0;
+        for (int j = 0; j <= n - 2; ++j) s += bspline(n, (double)(j + 1)) * cexp(2.0 * M_PI * I * k * j / K);
+        const double d = creal(s * conj(s));
+        bsq[k] = d > 1e-30 ? 1.0 / d : -1.0;
+    }
+    for (int k = 0; k < K; ++k)
+        if (bsq[k] < 0.0) bsq[k] = 0.5 * (bsq[(k + K - 1) % K] + bsq[(k + 1) % K]);
+}
+
+/* one-dimensional DFT along axis `ax` of a K0 x K1 x K2 complex grid, written
+   as the plain sum (sign -1 or +1 in the exponent) */
+static void dft_axis(double complex *a, const int K[3], int ax, int sign)
+{
+    const int n = K[ax];
+    const int64_t stride = ax == 2 ? 1 : (ax == 1 ? K[2] : (int64_t)K[1] * K[2]);
+    double complex *line = malloc(sizeof(double complex) * n), *out = malloc(sizeof(double complex) * n);
+    double complex *tw = malloc(sizeof(double complex) * n);     /* exp(sign 2 pi i j / n) */
+    for (int j = 0; j < n; ++j) tw[j] = cexp(sign * 2.0 * M_PI * I * (double)j / n);
+    const int64_t total = (int64_t)K[0] * K[1] * K[2];
+    for (int64_t base = 0; base < total; ++base) {
+        /* visit each line once: its first element has index 0 along ax */
+        if ((base / stride) % n != 0) continue;
+        for (int l = 0; l < n; ++l) line[l] = a[base + l * stride];
+        for (int k = 0; k < n; ++k) {
+            double complex acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += line[l] * tw[(int64_t)k * l % n];
+            out[k] = acc;
+        }
+        for (int k = 0; k < n; ++k) a[base + k * stride] = out[k];
+    }
+    free(line);
+    free(out);
+    free(tw);
+}
+
+/* the B-spline weights of one atom along one axis: grid points
+   l_j = (floor(u) - j) mod K and M_n(u - floor(u) + j), M_n' likewise */
+static void atom_weights(int n, int K, double u, int *l, double *w, double *dw)
+{
+    const double fl = floor(u);
+    for (int j = 0; j < n; ++j) {
+        int g = ((int)fl - j) % K;
+        if (g < 0) g += K;
+        l[j] = g;
+        w[j] = bspline(n, u - fl + j);
+        dw[j] = bspline_d(n, u - fl + j);
+    }
+}
+
+void orc_pme(const orc_params *p, const orc_topology *t, const double *q, double *grad, double e[3])
+{
+    const int n = p->pme_order;
+    const int K[3] = {p->pme_grid[0], p->pme_grid[1], p->pme_grid[2]};
+    const int64_t KK = (int64_t)K[0] * K[1] * K[2];
+    const double a = p->ewald_alpha;
+    const double V = p->box[0] * p->box[1] * p->box[2];
+    const int32_t N = t->n_atoms;
+    e[0] = e[1] = e[2] = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * 3 * (size_t)N);
+    /* fractional grid coordinates u = K x / L with x wrapped into [0, L) */
+    double *u = malloc(sizeof(double) * 3 * (size_t)N);
+    for (int32_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double x = q[3 * i + c] - p->box[c] * floor(q[3 * i + c] / p->box[c]);
+            u[3 * i + c] = (double)K[c] * x / p->box[c];
+        }
+    /* charge grid Q(l) = sum_i q_i prod_c M_n(u_ic - l_c), periodic images */
+    double complex *Q = calloc((size_t)KK, sizeof(double complex));
+    for (int32_t i = 0; i < N; ++i) {
+        int l[3][ORC_MAX_PME_ORDER];
+        double w[3][ORC_MAX_PME_ORDER], dw[3][ORC_MAX_PME_ORDER];
+        for (int c = 0; c < 3; ++c) atom_weights(n, K[c], u[3 * i + c], l[c], w[c], dw[c]);
+        const double qi = p->charge[t->type[i]];
+        for (int j0 = 0; j0 < n; ++j0)
+            for (int j1 = 0; j1 < n; ++j1)
+                for (int j2 = 0; j2 < n; ++j2)
+                    Q[((int64_t)l[0][j0] * K[1] + l[1][j1]) * K[2] + l[2][j2]] += qi * w[0][j0] * w[1][j1] * w[2][j2];
+    }
+    /* F(Q)(k) = sum_l Q(l) exp(2 pi i k.l / K) */
+    double complex *FQ = malloc(sizeof(double complex) * (size_t)KK);
+    memcpy(FQ, Q, sizeof(double complex) * (size_t)KK);
+    for (int ax = 0; ax < 3; ++ax) dft_axis(FQ, K, ax, +1);
+    /* theta(k) = k_e / (pi V) exp(-pi^2 m^2 / alpha^2) / m^2 B(k), theta(0) = 0 */
+    double *bsq[3];
+    for (int c = 0; c < 3; ++c) {
+        bsq[c] = malloc(sizeof(double) * K[c]);
+        bspline_moduli(n, K[c], bsq[c]);
+    }
+    double Erec = 0.0;
+    for (int k0 = 0; k0 < K[0]; ++k0)
+        for (int k1 = 0; k1 < K[1]; ++k1)
+            for (int k2 = 0; k2 < K[2]; ++k2) {
+                const int64_t idx = ((int64_t)k0 * K[1] + k1) * K[2] + k2;
+                const int kk[3] = {k0, k1, k2};
+                double m2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double mc = (double)(kk[c] <= K[c] / 2 ? kk[c] : kk[c] - K[c]) / p->box[c];
+                    m2 += mc * mc;
+                }
+                double th = 0.0;
+                if (idx != 0)
+                    th = ORC_KE / (M_PI * V) * exp(-M_PI * M_PI * m2 / (a * a)) / m2 * bsq[0][k0] *
+                         bsq[1][k1] * bsq[2][k2];
+                Erec += 0.5 * th * creal(FQ[idx] * conj(FQ[idx]));
+                FQ[idx] *= th;
+            }
+    e[0] = Erec;
+    if (grad) {
+        /* phi(l) = Re sum_k theta(k) F(Q)(k) exp(-2 pi i k.l / K); dE/dx_ic =
+           q_i sum_l phi(l) dQ_i(l)/dx_ic */
+        for (int ax = 0; ax < 3; ++ax) dft_axis(FQ, K, ax, -1);
+        for (int32_t i = 0; i < N; ++i) {
+            int l[3][ORC_MAX_PME_ORDER];
+            double w[3][ORC_MAX_PME_ORDER], dw[3][ORC_MAX_PME_ORDER];
+            for (int c = 0; c < 3; ++c) atom_weights(n, K[c], u[3 * i + c], l[c], w[c], dw[c]);
+            const double qi = p->charge[t->type[i]];
+            double gi[3] = {0.0, 0.0, 0.0};
+            for (int j0 = 0; j0 < n; ++j0)
+                for (int j1 = 0; j1 < n; ++j1)
+                    for (int j2 = 0; j2 < n; ++j2) {
+                        const double phi = creal(FQ[((int64_t)l[0][j0] * K[1] + l[1][j1]) * K[2] + l[2][j2]]);
+                        gi[0] += phi * dw[0][j0] * w[1][j1] * w[2][j2];
+                        gi[1] += phi * w[0][j0] * dw[1][j1] * w[2][j2];
+                        gi[2] += phi * w[0][j0] * w[1][j1] * dw[2][j2];
+                    }
+            for (int c = 0; c < 3; ++c) grad[3 * i + c] = qi * gi[c] * (double)K[c] / p->box[c];
+        }
+    }
+    /* self term and the excluded pairs' share of the mesh sum */
+    double esf = 0.0;
+    for (int32_t i = 0; i < N; ++i) esf += p->charge[t->type[i]] * p->charge[t->type[i]];
+    e[1] = -ORC_KE * a / sqrt(M_PI) * esf;
+    for (int32_t k = 0; k < t->n_excl; ++k) {
+        const int32_t i = t->excl[2 * k], j = t->excl[2 * k + 1];
+        double d[3];
+        min_image(p, q + 3 * i, q + 3 * j, d);
+        const double r = sqrt(norm2(d));
+        const double qq = ORC_KE * p->charge[t->type[i]] * p->charge[t->type[j]];
+        e[2] -= qq * erf(a * r) / r;
+        if (grad) {
+            /* d/dr [erf(a r)/r] = (2a/sqrt(pi) exp(-a^2 r^2) r - erf(a r)) / r^2 */
+            const double dfdr = (2.0 * a / sqrt(M_PI) * exp(-a * a * r * r) * r - erf(a * r)) / (r * r);
+            for (int c = 0; c < 3; ++c) {
+                grad[3 * i + c] -= qq * dfdr * d[c] / r;
+                grad[3 * j + c] += qq * dfdr * d[c] / r;
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) free(bsq[c]);
+    free(u); free(Q); free(FQ);
+}
+
+double orc_ewald_recip(const orc_params *p, const orc_topology *t, const double *q, int32_t kmax,
+                       double *grad)
+{
+    const double a = p->ewald_alpha, V = p->box[0] * p->box[1] * p->box[2];
+    const int32_t N = t->n_atoms;
+    double E = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * 3 * (size_t)N);
+    for (int k0 = -kmax; k0 <= kmax; ++k0)
+        for (int k1 = -kmax; k1 <= kmax; ++k1)
+            for (int k2 = -kmax; k2 <= kmax; ++k2) {
+                if (!k0 && !k1 && !k2) continue;
+                const double m[3] = {k0 / p->box[0], k1 / p->box[1], k2 / p->box[2]};
+                const double m2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+                const double f = ORC_KE / (2.0 * M_PI * V) * exp(-M_PI * M_PI * m2 / (a * a)) / m2;
+                double complex S = 0.0;
+                for (int32_t j = 0; j < N; ++j)
+                    S += p->charge[t->type[j]] *
+                         cexp(2.0 * M_PI * I * (m[0] * q[3 * j] + m[1] * q[3 * j + 1] + m[2] * q[3 * j + 2]));
+                E += f * creal(S * conj(S));
+                if (grad)
+                    for (int32_t i = 0; i < N; ++i) {
+                        /* d|S|^2/dx_i = 2 Re(conj(S) q_i 2 pi i m exp(2 pi i m.x_i)) */
+                        const double complex ei = cexp(2.0 * M_PI * I * (m[0] * q[3 * i] + m[1] * q[3 * i + 1] + m[2] * q[3 * i + 2]));
+                        const double s = 2.0 * creal(conj(S) * p->charge[t->type[i]] * 2.0 * M_PI * I * ei);
+                        for (int c = 0; c < 3; ++c) grad[3 * i + c] += f * s * m[c];
+                    }
+            }
+    return E;
+}
+
 int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, int64_t step0,
             int32_t nsteps, orc_event *ev, int64_t ev_cap, int64_t *n_ev, orc_counters *cnt)
 {
@@ -737,9 +949,15 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
     L.c_ptr = malloc(sizeof(int64_t) * (size_t)(n + 1));
     L.q_build = malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *g = malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    double *grec = malloc(sizeof(double) * 3 * (size_t)(n + 1));
     jump_consts jc = make_jump_consts(p);
     int bounce = p->integrator == ORC_BOUNCE;
     double h = 0.5 * p->dt;
+    /* reciprocal-space force: in F_0 (respa_m = 0) or as RESPA outer half kicks */
+    const int pme = p->periodic && p->pme_grid[0] > 0;
+    const int respa = pme && p->respa_m >= 1;
+    const double H = 0.5 * p->dt * (double)p->respa_m;
+    double erec[3];
 
 #define JUMP(STEP, PHASE)                                                                        \
     do {                                                                                         \
@@ -756,7 +974,11 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
     if (status != ORC_OK) goto done;
     cnt->rebuilds++;
     grad_f0(p, t, q, &L, g, cnt);
+    if (pme) orc_pme(p, t, q, grec, erec);
+    if (pme && !respa)
+        for (int64_t k = 0; k < 3 * (int64_t)n; ++k) g[k] += grec[k];
     for (int64_t n_step = step0; n_step < step0 + nsteps; ++n_step) {
+        if (respa && n_step % p->respa_m == 0) kick(t, v, grec, H);   /* outer half kick */
         kick(t, v, g, h);                          /* B */
         JUMP(n_step, ORC_PH_JA);                   /* J */
         drift(t, q, v, h);                         /* A */
@@ -774,15 +996,19 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
             cnt->rebuilds++;
         }
         grad_f0(p, t, q, &L, g, cnt);
+        if (pme) orc_pme(p, t, q, grec, erec);
+        if (pme && !respa)
+            for (int64_t k = 0; k < 3 * (int64_t)n; ++k) g[k] += grec[k];
         JUMP(n_step, ORC_PH_JB);                   /* J */
         kick(t, v, g, h);                          /* B */
+        if (respa && (n_step + 1) % p->respa_m == 0) kick(t, v, grec, H);   /* outer half kick */
         cnt->steps++;
         if (!finite_state(t, q, v)) { status = ORC_E_NONFINITE; goto done; }
     }
 #undef JUMP
 done:
     free(L.order); free(L.cell); free(L.s_ptr); free(L.c_ptr); free(L.s_col); free(L.c_col);
-    free(L.q_build); free(g);
+    free(L.q_build); free(g); free(grec);
     return status;
 }
 

@@ -24,6 +24,7 @@ extern "C" {
 #endif
 
 #define ORC_MAXT 8
+#define ORC_MAX_PME_ORDER 8
 
 /* physical constants (proposed readings: the paper does not state units) */
 #define ORC_KE 332.0637          /* Coulomb constant, kcal A / (mol e^2) */
@@ -35,7 +36,7 @@ enum { ORC_COUL_BARE = 0, ORC_COUL_EWALD = 1 };
 /* random-stream phases (counter word 1 = phase << 32 | atom) */
 enum { ORC_PH_JA = 0, ORC_PH_O = 1, ORC_PH_JB = 2 };
 /* gradient components */
-enum { ORC_G_BONDED = 1, ORC_G_SHORT = 2, ORC_G_LONG = 4, ORC_G_FULL = 8 };
+enum { ORC_G_BONDED = 1, ORC_G_SHORT = 2, ORC_G_LONG = 4, ORC_G_FULL = 8, ORC_G_RECIP = 16 };
 /* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may
    depend on the types of both atoms).  ATOM: every partner of an atom of type a
    gets the bound L_a = max_b L_ab, one Poisson count over all candidates.
@@ -71,6 +72,15 @@ typedef struct {
     int32_t rate_mode;                      /* ORC_RATE_ATOM or ORC_RATE_PAIR       */
     uint64_t seed, replica;                 /* Philox key                           */
     double charge[ORC_MAXT], eps[ORC_MAXT], sigma[ORC_MAXT];
+    /* reciprocal-space Ewald (Sec. V: SPME) for periodic boxes: grid points
+       per edge (pme_grid[0] = 0: no reciprocal part), B-spline order, and the
+       schedule: respa_m = 0 adds the reciprocal force to F_0 every step (the
+       basic algorithm), respa_m >= 1 applies it as half kicks of m dt around
+       every m steps (the RESPA outer step) */
+    int32_t pme_grid[3];
+    int32_t pme_order;
+    int32_t respa_m;
+    int32_t pad1;
 } orc_params;
 
 typedef struct {
@@ -149,6 +159,17 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
    dr = r_max / nbins */
 void orc_rdf_counts(const orc_params *p, const orc_topology *t, const double *q, double r_max,
                     int32_t nbins, int64_t *counts);
+
+/* Reciprocal-space Ewald by smooth particle-mesh Ewald (Sec. V; Essmann et al.,
+   J. Chem. Phys. 103, 8577 (1995)): energy parts e[0] = E_rec (mesh),
+   e[1] = E_self = -k_e alpha/sqrt(pi) sum q^2, e[2] = E_excl = -k_e sum over
+   excluded pairs q_i q_j erf(alpha r)/r, and the gradient of E_rec + E_excl
+   (NULL = skip).  Charges are the per-type charges. */
+void orc_pme(const orc_params *p, const orc_topology *t, const double *q, double *grad, double e[3]);
+/* the same reciprocal energy and gradient by the plain Ewald sum over
+   reciprocal vectors with |k_a| <= kmax per axis (E_rec only; for checks) */
+double orc_ewald_recip(const orc_params *p, const orc_topology *t, const double *q, int32_t kmax,
+                       double *grad);
 
 /* direct-space energy sum_{i<j, not excluded, r<rc} W_sf and its gradients with
    respect to positions and per-type charge, epsilon, sigma (NULL = skip). */

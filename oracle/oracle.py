@@ -22,7 +22,7 @@ COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
 RATE_ATOM, RATE_PAIR = 0, 1
 WEIGHT_BITS = 20
-G_BONDED, G_SHORT, G_LONG, G_FULL = 1, 2, 4, 8
+G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
 STATUS = {0: "OK", -1: "ARG", -4: "SKIN", -5: "BOUND", -6: "POISSON_CAP", -7: "NONFINITE",
           -9: "GRID"}
 KE, KB, ACC = 332.0637, 0.0019872041, 4.184e-4
@@ -51,7 +51,8 @@ class Params(C.Structure):
                 ("grid_origin", C.c_double * 3), ("grid_dims", C.c_int32 * 3),
                 ("rate_mode", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("charge", C.c_double * MAXT), ("eps", C.c_double * MAXT),
-                ("sigma", C.c_double * MAXT)]
+                ("sigma", C.c_double * MAXT), ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32),
+                ("respa_m", C.c_int32), ("pad1", C.c_int32)]
 
 
 class Topo(C.Structure):
@@ -109,6 +110,9 @@ def lib():
         L.orc_run.argtypes = [P, T, vp, vp, i64, i32, vp, i64, vp, C.POINTER(Counters)]
         L.orc_run.restype = C.c_int
         L.orc_rdf_counts.argtypes = [P, T, vp, C.c_double, i32, vp]
+        L.orc_pme.argtypes = [P, T, vp, vp, vp]
+        L.orc_ewald_recip.argtypes = [P, T, vp, i32, vp]
+        L.orc_ewald_recip.restype = C.c_double
         L.orc_direct_energy.argtypes = [P, T, vp, vp, vp, vp, vp]
         L.orc_direct_energy.restype = C.c_double
         _lib = L
@@ -123,7 +127,8 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
                 temperature=300.0, r_on=5.0, r_off=6.0, r_cut=9.0, skin=2.0, ewald_alpha=0.35,
                 rebuild_interval=10, seed=0, replica=0, bound_scale=1.0, max_proposals=100000,
                 charge=None, eps=None, sigma=None, periodic=None, box=None, cell_size=None,
-                grid_origin=None, grid_dims=None, rate_mode=RATE_ATOM):
+                grid_origin=None, grid_dims=None, rate_mode=RATE_ATOM, pme_grid=None, pme_order=5,
+                respa_m=0):
     """Parameters for the oracle; geometry defaults are taken from a WaterSystem."""
     p = Params()
     p.integrator = integrator
@@ -139,6 +144,9 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
     p.rebuild_interval, p.max_proposals = rebuild_interval, max_proposals
     p.seed, p.replica = seed, replica
     p.rate_mode = rate_mode
+    for k in range(3):
+        p.pme_grid[k] = int(pme_grid[k]) if pme_grid is not None else 0
+    p.pme_order, p.respa_m = int(pme_order), int(respa_m)
     if sys is not None:
         from workloads import tip3p_params
         ff = tip3p_params()
@@ -346,6 +354,23 @@ def rdf_counts(p, topo, q, r_max, nbins):
     lib().orc_rdf_counts(C.byref(p), C.byref(topo.c), _ptr(q), float(r_max), int(nbins),
                          _ptr(counts))
     return counts.reshape(nt, nt, nbins)
+
+
+def pme(p, topo, q, grad=True):
+    """Smooth-PME reciprocal part: ((E_rec, E_self, E_excl), gradient of E_rec + E_excl)."""
+    q = np.ascontiguousarray(q, np.float64)
+    g = np.zeros_like(q) if grad else None
+    e = np.zeros(3)
+    lib().orc_pme(C.byref(p), C.byref(topo.c), _ptr(q), _ptr(g), _ptr(e))
+    return tuple(e.tolist()), g
+
+
+def ewald_recip(p, topo, q, kmax, grad=True):
+    """Plain reciprocal Ewald sum over |k_a| <= kmax: (E_rec, gradient)."""
+    q = np.ascontiguousarray(q, np.float64)
+    g = np.zeros_like(q) if grad else None
+    E = lib().orc_ewald_recip(C.byref(p), C.byref(topo.c), _ptr(q), int(kmax), _ptr(g))
+    return E, g
 
 
 def direct_energy(p, topo, q, grads=True):
