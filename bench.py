@@ -88,14 +88,14 @@ def pair_count(pos, box, r, n_excl_within):
 RATE_MODES = {"atom": 0, "pair": 1}
 
 
-def run_gpu(args, system, ff, integrator, state, rate_mode=0):
+def run_gpu(args, system, ff, integrator, state, rate_mode=0, **mesh):
     import torch
     import paper_2002_07109_amd as B
     p = B.make_params(integrator=integrator, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
                       periodic=1, dt=1.0, gamma=1e-3, temperature=300.0, r_on=args.r_on,
                       r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
                       rebuild_interval=args.rebuild, seed=0, cell_size=system.cell_size,
-                      use_graph=0 if args.no_graph else 1, rate_mode=rate_mode)
+                      use_graph=0 if args.no_graph else 1, rate_mode=rate_mode, **mesh)
     sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
     sim.set_state(pos=state[0], vel=state[1], step=0)
     sim.step(args.warmup)
@@ -117,6 +117,7 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0):
     c1 = sim.counters()
     pair_ms = sim.profile_kernel(0, 50)
     build_ms = sim.profile_kernel(1, 10)
+    mesh_ms = sim.profile_kernel(4, 20) if mesh.get("pme_grid") else None
     e = sim.energies()[0]
     step_ms = sim.profile_kernel(3, 50)        # advances the state: taken last
     out = dict(wall_s=wall, gpu_ms=gpu_ms, ms_per_step=1e3 * wall / args.steps,
@@ -124,7 +125,7 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0):
                accepted_per_step=(c1["accepted"] - c0["accepted"]) / args.steps,
                pair_kernel_ms=pair_ms, build_ms=build_ms, step_kernel_ms=step_ms, t_kin=e["tkin"],
                lanes=lanes, tune_ms={k: round(v, 5) for k, v in tune.items()},
-               e_pot=e["pair"] + e["bond"] + e["angle"],
+               e_pot=e["pair"] + e["bond"] + e["angle"], mesh_ms=mesh_ms,
                pos=sim.pos.cpu().numpy())
     sim.close()
     return out
@@ -291,6 +292,40 @@ def run_big(args, ff):
     return out
 
 
+def run_mesh(args, ff):
+    """The 98,304-atom box with the reciprocal Ewald part by smooth PME (64^3
+    mesh, order-5 B-splines, alpha = 0.35/A, real-space cutoff 9 A): BAOAB 1 fs
+    with the mesh force every step, BOUNCE with it in F_0 every step, and
+    BOUNCE-RESPA with it on an outer step of m = 2 and 4 inner steps."""
+    from workloads import water_box
+    system = water_box(n_side=32, box_len=98.3, seed=3)
+    sub_args = argparse.Namespace(**vars(args))
+    sub_args.equil = 600
+    sub_args.steps = args.mesh_steps
+    sub_args.warmup = 50
+    sub_args.alpha = 0.35
+    state = equilibrate(sub_args, system, ff)
+    import paper_2002_07109_amd as B
+    grid = (64, 64, 64)
+    out = {"workload": "periodic 98,304-atom flexible water box (98.3 A cube), real-space erfc "
+                       "Coulomb + LJ (9 A cutoff) plus smooth-PME reciprocal sum (64^3 mesh, "
+                       "order 5, alpha 0.35/A)", "steps": args.mesh_steps}
+    runs = (("baoab", B.BAOAB, 0), ("bounce", B.BJAOAJB, 0), ("bounce_respa2", B.BJAOAJB, 2),
+            ("bounce_respa4", B.BJAOAJB, 4))
+    for name, integ, m in runs:
+        r = run_gpu(sub_args, system, ff, integ, state, pme_grid=grid, pme_order=5, respa_m=m)
+        out[name] = {"ms_per_step": round(r["ms_per_step"], 5),
+                     "ns_per_day": round(1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
+                     "respa_m": m, "mesh_us": round(r["mesh_ms"] * 1e3, 3),
+                     "pair_kernel_us": round(r["pair_kernel_ms"] * 1e3, 3),
+                     "t_kin": round(r["t_kin"], 2)}
+        log(f"98k box with mesh, {name}: {out[name]}")
+    for name, *_ in runs[1:]:
+        out[name]["speedup_vs_baoab"] = round(out["baoab"]["ms_per_step"] /
+                                              out[name]["ms_per_step"], 4)
+    return out
+
+
 def cpu_baseline(args, system):
     """The FP64 oracle on a bounded sample of the same workload (its seeded
     input state), on all host cores."""
@@ -335,6 +370,9 @@ def main():
     ap.add_argument("--big", action="store_true",
                     help="also time a 98,304-atom box with the same model")
     ap.add_argument("--big-steps", type=int, default=500)
+    ap.add_argument("--mesh", action="store_true",
+                    help="also time the 98,304-atom box with smooth PME (BAOAB, BOUNCE, BOUNCE-RESPA)")
+    ap.add_argument("--mesh-steps", type=int, default=500)
     ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
                     help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
                          "BAOAB at 0.25 fs over PS picoseconds each")
@@ -441,6 +479,9 @@ def main():
     if args.big:
         log("timing the 98,304-atom box")
         line["big_box"] = run_big(args, ff)
+    if args.mesh:
+        log("timing the 98,304-atom box with the PME mesh")
+        line["mesh_box"] = run_mesh(args, ff)
     if args.accuracy > 0:
         line["accuracy"] = run_accuracy(args, system, ff, state)
     if not args.skip_cpu:

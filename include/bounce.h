@@ -60,7 +60,8 @@ enum { BOUNCE_PAIR_FP32 = 0, BOUNCE_PAIR_FP64 = 1 };    /* pair arithmetic     *
 enum { BOUNCE_COUL_BARE = 0, BOUNCE_COUL_EWALD = 1 };   /* 1/r or erfc(a r)/r  */
 enum { BOUNCE_PH_JA = 0, BOUNCE_PH_O = 1, BOUNCE_PH_JB = 2 };  /* random-stream phases */
 /* gradient parts for bounce_compute_gradient (bit mask) */
-enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8 };
+enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8,
+       BOUNCE_G_RECIP = 16 };   /* RECIP: smooth-PME mesh + excluded-pair correction */
 /* lists for bounce_get_list */
 enum { BOUNCE_LIST_FORCE = 0, BOUNCE_LIST_CAND = 1 };
 /* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may
@@ -97,6 +98,13 @@ typedef struct {
     int64_t event_capacity;    /* events kept when log_events = 1                          */
     int32_t pair_lanes;        /* lanes per atom in the pair kernel: 4, 8, 16, 32 (0 = 8)  */
     int32_t rate_mode;         /* BOUNCE_RATE_ATOM or BOUNCE_RATE_PAIR (fixed at create)   */
+    /* Reciprocal-space Ewald by smooth PME (Sec. V), one periodic box only:      */
+    int32_t pme_grid[3];       /* mesh points per edge, powers of two in [8, 512]; 0 = off */
+    int32_t pme_order;         /* B-spline order: 4, 5 or 6                              */
+    int32_t respa_m;           /* 0: mesh force in F_0 every step (basic BOUNCE);        */
+                               /* m >= 1: RESPA outer step of m dt, half kicks with the  */
+                               /* mesh force at every m-th step (rebuild_interval % m == 0) */
+    int32_t pme_reserved;
 } bounce_params;
 
 typedef struct {
@@ -186,6 +194,12 @@ bounce_status bounce_rate_weights(const bounce_ctx *ctx, uint32_t *Lq_host, doub
    the current candidate lists, random stream (step, phase).  Synchronous. */
 bounce_status bounce_jump_halfstep(bounce_ctx *ctx, int64_t step, int32_t phase);
 
+/* Reciprocal-space Ewald parts at the current positions (needs pme_grid):
+   e3_host = {E_rec (mesh), E_self = -k_e alpha/sqrt(pi) sum q^2, E_excl = -k_e
+   sum over excluded pairs q_i q_j erf(alpha r)/r}.  bounce_compute_energies
+   adds all three to E_coul.  Synchronous. */
+bounce_status bounce_pme_energy(bounce_ctx *ctx, double *e3_host);
+
 /* Pair-structure diagnostic (the radial distribution functions that Sec. VI
    compares between integrators) at the current positions: ordered
    non-excluded pairs (i != j) of every replica with r < r_max, counted per
@@ -225,7 +239,10 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
      which = 1: the list build, reps times at the current positions (positions
                 and velocities stay; the following steps use these lists);
      which = 3: the integrator kernel of reps real steps (advances the
-                trajectory by reps + 1 steps; only that kernel is timed). */
+                trajectory by reps + 1 steps; only that kernel is timed);
+     which = 4: the reciprocal-space mesh sum (spread, FFT, convolution, FFT
+                back, gather) at the current positions, reps times; needs
+                pme_grid; the trajectory is unchanged. */
 bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);
 
 /* Autotuner: time the F_0 pair kernel (reps launches each) with 4, 8, 16 and 32

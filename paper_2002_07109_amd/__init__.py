@@ -13,14 +13,15 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_SHORT,
+from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_RECIP,
+                   G_SHORT,
                    LIST_CAND, LIST_FORCE, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, RATE_ATOM,
                    RATE_PAIR, BounceError,
                    bounce_counters, bounce_event, bounce_params, bounce_system, check)
 
 __all__ = ["lib", "Simulation", "DirectEnergy", "make_params", "BounceError", "BJAOAJB", "BAOAB",
            "PAIR_FP32", "PAIR_FP64", "COUL_BARE", "COUL_EWALD", "PH_JA", "PH_O", "PH_JB",
-           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
+           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "G_RECIP", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
            "RATE_PAIR"]
 
 
@@ -32,16 +33,21 @@ def lib():
 def make_params(**kw) -> bounce_params:
     """bounce_params with defaults: BOUNCE, FP32 pair math, dt = 1 fs, gamma = 1/ps,
     300 K, r'/r'' = 6/7, rc = 9, skin 2, alpha 0.35, K = 10, one rate bound per
-    atom type (RATE_ATOM)."""
+    atom type (RATE_ATOM), no reciprocal-space mesh (pme_grid = (0, 0, 0); when
+    set: B-spline order 5, mesh force in F_0 unless respa_m >= 1)."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
-             pair_lanes=0, rate_mode=RATE_ATOM)
+             pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():
-        setattr(p, k, v)
+        if k == "pme_grid":
+            for c in range(3):
+                p.pme_grid[c] = int(v[c])
+        else:
+            setattr(p, k, v)
     return p
 
 
@@ -243,6 +249,13 @@ class Simulation:
         check(self.L.bounce_msd(self.ctx, _tptr(ref), _ptr(out)), self.ctx, "bounce_msd")
         return out.reshape(-1, self.n_types)
 
+    def pme_energy(self):
+        """Mesh Ewald parts at the current positions: (E_recip, E_self, E_excl) in
+        kcal/mol, the last the excluded pairs' erf(alpha r)/r correction."""
+        out = np.zeros(3)
+        check(self.L.bounce_pme_energy(self.ctx, _ptr(out)), self.ctx, "bounce_pme_energy")
+        return out
+
     def jump_halfstep(self, step, phase):
         check(self.L.bounce_jump_halfstep(self.ctx, int(step), int(phase)), self.ctx,
               "bounce_jump_halfstep")
@@ -252,7 +265,8 @@ class Simulation:
         0 the F_0 pair kernel, 2 the integrator kernel with kicks, jumps and
         drifts off (both leave the trajectory unchanged), 1 the list build at
         the current positions (later steps use these lists), 3 the integrator
-        kernel of `reps` real steps (advances the trajectory by reps + 1 steps)."""
+        kernel of `reps` real steps (advances the trajectory by reps + 1 steps),
+        4 the reciprocal-space mesh sum (needs pme_grid; trajectory unchanged)."""
         ms = C.c_double()
         check(self.L.bounce_profile_kernel(self.ctx, int(which), int(reps), C.byref(ms)), self.ctx,
               "bounce_profile_kernel")

@@ -18,7 +18,7 @@ BJAOAJB, BAOAB = 0, 1
 PAIR_FP32, PAIR_FP64 = 0, 1
 COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
-G_BONDED, G_SHORT, G_LONG, G_FULL = 1, 2, 4, 8
+G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
 LIST_FORCE, LIST_CAND = 0, 1
 RATE_ATOM, RATE_PAIR = 0, 1
 
@@ -31,7 +31,9 @@ class bounce_params(C.Structure):
                 ("r_on", C.c_double), ("r_off", C.c_double), ("r_cut", C.c_double),
                 ("skin", C.c_double), ("ewald_alpha", C.c_double), ("bound_scale", C.c_double),
                 ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64),
-                ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32)]
+                ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32),
+                ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32), ("respa_m", C.c_int32),
+                ("pme_reserved", C.c_int32)]
 
 
 class bounce_system(C.Structure):
@@ -80,6 +82,7 @@ SIGNATURES = {
     "bounce_rate_weights": (i32, [ctx_p, vp, vp]),
     "bounce_rdf_counts": (i32, [ctx_p, C.c_double, i32, vp]),
     "bounce_msd": (i32, [ctx_p, vp, vp]),
+    "bounce_pme_energy": (i32, [ctx_p, vp]),
     "bounce_jump_halfstep": (i32, [ctx_p, i64, i32]),
     "bounce_direct_energy": (i32, [ctx_p, vp, vp, vp]),
     "bounce_direct_energy_bwd": (i32, [ctx_p, vp, vp, vp, vp, vp]),

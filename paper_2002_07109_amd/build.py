@@ -21,6 +21,7 @@ SOURCES = {
     "kernels_list.hip": ["-ffp-contract=off"],
     "kernels_pair.hip": [],
     "kernels_step.hip": [],
+    "kernels_pme.hip": [],
     "bounce_api.cpp": [],
 }
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -111,6 +111,13 @@ struct bounce_ctx {
     int32_t *d_cell_rep = nullptr;
     uint32_t *d_Lq = nullptr;
     unsigned long long *d_rdf = nullptr;
+    // smooth PME: mesh, influence function theta(k) (host-computed), RESPA gradient
+    bool pme = false;
+    int64_t pme_points = 0;
+    double pme_qscale = 1.0;
+    std::vector<double> theta;
+    double2 *d_grid = nullptr;
+    double *d_theta = nullptr, *d_grec = nullptr, *d_pme_e = nullptr, *d_charge = nullptr;
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
     // schedule
@@ -169,6 +176,14 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->rebuild_interval < 1 || p->max_proposals < 1) return BOUNCE_E_ARG;
     if (!(p->bound_scale > 0)) return BOUNCE_E_ARG;
     if (p->rate_mode != BOUNCE_RATE_ATOM && p->rate_mode != BOUNCE_RATE_PAIR) return BOUNCE_E_ARG;
+    if (p->pme_grid[0] || p->pme_grid[1] || p->pme_grid[2]) {
+        for (int k = 0; k < 3; ++k) {
+            const int32_t g = p->pme_grid[k];
+            if (g < 8 || g > 512 || (g & (g - 1))) return BOUNCE_E_ARG;
+        }
+        if (p->pme_order < 4 || p->pme_order > 6 || !p->periodic || p->respa_m < 0) return BOUNCE_E_ARG;
+        if (p->respa_m > 0 && p->rebuild_interval % p->respa_m) return BOUNCE_E_ARG;
+    }
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
@@ -185,6 +200,66 @@ void bounce_destroy(bounce_ctx *c)
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
+}
+
+// cardinal B-spline values M_n(1), ..., M_n(n-1) by the order recursion on the
+// integer points, for the Euler-spline factors |b(k)|^2 of smooth PME
+static std::vector<double> spline_at_integers(int n)
+{
+    std::vector<double> m(n + 1, 0.0);      // m[j] = M_k(j), k = 2 at start
+    m[1] = 1.0;
+    for (int k = 3; k <= n; ++k) {
+        std::vector<double> nx(n + 1, 0.0);
+        for (int j = 1; j < k; ++j)
+            nx[j] = ((double)j * m[j] + (double)(k - j) * m[j - 1]) / (double)(k - 1);
+        m = nx;
+    }
+    return m;
+}
+
+// theta(k) = k_e / (pi V) exp(-pi^2 m^2 / alpha^2) / m^2 |b_0|^2 |b_1|^2 |b_2|^2,
+// theta(0) = 0; |b(k)|^2 = 1 / |sum_{j=0}^{n-2} M_n(j+1) exp(2 pi i k j / K)|^2, and
+// where that sum vanishes (odd n, k = K/2) the mean of the neighbouring values
+static void make_theta(bounce_ctx *c)
+{
+    const RepInfo &ri = c->reps[0];
+    const int n = c->p.pme_order;
+    const std::vector<double> M = spline_at_integers(n);
+    std::vector<double> bsq[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const int K = c->p.pme_grid[ax];
+        bsq[ax].assign(K, 0.0);
+        for (int k = 0; k < K; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j <= n - 2; ++j) {
+                const double ph = 2.0 * M_PI * (double)((int64_t)k * j % K) / (double)K;
+                re += M[j + 1] * std::cos(ph);
+                im += M[j + 1] * std::sin(ph);
+            }
+            const double d = re * re + im * im;
+            bsq[ax][k] = d > 1e-30 ? 1.0 / d : -1.0;
+        }
+        for (int k = 0; k < K; ++k)
+            if (bsq[ax][k] < 0.0) bsq[ax][k] = 0.5 * (bsq[ax][(k + K - 1) % K] + bsq[ax][(k + 1) % K]);
+    }
+    const int K0 = c->p.pme_grid[0], K1 = c->p.pme_grid[1], K2 = c->p.pme_grid[2];
+    const double V = ri.box[0] * ri.box[1] * ri.box[2], a = c->p.ewald_alpha;
+    c->pme_points = (int64_t)K0 * K1 * K2;
+    c->theta.assign(c->pme_points, 0.0);
+    for (int k0 = 0; k0 < K0; ++k0)
+        for (int k1 = 0; k1 < K1; ++k1)
+            for (int k2 = 0; k2 < K2; ++k2) {
+                if (!k0 && !k1 && !k2) continue;
+                const int kk[3] = {k0, k1, k2}, KK[3] = {K0, K1, K2};
+                double m2 = 0.0;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const double mc = (double)(kk[ax] <= KK[ax] / 2 ? kk[ax] : kk[ax] - KK[ax]) / ri.box[ax];
+                    m2 += mc * mc;
+                }
+                c->theta[((int64_t)k0 * K1 + k1) * K2 + k2] =
+                    KE / (M_PI * V) * std::exp(-M_PI * M_PI * m2 / (a * a)) / m2 * bsq[0][k0] * bsq[1][k1] *
+                    bsq[2][k2];
+            }
 }
 
 static void make_ou(bounce_ctx *c)
@@ -392,6 +467,20 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     }
     make_ou(c);
     make_bounds(c);
+    c->pme = c->p.pme_grid[0] > 0;
+    c->pme_points = 0;
+    if (c->pme) {
+        if (R != 1 || !c->reps[0].periodic)
+            return fail(c, BOUNCE_E_ARG, "the PME mesh needs one periodic replica");
+        make_theta(c);
+        // fixed point of the spread: 2^k with sum_i |q_i| 2^k <= 2^61 (a grid
+        // point's sum is at most sum_i |q_i|: the spline weights lie in [0, 1])
+        double qabs = 0.0;
+        for (int32_t g = 0; g < n; ++g) qabs += std::fabs(c->tparams[c->type[g]]);
+        int e2 = 0;
+        std::frexp(std::max(qabs, 1e-300), &e2);     // qabs < 2^e2
+        c->pme_qscale = std::ldexp(1.0, std::min(61 - e2, 60));
+    }
     c->have_system = true;
     c->bound = false;
     return BOUNCE_OK;
@@ -414,7 +503,7 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
-        seg, xcnt, xcol, cell_rep, rdf;
+        seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e;
     size_t ls[2][15];
 };
 
@@ -454,6 +543,10 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.atom = L.take(8 * n * std::max(5, 3 * MAXT));
     o.seg = L.take(8 * 8 * R);
     o.rdf = L.take(8 * (size_t)RDF_MAX_BINS);
+    o.grid = L.take(16 * (size_t)std::max<int64_t>(1, c->pme_points));
+    o.theta = L.take(8 * (size_t)std::max<int64_t>(1, c->pme_points));
+    o.grec = L.take(24 * n);
+    o.pme_e = L.take(8 * (size_t)(c->pme_points / 256 + 2));
     o.xcnt = L.take(4 * n);
     o.xcol = L.take(4 * n * (size_t)c->xcap);
     for (int k = 0; k < 2; ++k) {
@@ -569,6 +662,13 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     c->d_atom = at<double>(ws, o.atom);
     c->d_seg = at<double>(ws, o.seg);
     c->d_rdf = at<unsigned long long>(ws, o.rdf);
+    c->d_grid = at<double2>(ws, o.grid);
+    c->d_theta = at<double>(ws, o.theta);
+    c->d_grec = at<double>(ws, o.grec);
+    c->d_pme_e = at<double>(ws, o.pme_e);
+    c->d_charge = at<double>(ws, o.tparams);     // per-type charges: the first n_types parameters
+    if (c->pme) HIPCHK(c, up(sm, ws, o.theta, c->theta));
+    HIPCHK(c, hipMemsetAsync(c->d_grec, 0, 24 * (size_t)c->n, sm));
     c->d_ou_c2 = at<double>(ws, o.ou_c2);
     c->d_xcnt = at<int32_t>(ws, o.xcnt);
     c->d_xcol = at<int32_t>(ws, o.xcol);
@@ -736,6 +836,39 @@ static void enqueue_force(bounce_ctx *c, int32_t step_off)
                 c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
 }
 
+static PmeArgs pme_args(const bounce_ctx *c, int32_t step_off, int32_t mirror_sel)
+{
+    PmeArgs pa{};
+    const RepInfo &ri = c->reps[0];
+    for (int k = 0; k < 3; ++k) {
+        pa.K[k] = c->p.pme_grid[k];
+        pa.box[k] = ri.box[k];
+        pa.inv_box[k] = ri.inv_box[k];
+    }
+    pa.order = c->p.pme_order;
+    pa.alpha = c->p.ewald_alpha;
+    pa.st = c->d_st;
+    pa.step_off = step_off;
+    pa.mirror_sel = mirror_sel;
+    pa.qscale = c->pme_qscale;
+    pa.inv_qscale = 1.0 / c->pme_qscale;
+    return pa;
+}
+
+// the mesh force at step n (device offset step_off): into F_0's pair part
+// every step (respa_m = 0), or into the RESPA gradient at every m-th step
+static bool pme_at(const bounce_ctx *c, int64_t n)
+{
+    return c->pme && (c->p.respa_m == 0 || n % c->p.respa_m == 0);
+}
+
+static void enqueue_pme(bounce_ctx *c, int32_t step_off)
+{
+    const bool in_f0 = c->p.respa_m == 0;
+    launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1), c->d_grid,
+               c->d_theta, in_f0 ? c->d_fpair : c->d_grec, 0, in_f0 ? 1 : 0, nullptr);
+}
+
 static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
 {
     StepArgs a{};
@@ -751,6 +884,8 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     a.reps = c->d_reps;
     a.tp = c->tp;
     a.ls = c->main;
+    a.grec = c->d_grec;
+    a.rec_close = a.rec_open = 0.0;
     a.st = c->d_st;
     a.cnt = c->d_cnt;
     a.wave_cnt = c->d_wave_cnt;
@@ -785,8 +920,16 @@ static void enqueue_substep(bounce_ctx *c, int close, int open, hipEvent_t e0 = 
         c->host_rebuilds++;
     }
     enqueue_force(c, c->pending);
+    if (pme_at(c, c->step)) enqueue_pme(c, c->pending);
+    StepArgs a = step_args(c, close, open, c->pending);
+    if (c->pme && c->p.respa_m > 0 && c->step % c->p.respa_m == 0) {
+        // step n = c->step ends one RESPA block (close) and starts the next (open)
+        const double H = 0.5 * c->p.dt * (double)c->p.respa_m;
+        a.rec_close = close ? H : 0.0;
+        a.rec_open = open ? H : 0.0;
+    }
     if (e0) (void)hipEventRecord(e0, c->stream);
-    launch_step(c->stream, step_args(c, close, open, c->pending));
+    launch_step(c->stream, a);
     if (e1) (void)hipEventRecord(e1, c->stream);
     if (open) {
         c->step++;
@@ -818,7 +961,13 @@ static bounce_status make_graph(bounce_ctx *c)
     for (int k = 0; k < c->p.rebuild_interval; ++k) {
         if (k == 0) enqueue_build(c, 0);
         enqueue_force(c, k);
-        launch_step(c->stream, step_args(c, 1, 1, k));
+        // the graph starts at a multiple of K, and K is a multiple of respa_m
+        StepArgs a = step_args(c, 1, 1, k);
+        if (pme_at(c, k)) {
+            enqueue_pme(c, k);
+            if (c->p.respa_m > 0) a.rec_close = a.rec_open = 0.5 * c->p.dt * (double)c->p.respa_m;
+        }
+        launch_step(c->stream, a);
     }
     launch_advance(c->stream, c->d_st, c->p.rebuild_interval);
     e = hipStreamEndCapture(cap, &c->graph);
@@ -901,7 +1050,8 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
 {
     bounce_status s = ready(c);
     if (s) return s;
-    if (!grad || (which & ~15) || !which) return BOUNCE_E_ARG;
+    if (!grad || (which & ~31) || !which) return BOUNCE_E_ARG;
+    if ((which & BOUNCE_G_RECIP) && !c->pme) return fail(c, BOUNCE_E_ARG, "G_RECIP needs pme_grid");
     hipStream_t sm = c->stream;
     const int pairs[3] = {BOUNCE_G_SHORT, BOUNCE_G_LONG, BOUNCE_G_FULL};
     const int modes[3] = {MODE_SHORT, MODE_LONG, MODE_FULL};
@@ -915,6 +1065,13 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
         a.out_global = 1;
         a.accumulate = !first;
         launch_pair(sm, modes[k], c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
+        first = 0;
+    }
+    if (which & BOUNCE_G_RECIP) {
+        if (!(which & (BOUNCE_G_SHORT | BOUNCE_G_LONG | BOUNCE_G_FULL)))
+            launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+        launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pme_args(c, 0, 0), c->d_grid, c->d_theta,
+                   grad, 1, first ? 0 : 1, nullptr);
         first = 0;
     }
     if (which & BOUNCE_G_BONDED) {
@@ -943,11 +1100,17 @@ bounce_status bounce_compute_energies(bounce_ctx *c, double *out)
     HIPCHK(c, hipMemcpyAsync(seg.data(), c->d_seg, 8 * seg.size(), hipMemcpyDeviceToHost, sm));
     s = bounce_sync(c);
     if (s) return s;
+    double emesh[3] = {0.0, 0.0, 0.0};
+    if (c->pme) {
+        s = bounce_pme_energy(c, emesh);
+        if (s) return s;
+    }
     for (int32_t r = 0; r < c->R; ++r) {
         const double *v = &seg[5 * r];
         double *o = out + 7 * r;
         int64_t na = c->rep_off[r + 1] - c->rep_off[r];
-        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; o[4] = v[2] + v[3]; o[5] = v[4];
+        const double ec = v[2] + (emesh[0] + emesh[1] + emesh[2]);   // one replica when meshed
+        o[0] = v[0]; o[1] = v[1]; o[2] = ec; o[3] = v[3]; o[4] = ec + v[3]; o[5] = v[4];
         o[6] = 2.0 * v[4] / (3.0 * (double)na * KB);
     }
     return BOUNCE_OK;
@@ -1028,6 +1191,35 @@ bounce_status bounce_rate_bounds(const bounce_ctx *c, double *L_ab, double *L_a)
     if (!c->have_system) return BOUNCE_E_STATE;
     std::memcpy(L_ab, c->L_ab.data(), 8 * c->L_ab.size());
     std::memcpy(L_a, c->L_a.data(), 8 * c->L_a.size());
+    return BOUNCE_OK;
+}
+
+bounce_status bounce_pme_energy(bounce_ctx *c, double *e3)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (!e3) return BOUNCE_E_ARG;
+    if (!c->pme) return fail(c, BOUNCE_E_ARG, "no PME mesh (pme_grid)");
+    hipStream_t sm = c->stream;
+    launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
+    const PmeArgs pa = pme_args(c, 0, 0);
+    launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pa, c->d_grid, c->d_theta, nullptr, 0, 0,
+               c->d_pme_e);
+    launch_pme_excl_energy(sm, c->n, c->pos, c->d_charge, c->tp, pa, c->d_atom);
+    launch_segment_sum(sm, 1, c->d_one_seg, c->d_atom, 1, 1, 0, c->d_seg);
+    const int64_t nb = (c->pme_points + 255) / 256;
+    std::vector<double> part(nb), ex(1);
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->d_pme_e, 8 * nb, hipMemcpyDeviceToHost, sm));
+    HIPCHK(c, hipMemcpyAsync(ex.data(), c->d_seg, 8, hipMemcpyDeviceToHost, sm));
+    s = bounce_sync(c);
+    if (s) return s;
+    double er = 0.0;
+    for (int64_t b = 0; b < nb; ++b) er += part[b];
+    double q2 = 0.0;
+    for (int32_t g = 0; g < c->n; ++g) q2 += c->tparams[c->type[g]] * c->tparams[c->type[g]];
+    e3[0] = er;
+    e3[1] = -KE * c->p.ewald_alpha / std::sqrt(M_PI) * q2;
+    e3[2] = ex[0];
     return BOUNCE_OK;
 }
 
@@ -1148,7 +1340,8 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
 {
     bounce_status s = ready(c);
     if (s) return s;
-    if (!avg_ms || reps < 1 || which < 0 || which > 3) return BOUNCE_E_ARG;
+    if (!avg_ms || reps < 1 || which < 0 || which > 4) return BOUNCE_E_ARG;
+    if (which == 4 && !c->pme) return fail(c, BOUNCE_E_ARG, "no PME mesh (pme_grid)");
     if (c->built_step < 0) {
         enqueue_build(c, 0);
         c->built_step = c->step;
@@ -1181,6 +1374,9 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     for (int32_t k = 0; k < reps; ++k) {
         if (which == 0) enqueue_force(c, 0);
         else if (which == 1) enqueue_build(c, 0);
+        else if (which == 4)     // into the RESPA buffer, which every outer kick recomputes first
+            launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, 0, -1), c->d_grid,
+                       c->d_theta, c->d_grec, 0, 0, nullptr);
         else launch_step(c->stream, step_args(c, 0, 0, 0));   // no kicks, jumps or drifts
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));

@@ -17,6 +17,8 @@ constexpr int WEIGHT_BITS = 20;
 constexpr double WEIGHT_SLACK = 1e-4;
 // pair-structure histogram: at most this many (type pair, bin) counters
 constexpr int RDF_MAX_BINS = 8192;
+// smooth-PME B-spline order limit
+constexpr int PME_MAX_ORDER = 8;
 
 // latched device conditions
 enum : uint32_t {

@@ -60,6 +60,20 @@ struct StepArgs {
     PairGlobals pg;
     double dt, half_dt, c1, beta;
     double skin_half2;            // (s/2)^2
+    const double *grec;           // [N][3] sorted: reciprocal-space gradient for RESPA kicks
+    double rec_close, rec_open;   // kick lengths (fs) with grec after the closing B / before the opening B
+};
+
+// one periodic box's smooth-PME mesh
+struct PmeArgs {
+    int32_t K[3];                 // grid points per edge (powers of two)
+    int32_t order;                // B-spline order n
+    double box[3], inv_box[3];
+    double alpha;                 // Ewald splitting (1/A)
+    const DevState *st;           // mirror parity: device step counter + step_off
+    int32_t step_off;
+    int32_t mirror_sel;           // -1: parity of the step, 0/1: fixed mirror
+    double qscale, inv_qscale;    // fixed-point scale of the spread charges (2^k)
 };
 
 struct JumpArgs {
@@ -87,6 +101,11 @@ void launch_rdf(hipStream_t sm, int32_t n, const RepInfo *reps, int32_t single_r
                 unsigned long long *counts);
 void launch_msd_atom(hipStream_t sm, int32_t n, const double *pos, const double *ref,
                      const int32_t *type, double *vals);
+void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos, const double *charge,
+                const Topo &tp, const PmeArgs &pa, double2 *grid, const double *theta, double *out,
+                int32_t out_global, int32_t accumulate, double *energy_parts);
+void launch_pme_excl_energy(hipStream_t sm, int32_t n, const double *pos, const double *charge,
+                            const Topo &tp, const PmeArgs &pa, double *atom_out);
 void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
                            int32_t *cnt_global, int32_t *col_global, int32_t cap);
 void launch_dbwd_finish(hipStream_t sm, int32_t n, int32_t n_types, const double *atom_basis,

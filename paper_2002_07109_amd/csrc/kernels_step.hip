@@ -368,6 +368,14 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
 constexpr int LPA = 4;
 constexpr int JB_L1 = 3, JB_L2 = 1, JA_L1 = 2, JA_L2 = 0;
 
+// RESPA outer half kick (Sec. V): v -= H * grad_rec / m at the boundary of an
+// outer step, read where used (one step in respa_m is a boundary)
+__device__ __forceinline__ void outer_kick(const StepArgs &a, int32_t s, int32_t g, double H, double *v)
+{
+    const double k = a.tp.acc_m[g];
+    for (int c = 0; c < 3; ++c) v[c] = v[c] - H * (a.grec[3 * (int64_t)s + c] * k);
+}
+
 template <typename R, bool BOUNCE, int KC = 1>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
@@ -506,8 +514,10 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
                                       M_jb, JB_L1, JB_L2, pp, sub, tally);
         }
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
+        if (a.rec_close != 0.0 && active) outer_kick(a, s, g, a.rec_close, v);
     }
     if (a.do_open) {
+        if (a.rec_open != 0.0 && active) outer_kick(a, s, g, a.rec_open, v);
         v[0] = v[0] - km * F[0]; v[1] = v[1] - km * F[1]; v[2] = v[2] - km * F[2];
         if (BOUNCE) {
             const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);

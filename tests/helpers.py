@@ -26,7 +26,9 @@ def oracle_params(orc, sys, cfg, replica=0):
                            skin=cfg["skin"], ewald_alpha=cfg["ewald_alpha"],
                            rebuild_interval=cfg["rebuild_interval"], seed=cfg["seed"],
                            replica=replica, bound_scale=cfg["bound_scale"],
-                           periodic=bool(cfg["periodic"]), rate_mode=cfg.get("rate_mode", 0))
+                           periodic=bool(cfg["periodic"]), rate_mode=cfg.get("rate_mode", 0),
+                           pme_grid=cfg.get("pme_grid"), pme_order=cfg.get("pme_order", 5),
+                           respa_m=cfg.get("respa_m", 0))
 
 
 def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_graph=False):
@@ -40,7 +42,9 @@ def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_gr
                       bound_scale=cfg["bound_scale"], cell_size=cell,
                       pair_precision=B.PAIR_FP64 if fp64 else B.PAIR_FP32,
                       log_events=int(log_events), event_capacity=event_capacity,
-                      use_graph=int(use_graph), rate_mode=cfg.get("rate_mode", 0))
+                      use_graph=int(use_graph), rate_mode=cfg.get("rate_mode", 0),
+                      pme_grid=cfg.get("pme_grid") or (0, 0, 0), pme_order=cfg.get("pme_order", 5),
+                      respa_m=cfg.get("respa_m", 0))
     return B.Simulation(systems, p, FF["charge"], FF["eps"], FF["sigma"])
 
 

@@ -70,6 +70,18 @@ def test_argument_errors_need_no_gpu():
     assert L.bounce_workspace_size(ctx, C.byref(nb)) == _abi.E_STATE
     assert L.bounce_status_string(_abi.E_SKIN).decode().startswith("an atom moved")
     L.bounce_destroy(ctx)
+    # mesh parameters: powers of two in [8, 512], order 4..6, periodic, and a
+    # RESPA outer step that divides the rebuild interval
+    for kw in (dict(pme_grid=(24, 32, 32)), dict(pme_grid=(4, 4, 4)), dict(pme_grid=(1024, 8, 8)),
+               dict(pme_grid=(32, 32, 32), pme_order=3), dict(pme_grid=(32, 32, 32), pme_order=7),
+               dict(pme_grid=(32, 32, 32), periodic=0),
+               dict(pme_grid=(32, 32, 32), respa_m=3, rebuild_interval=10),
+               dict(pme_grid=(32, 32, 32), respa_m=-1)):
+        p = make_params(**kw)
+        assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.E_ARG, kw
+    p = make_params(pme_grid=(16, 32, 64), pme_order=6, respa_m=5, rebuild_interval=10)
+    assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.OK
+    L.bounce_destroy(ctx)
 
 
 def test_missing_library_fails_loudly(tmp_path):

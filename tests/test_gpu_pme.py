@@ -1,0 +1,110 @@
+"""GPU parity of the reciprocal-space Ewald sum by smooth PME and of the RESPA
+outer step (Sec. V) against the oracle's plain-DFT mesh sum: energy parts,
+gradients, energies, trajectories with the mesh force in F_0 (respa_m = 0) or
+as outer half kicks every m steps, and graph replay."""
+import numpy as np
+import pytest
+
+from helpers import BOX, event_keys, gpu_sim, oracle_params, rel_err_total, relaxed_box
+from workloads import jitter_positions
+
+pytestmark = pytest.mark.gpu
+
+MESH = dict(BOX, pme_grid=(32, 32, 32), pme_order=5)
+
+
+@pytest.fixture(scope="module")
+def box():
+    return relaxed_box("b8")
+
+
+@pytest.mark.parametrize("order,grid", [(4, (32, 32, 32)), (5, (32, 32, 32)), (6, (32, 32, 32)),
+                                        (5, (16, 32, 64))])
+def test_mesh_energy_and_gradient(orc, box, order, grid):
+    import paper_2002_07109_amd as B
+    cfg = dict(MESH, pme_order=order, pme_grid=grid)
+    sim = gpu_sim(box, cfg, fp64=True)
+    q = jitter_positions(box.pos, 0.05, seed=11)
+    sim.set_state(pos=q)
+    p = oracle_params(orc, box, cfg)
+    topo = orc.Topology.from_system(box)
+    (er, es, ex), go = orc.pme(p, topo, q)
+    e = sim.pme_energy()
+    assert e[0] == pytest.approx(er, rel=1e-10)
+    assert e[1] == pytest.approx(es, rel=1e-13)
+    assert e[2] == pytest.approx(ex, rel=1e-12)
+    total = orc.gradient(p, topo, q, orc.G_BONDED | orc.G_FULL | orc.G_RECIP)
+    g = sim.gradient(B.G_RECIP).cpu().numpy()
+    assert rel_err_total(g, go, total) < 1e-10
+    # combined with the real-space part, summed into one output
+    g2 = sim.gradient(B.G_FULL | B.G_RECIP).cpu().numpy()
+    o2 = orc.gradient(p, topo, q, orc.G_FULL | orc.G_RECIP)
+    assert rel_err_total(g2, o2, total) < 1e-10
+
+
+def test_energies_include_mesh_terms(orc, box):
+    sim = gpu_sim(box, MESH, fp64=True)
+    e = sim.energies()[0]
+    o = orc.energies(oracle_params(orc, box, MESH), orc.Topology.from_system(box), box.pos, box.vel)
+    for k in ("bond", "angle", "coul", "lj", "pair", "kin"):
+        assert e[k] == pytest.approx(o[k], rel=1e-10, abs=1e-8), k
+    plain = gpu_sim(box, BOX, fp64=True).energies()[0]
+    assert e["coul"] - plain["coul"] == pytest.approx(sum(sim.pme_energy()), rel=1e-12)
+
+
+@pytest.mark.parametrize("integrator", [0, 1])
+@pytest.mark.parametrize("respa_m", [0, 2, 5])
+def test_trajectory_with_mesh(orc, box, respa_m, integrator):
+    cfg = dict(MESH, respa_m=respa_m, integrator=integrator)
+    nsteps = 60
+    sim = gpu_sim(box, cfg, fp64=True, log_events=True, event_capacity=4_000_000)
+    sim.step(nsteps)
+    sim.sync()
+    o = orc.run(oracle_params(orc, box, cfg), orc.Topology.from_system(box), box.pos, box.vel, 0,
+                nsteps, ev_cap=4_000_000)
+    assert o["status"] == 0, o["status_name"]
+    dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
+    dv = np.abs(sim.vel.cpu().numpy() - o["v"]).max()
+    assert dq <= 1e-6 and dv <= 1e-6, (dq, dv)
+    if integrator == 0:
+        ev, n = sim.events()
+        assert n == o["n_events"] and n > 0
+        assert np.array_equal(event_keys(ev), event_keys(o["events"]))
+
+
+def test_outer_kick_matters(orc, box):
+    """The mesh force moves the trajectory: without it (or with the outer
+    kicks at the wrong steps) the run leaves the oracle's."""
+    cfg = dict(MESH, respa_m=2)
+    a = gpu_sim(box, cfg, fp64=True)
+    b = gpu_sim(box, dict(cfg, respa_m=5), fp64=True)
+    c = gpu_sim(box, BOX, fp64=True)
+    for s in (a, b, c):
+        s.step(20)
+        s.sync()
+    qa, qb, qc = (s.pos.cpu().numpy() for s in (a, b, c))
+    assert np.abs(qa - qb).max() > 1e-5 and np.abs(qa - qc).max() > 1e-5
+
+
+@pytest.mark.parametrize("respa_m", [0, 2])
+def test_graph_replay_and_resume_are_bit_exact(box, respa_m):
+    cfg = dict(MESH, respa_m=respa_m)
+    sa = gpu_sim(box, cfg, fp64=False, use_graph=False)
+    sb = gpu_sim(box, cfg, fp64=False, use_graph=True)
+    for sim in (sa, sb):
+        sim.step(35)
+        sim.sync()
+    assert np.array_equal(sa.pos.cpu().numpy(), sb.pos.cpu().numpy())
+    assert np.array_equal(sa.vel.cpu().numpy(), sb.vel.cpu().numpy())
+    # stopping and restarting at any step gives the same bits
+    sc = gpu_sim(box, cfg, fp64=False, use_graph=True)
+    for k in (3, 7, 25):
+        sc.step(k)
+    sc.sync()
+    assert np.array_equal(sc.pos.cpu().numpy(), sb.pos.cpu().numpy())
+
+
+def test_mesh_needs_one_periodic_replica(box):
+    import paper_2002_07109_amd as B
+    with pytest.raises(B.BounceError):
+        gpu_sim([box, box], MESH)
