@@ -118,6 +118,7 @@ struct bounce_ctx {
     std::vector<double> theta;
     double2 *d_grid = nullptr;
     double *d_theta = nullptr, *d_grec = nullptr, *d_pme_e = nullptr, *d_charge = nullptr;
+    PmeAtoms pme_atoms{};
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
     // schedule
@@ -473,13 +474,19 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
         if (R != 1 || !c->reps[0].periodic)
             return fail(c, BOUNCE_E_ARG, "the PME mesh needs one periodic replica");
         make_theta(c);
-        // fixed point of the spread: 2^k with sum_i |q_i| 2^k <= 2^61 (a grid
+        // fixed point of the spread: 2^k with sum_i |q_i| 2^k < 2^61 (a mesh
         // point's sum is at most sum_i |q_i|: the spline weights lie in [0, 1])
-        double qabs = 0.0;
-        for (int32_t g = 0; g < n; ++g) qabs += std::fabs(c->tparams[c->type[g]]);
-        int e2 = 0;
+        // and every term |q w w w| 2^k < 2^51 (exact integer conversion by one
+        // FP64 addition)
+        double qabs = 0.0, qmax = 0.0;
+        for (int32_t g = 0; g < n; ++g) {
+            qabs += std::fabs(c->tparams[c->type[g]]);
+            qmax = std::max(qmax, std::fabs(c->tparams[c->type[g]]));
+        }
+        int e2 = 0, e3 = 0;
         std::frexp(std::max(qabs, 1e-300), &e2);     // qabs < 2^e2
-        c->pme_qscale = std::ldexp(1.0, std::min(61 - e2, 60));
+        std::frexp(std::max(qmax, 1e-300), &e3);     // qmax < 2^e3
+        c->pme_qscale = std::ldexp(1.0, std::min(std::min(61 - e2, 51 - e3), 60));
     }
     c->have_system = true;
     c->bound = false;
@@ -503,7 +510,7 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
-        seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e;
+        seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w;
     size_t ls[2][15];
 };
 
@@ -546,7 +553,11 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.grid = L.take(16 * (size_t)std::max<int64_t>(1, c->pme_points));
     o.theta = L.take(8 * (size_t)std::max<int64_t>(1, c->pme_points));
     o.grec = L.take(24 * n);
-    o.pme_e = L.take(8 * (size_t)(c->pme_points / 256 + 2));
+    o.pme_e = L.take(8 * (size_t)(c->pme_points / 256 + 2));   // >= the fused pass's blocks (K^3 / 512)
+    const size_t pn = c->pme ? (size_t)n : 1;
+    o.pme_fl = L.take(16 * pn);
+    o.pme_f = L.take(32 * pn);
+    o.pme_w = L.take(8 * 3 * (size_t)std::max(1, c->p.pme_order) * pn);
     o.xcnt = L.take(4 * n);
     o.xcol = L.take(4 * n * (size_t)c->xcap);
     for (int k = 0; k < 2; ++k) {
@@ -666,6 +677,9 @@ bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double
     c->d_theta = at<double>(ws, o.theta);
     c->d_grec = at<double>(ws, o.grec);
     c->d_pme_e = at<double>(ws, o.pme_e);
+    c->pme_atoms.fl = at<int4>(ws, o.pme_fl);
+    c->pme_atoms.f = at<double4>(ws, o.pme_f);
+    c->pme_atoms.w = at<double>(ws, o.pme_w);
     c->d_charge = at<double>(ws, o.tparams);     // per-type charges: the first n_types parameters
     if (c->pme) HIPCHK(c, up(sm, ws, o.theta, c->theta));
     HIPCHK(c, hipMemsetAsync(c->d_grec, 0, 24 * (size_t)c->n, sm));
@@ -852,6 +866,13 @@ static PmeArgs pme_args(const bounce_ctx *c, int32_t step_off, int32_t mirror_se
     pa.mirror_sel = mirror_sel;
     pa.qscale = c->pme_qscale;
     pa.inv_qscale = 1.0 / c->pme_qscale;
+    for (int k = 0; k < 3; ++k) {
+        pa.ncell[k] = ri.ncell[k];
+        pa.cw[k] = ri.cw[k];
+    }
+    // an atom lies within s/2 of the cell it was listed in (the skin guard);
+    // the small extra covers rounding at cell edges
+    pa.margin = 0.5 * c->p.skin + 1e-9 * std::max(ri.box[0], std::max(ri.box[1], ri.box[2]));
     return pa;
 }
 
@@ -865,8 +886,8 @@ static bool pme_at(const bounce_ctx *c, int64_t n)
 static void enqueue_pme(bounce_ctx *c, int32_t step_off)
 {
     const bool in_f0 = c->p.respa_m == 0;
-    launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1), c->d_grid,
-               c->d_theta, in_f0 ? c->d_fpair : c->d_grec, 0, in_f0 ? 1 : 0, nullptr);
+    launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1), c->pme_atoms,
+               c->d_grid, c->d_theta, in_f0 ? c->d_fpair : c->d_grec, 0, in_f0 ? 1 : 0, nullptr);
 }
 
 static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
@@ -1070,7 +1091,8 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
     if (which & BOUNCE_G_RECIP) {
         if (!(which & (BOUNCE_G_SHORT | BOUNCE_G_LONG | BOUNCE_G_FULL)))
             launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
-        launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pme_args(c, 0, 0), c->d_grid, c->d_theta,
+        launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pme_args(c, 0, 0), c->pme_atoms, c->d_grid,
+                   c->d_theta,
                    grad, 1, first ? 0 : 1, nullptr);
         first = 0;
     }
@@ -1203,11 +1225,12 @@ bounce_status bounce_pme_energy(bounce_ctx *c, double *e3)
     hipStream_t sm = c->stream;
     launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
     const PmeArgs pa = pme_args(c, 0, 0);
-    launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pa, c->d_grid, c->d_theta, nullptr, 0, 0,
+    launch_pme(sm, c->n, c->aux, c->pos, c->d_charge, c->tp, pa, c->pme_atoms, c->d_grid, c->d_theta, nullptr,
+               0, 0,
                c->d_pme_e);
     launch_pme_excl_energy(sm, c->n, c->pos, c->d_charge, c->tp, pa, c->d_atom);
     launch_segment_sum(sm, 1, c->d_one_seg, c->d_atom, 1, 1, 0, c->d_seg);
-    const int64_t nb = (c->pme_points + 255) / 256;
+    const int64_t nb = pme_energy_parts(pa);
     std::vector<double> part(nb), ex(1);
     HIPCHK(c, hipMemcpyAsync(part.data(), c->d_pme_e, 8 * nb, hipMemcpyDeviceToHost, sm));
     HIPCHK(c, hipMemcpyAsync(ex.data(), c->d_seg, 8, hipMemcpyDeviceToHost, sm));
@@ -1375,8 +1398,8 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
         if (which == 0) enqueue_force(c, 0);
         else if (which == 1) enqueue_build(c, 0);
         else if (which == 4)     // into the RESPA buffer, which every outer kick recomputes first
-            launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, 0, -1), c->d_grid,
-                       c->d_theta, c->d_grec, 0, 0, nullptr);
+            launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, 0, -1), c->pme_atoms,
+                       c->d_grid, c->d_theta, c->d_grec, 0, 0, nullptr);
         else launch_step(c->stream, step_args(c, 0, 0, 0));   // no kicks, jumps or drifts
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));

@@ -74,6 +74,18 @@ struct PmeArgs {
     int32_t step_off;
     int32_t mirror_sel;           // -1: parity of the step, 0/1: fixed mirror
     double qscale, inv_qscale;    // fixed-point scale of the spread charges (2^k)
+    int32_t ncell[3];             // the list cell grid (atoms of a cell are contiguous in
+    double cw[3];                 //   sorted order) and its cell edges
+    double margin;                // how far an atom may be from its cell: s/2 (skin guard)
+};
+
+// per-atom mesh data of one evaluation (sorted slots), written by its first
+// kernel: floor(u) per axis, the fractions u - floor(u) with the charge, and
+// the spread weights M_n(f + j) (axis 0 times q 2^k)
+struct PmeAtoms {
+    int4 *fl;                     // [N] (fl0, fl1, fl2, 0)
+    double4 *f;                   // [N] (f0, f1, f2, q)
+    double *w;                    // [3 n][N]: weight k of atom s at w[k N + s]
 };
 
 struct JumpArgs {
@@ -102,8 +114,10 @@ void launch_rdf(hipStream_t sm, int32_t n, const RepInfo *reps, int32_t single_r
 void launch_msd_atom(hipStream_t sm, int32_t n, const double *pos, const double *ref,
                      const int32_t *type, double *vals);
 void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos, const double *charge,
-                const Topo &tp, const PmeArgs &pa, double2 *grid, const double *theta, double *out,
-                int32_t out_global, int32_t accumulate, double *energy_parts);
+                const Topo &tp, const PmeArgs &pa, const PmeAtoms &pm, double2 *grid, const double *theta,
+                double *out, int32_t out_global, int32_t accumulate, double *energy_parts);
+// number of per-block energy partials launch_pme writes (energy_parts != NULL)
+int64_t pme_energy_parts(const PmeArgs &pa);
 void launch_pme_excl_energy(hipStream_t sm, int32_t n, const double *pos, const double *charge,
                             const Topo &tp, const PmeArgs &pa, double *atom_out);
 void launch_list_to_global(hipStream_t sm, int32_t n, const ListSet &ls, int32_t which,
