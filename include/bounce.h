@@ -59,6 +59,8 @@ enum { BOUNCE_BJAOAJB = 0, BOUNCE_BAOAB = 1 };          /* integrator          *
 enum { BOUNCE_PAIR_FP32 = 0, BOUNCE_PAIR_FP64 = 1 };    /* pair arithmetic     */
 enum { BOUNCE_COUL_BARE = 0, BOUNCE_COUL_EWALD = 1 };   /* 1/r or erfc(a r)/r  */
 enum { BOUNCE_PH_JA = 0, BOUNCE_PH_O = 1, BOUNCE_PH_JB = 2 };  /* random-stream phases */
+/* what the RESPA outer step carries (bounce_params.respa_outer) */
+enum { BOUNCE_OUTER_RECIP = 0, BOUNCE_OUTER_NONBONDED = 1 };
 /* gradient parts for bounce_compute_gradient (bit mask) */
 enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8,
        BOUNCE_G_RECIP = 16 };   /* RECIP: smooth-PME mesh + excluded-pair correction */
@@ -103,8 +105,11 @@ typedef struct {
     int32_t pme_order;         /* B-spline order: 4, 5 or 6                              */
     int32_t respa_m;           /* 0: mesh force in F_0 every step (basic BOUNCE);        */
                                /* m >= 1: RESPA outer step of m dt, half kicks with the  */
-                               /* mesh force at every m-th step (rebuild_interval % m == 0) */
-    int32_t pme_reserved;
+                               /* outer force at every m-th step (rebuild_interval % m == 0) */
+    int32_t respa_outer;       /* BOUNCE_OUTER_RECIP: the outer force is the mesh force;  */
+                               /* BOUNCE_OUTER_NONBONDED: also the short-range pair force */
+                               /* (Sec. V: F_out = short direct + short VdW + recip; F_0  */
+                               /* keeps the bonded terms); needs respa_m >= 1, any box   */
 } bounce_params;
 
 typedef struct {

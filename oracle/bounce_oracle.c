@@ -673,8 +673,10 @@ static int build_run_lists(const orc_params *p, const orc_topology *t, const dou
 /* F_0 (Sec. IV.A / V): bonded + short pair part ((1-chi) W'_sf, r < r'') for
    BOUNCE, bonded + full W'_sf (r < rc) for BAOAB; pairs from the force list in
    canonical order. */
-static void grad_f0(const orc_params *p, const orc_topology *t, const double *q,
-                    const run_lists *L, double *g, orc_counters *cnt)
+/* F_0: bonded terms plus (pair != 0) the short-range pair part; with
+   bonded = 0 only the pair part (the outer force of BOUNCE-RESPA) */
+static void grad_parts(const orc_params *p, const orc_topology *t, const double *q,
+                       const run_lists *L, double *g, orc_counters *cnt, int pair, int bonded)
 {
     int which = p->integrator == ORC_BOUNCE ? ORC_G_SHORT : ORC_G_FULL;
     double rlim = p->integrator == ORC_BOUNCE ? p->r_off : p->r_cut;
@@ -682,7 +684,7 @@ static void grad_f0(const orc_params *p, const orc_topology *t, const double *q,
 #pragma omp parallel for reduction(+ : evals) schedule(dynamic, 16)
     for (int32_t i = 0; i < t->n_atoms; ++i) {
         double gi[3] = {0.0, 0.0, 0.0};
-        for (int64_t k = L->s_ptr[i]; k < L->s_ptr[i + 1]; ++k) {
+        for (int64_t k = L->s_ptr[i]; k < L->s_ptr[i + 1] && pair; ++k) {
             int32_t j = L->s_col[k];
             double d[3], gp[3];
             min_image(p, q + 3 * i, q + 3 * j, d);
@@ -691,7 +693,7 @@ static void grad_f0(const orc_params *p, const orc_topology *t, const double *q,
             for (int c = 0; c < 3; ++c) gi[c] += gp[c];
             ++evals;
         }
-        bonded_atom(p, t, q, i, gi);
+        if (bonded) bonded_atom(p, t, q, i, gi);
         for (int c = 0; c < 3; ++c) g[3 * i + c] = gi[c];
     }
     cnt->pair_evals += evals / 2;
@@ -934,6 +936,28 @@ double orc_ewald_recip(const orc_params *p, const orc_topology *t, const double 
     return E;
 }
 
+/* the gradients of one step at q: g = F_0 (bonded terms, the short-range
+   pair part unless it is on the outer step, the mesh part unless it is on
+   the outer step) and gout = the outer-step gradient (mesh part and, with
+   out_pair, the short-range pair part) */
+static void forces(const orc_params *p, const orc_topology *t, const double *q, const run_lists *L,
+                   double *g, double *gout, orc_counters *cnt, int pme, int respa, int out_pair,
+                   double erec[3])
+{
+    const int64_t n3 = 3 * (int64_t)t->n_atoms;
+    grad_parts(p, t, q, L, g, cnt, !out_pair, 1);
+    if (out_pair) grad_parts(p, t, q, L, gout, cnt, 1, 0);
+    else
+        for (int64_t k = 0; k < n3; ++k) gout[k] = 0.0;
+    if (pme) {
+        double *gr = malloc(sizeof(double) * (size_t)(n3 + 1));
+        orc_pme(p, t, q, gr, erec);
+        double *dst = respa ? gout : g;
+        for (int64_t k = 0; k < n3; ++k) dst[k] += gr[k];
+        free(gr);
+    }
+}
+
 int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, int64_t step0,
             int32_t nsteps, orc_event *ev, int64_t ev_cap, int64_t *n_ev, orc_counters *cnt)
 {
@@ -953,9 +977,12 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
     jump_consts jc = make_jump_consts(p);
     int bounce = p->integrator == ORC_BOUNCE;
     double h = 0.5 * p->dt;
-    /* reciprocal-space force: in F_0 (respa_m = 0) or as RESPA outer half kicks */
+    /* reciprocal-space force: in F_0 (respa_m = 0) or as RESPA outer half kicks;
+       with respa_outer = NONBONDED the short-range pair force moves to the
+       outer step as well (F_0 keeps the bonded terms) */
     const int pme = p->periodic && p->pme_grid[0] > 0;
-    const int respa = pme && p->respa_m >= 1;
+    const int out_pair = p->respa_m >= 1 && p->respa_outer == ORC_OUTER_NONBONDED;
+    const int respa = p->respa_m >= 1 && (pme || out_pair);
     const double H = 0.5 * p->dt * (double)p->respa_m;
     double erec[3];
 
@@ -973,10 +1000,7 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
     status = build_run_lists(p, t, q, &L);
     if (status != ORC_OK) goto done;
     cnt->rebuilds++;
-    grad_f0(p, t, q, &L, g, cnt);
-    if (pme) orc_pme(p, t, q, grec, erec);
-    if (pme && !respa)
-        for (int64_t k = 0; k < 3 * (int64_t)n; ++k) g[k] += grec[k];
+    forces(p, t, q, &L, g, grec, cnt, pme, respa, out_pair, erec);
     for (int64_t n_step = step0; n_step < step0 + nsteps; ++n_step) {
         if (respa && n_step % p->respa_m == 0) kick(t, v, grec, H);   /* outer half kick */
         kick(t, v, g, h);                          /* B */
@@ -995,10 +1019,7 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
             if (s != ORC_OK) { status = s; goto done; }
             cnt->rebuilds++;
         }
-        grad_f0(p, t, q, &L, g, cnt);
-        if (pme) orc_pme(p, t, q, grec, erec);
-        if (pme && !respa)
-            for (int64_t k = 0; k < 3 * (int64_t)n; ++k) g[k] += grec[k];
+        forces(p, t, q, &L, g, grec, cnt, pme, respa, out_pair, erec);
         JUMP(n_step, ORC_PH_JB);                   /* J */
         kick(t, v, g, h);                          /* B */
         if (respa && (n_step + 1) % p->respa_m == 0) kick(t, v, grec, H);   /* outer half kick */

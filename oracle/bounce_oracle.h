@@ -76,12 +76,17 @@ typedef struct {
        per edge (pme_grid[0] = 0: no reciprocal part), B-spline order, and the
        schedule: respa_m = 0 adds the reciprocal force to F_0 every step (the
        basic algorithm), respa_m >= 1 applies it as half kicks of m dt around
-       every m steps (the RESPA outer step) */
+       every m steps (the RESPA outer step).  respa_outer = ORC_OUTER_NONBONDED
+       (with respa_m >= 1) also moves the short-range pair force out of F_0
+       onto the outer step (Sec. V: F_out = short direct + short VdW + recip;
+       bonded terms stay inner), with or without the mesh */
     int32_t pme_grid[3];
     int32_t pme_order;
     int32_t respa_m;
-    int32_t pad1;
+    int32_t respa_outer;
 } orc_params;
+
+enum { ORC_OUTER_RECIP = 0, ORC_OUTER_NONBONDED = 1 };
 
 typedef struct {
     int32_t n_atoms;

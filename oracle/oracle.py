@@ -23,6 +23,7 @@ PH_JA, PH_O, PH_JB = 0, 1, 2
 RATE_ATOM, RATE_PAIR = 0, 1
 WEIGHT_BITS = 20
 G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
+OUTER_RECIP, OUTER_NONBONDED = 0, 1
 STATUS = {0: "OK", -1: "ARG", -4: "SKIN", -5: "BOUND", -6: "POISSON_CAP", -7: "NONFINITE",
           -9: "GRID"}
 KE, KB, ACC = 332.0637, 0.0019872041, 4.184e-4
@@ -52,7 +53,7 @@ class Params(C.Structure):
                 ("rate_mode", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("charge", C.c_double * MAXT), ("eps", C.c_double * MAXT),
                 ("sigma", C.c_double * MAXT), ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32),
-                ("respa_m", C.c_int32), ("pad1", C.c_int32)]
+                ("respa_m", C.c_int32), ("respa_outer", C.c_int32)]
 
 
 class Topo(C.Structure):
@@ -128,7 +129,7 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
                 rebuild_interval=10, seed=0, replica=0, bound_scale=1.0, max_proposals=100000,
                 charge=None, eps=None, sigma=None, periodic=None, box=None, cell_size=None,
                 grid_origin=None, grid_dims=None, rate_mode=RATE_ATOM, pme_grid=None, pme_order=5,
-                respa_m=0):
+                respa_m=0, respa_outer=0):
     """Parameters for the oracle; geometry defaults are taken from a WaterSystem."""
     p = Params()
     p.integrator = integrator
@@ -146,7 +147,7 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
     p.rate_mode = rate_mode
     for k in range(3):
         p.pme_grid[k] = int(pme_grid[k]) if pme_grid is not None else 0
-    p.pme_order, p.respa_m = int(pme_order), int(respa_m)
+    p.pme_order, p.respa_m, p.respa_outer = int(pme_order), int(respa_m), int(respa_outer)
     if sys is not None:
         from workloads import tip3p_params
         ff = tip3p_params()

@@ -15,14 +15,14 @@ import numpy as np
 from . import _abi
 from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_RECIP,
                    G_SHORT,
-                   LIST_CAND, LIST_FORCE, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, RATE_ATOM,
+                   LIST_CAND, LIST_FORCE, OUTER_NONBONDED, OUTER_RECIP, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, RATE_ATOM,
                    RATE_PAIR, BounceError,
                    bounce_counters, bounce_event, bounce_params, bounce_system, check)
 
 __all__ = ["lib", "Simulation", "DirectEnergy", "make_params", "BounceError", "BJAOAJB", "BAOAB",
            "PAIR_FP32", "PAIR_FP64", "COUL_BARE", "COUL_EWALD", "PH_JA", "PH_O", "PH_JB",
            "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "G_RECIP", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
-           "RATE_PAIR"]
+           "RATE_PAIR", "OUTER_RECIP", "OUTER_NONBONDED"]
 
 
 def lib():
@@ -34,12 +34,15 @@ def make_params(**kw) -> bounce_params:
     """bounce_params with defaults: BOUNCE, FP32 pair math, dt = 1 fs, gamma = 1/ps,
     300 K, r'/r'' = 6/7, rc = 9, skin 2, alpha 0.35, K = 10, one rate bound per
     atom type (RATE_ATOM), no reciprocal-space mesh (pme_grid = (0, 0, 0); when
-    set: B-spline order 5, mesh force in F_0 unless respa_m >= 1)."""
+    set: B-spline order 5, mesh force in F_0 unless respa_m >= 1); with
+    respa_m >= 1 and respa_outer = OUTER_NONBONDED the short-range pair force
+    moves to the outer step too."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
-             pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0)
+             pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0,
+             respa_outer=OUTER_RECIP)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():

@@ -19,6 +19,7 @@ PAIR_FP32, PAIR_FP64 = 0, 1
 COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
 G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
+OUTER_RECIP, OUTER_NONBONDED = 0, 1
 LIST_FORCE, LIST_CAND = 0, 1
 RATE_ATOM, RATE_PAIR = 0, 1
 
@@ -33,7 +34,7 @@ class bounce_params(C.Structure):
                 ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64),
                 ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32),
                 ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32), ("respa_m", C.c_int32),
-                ("pme_reserved", C.c_int32)]
+                ("respa_outer", C.c_int32)]
 
 
 class bounce_system(C.Structure):

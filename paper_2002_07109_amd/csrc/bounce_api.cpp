@@ -113,6 +113,8 @@ struct bounce_ctx {
     unsigned long long *d_rdf = nullptr;
     // smooth PME: mesh, influence function theta(k) (host-computed), RESPA gradient
     bool pme = false;
+    bool out_pair = false;        // the short-range pair force is on the RESPA outer step
+    bool outer = false;           // there is an outer step (mesh and/or pair force on it)
     int64_t pme_points = 0;
     double pme_qscale = 1.0;
     std::vector<double> theta;
@@ -182,9 +184,11 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
             const int32_t g = p->pme_grid[k];
             if (g < 8 || g > 512 || (g & (g - 1))) return BOUNCE_E_ARG;
         }
-        if (p->pme_order < 4 || p->pme_order > 6 || !p->periodic || p->respa_m < 0) return BOUNCE_E_ARG;
-        if (p->respa_m > 0 && p->rebuild_interval % p->respa_m) return BOUNCE_E_ARG;
+        if (p->pme_order < 4 || p->pme_order > 6 || !p->periodic) return BOUNCE_E_ARG;
     }
+    if (p->respa_m < 0 || (p->respa_m > 0 && p->rebuild_interval % p->respa_m)) return BOUNCE_E_ARG;
+    if (p->respa_outer != BOUNCE_OUTER_RECIP && p->respa_outer != BOUNCE_OUTER_NONBONDED) return BOUNCE_E_ARG;
+    if (p->respa_outer == BOUNCE_OUTER_NONBONDED && p->respa_m < 1) return BOUNCE_E_ARG;
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
@@ -469,6 +473,8 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     make_ou(c);
     make_bounds(c);
     c->pme = c->p.pme_grid[0] > 0;
+    c->out_pair = c->p.respa_m >= 1 && c->p.respa_outer == BOUNCE_OUTER_NONBONDED;
+    c->outer = c->p.respa_m >= 1 && (c->pme || c->out_pair);
     c->pme_points = 0;
     if (c->pme) {
         if (R != 1 || !c->reps[0].periodic)
@@ -839,15 +845,22 @@ static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
     return a;
 }
 
-static void enqueue_force(bounce_ctx *c, int32_t step_off)
+// the short-range pair force (F_0's pair part, or the outer step's) into out,
+// sorted order
+static void launch_step_pair(bounce_ctx *c, int32_t step_off, double *out)
 {
     PairArgs a = pair_args(c, c->main, -1);
     a.step_off = step_off;
-    a.out = c->d_fpair;
+    a.out = out;
     a.out_global = 0;
     a.accumulate = 0;
     launch_pair(c->stream, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
                 c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
+}
+
+static void enqueue_force(bounce_ctx *c, int32_t step_off)
+{
+    if (!c->out_pair) launch_step_pair(c, step_off, c->d_fpair);
 }
 
 static PmeArgs pme_args(const bounce_ctx *c, int32_t step_off, int32_t mirror_sel)
@@ -876,18 +889,27 @@ static PmeArgs pme_args(const bounce_ctx *c, int32_t step_off, int32_t mirror_se
     return pa;
 }
 
-// the mesh force at step n (device offset step_off): into F_0's pair part
-// every step (respa_m = 0), or into the RESPA gradient at every m-th step
-static bool pme_at(const bounce_ctx *c, int64_t n)
+// step n is the boundary of a RESPA outer step
+static bool outer_at(const bounce_ctx *c, int64_t n)
 {
-    return c->pme && (c->p.respa_m == 0 || n % c->p.respa_m == 0);
+    return c->outer && n % c->p.respa_m == 0;
 }
 
-static void enqueue_pme(bounce_ctx *c, int32_t step_off)
+// the forces of step n beyond F_0's own (device offset step_off): the mesh
+// force into F_0's pair part every step (respa_m = 0), or, at an outer
+// boundary, the outer gradient (mesh force and/or short-range pair force)
+static void enqueue_extra(bounce_ctx *c, int64_t n, int32_t step_off)
 {
-    const bool in_f0 = c->p.respa_m == 0;
-    launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1), c->pme_atoms,
-               c->d_grid, c->d_theta, in_f0 ? c->d_fpair : c->d_grec, 0, in_f0 ? 1 : 0, nullptr);
+    if (c->pme && c->p.respa_m == 0) {
+        launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1),
+                   c->pme_atoms, c->d_grid, c->d_theta, c->d_fpair, 0, 1, nullptr);
+        return;
+    }
+    if (!outer_at(c, n)) return;
+    if (c->out_pair) launch_step_pair(c, step_off, c->d_grec);
+    if (c->pme)
+        launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, step_off, -1),
+                   c->pme_atoms, c->d_grid, c->d_theta, c->d_grec, 0, c->out_pair ? 1 : 0, nullptr);
 }
 
 static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
@@ -907,6 +929,7 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     a.ls = c->main;
     a.grec = c->d_grec;
     a.rec_close = a.rec_open = 0.0;
+    a.f0_pair = c->out_pair ? 0 : 1;
     a.st = c->d_st;
     a.cnt = c->d_cnt;
     a.wave_cnt = c->d_wave_cnt;
@@ -941,9 +964,9 @@ static void enqueue_substep(bounce_ctx *c, int close, int open, hipEvent_t e0 = 
         c->host_rebuilds++;
     }
     enqueue_force(c, c->pending);
-    if (pme_at(c, c->step)) enqueue_pme(c, c->pending);
+    enqueue_extra(c, c->step, c->pending);
     StepArgs a = step_args(c, close, open, c->pending);
-    if (c->pme && c->p.respa_m > 0 && c->step % c->p.respa_m == 0) {
+    if (outer_at(c, c->step)) {
         // step n = c->step ends one RESPA block (close) and starts the next (open)
         const double H = 0.5 * c->p.dt * (double)c->p.respa_m;
         a.rec_close = close ? H : 0.0;
@@ -984,10 +1007,8 @@ static bounce_status make_graph(bounce_ctx *c)
         enqueue_force(c, k);
         // the graph starts at a multiple of K, and K is a multiple of respa_m
         StepArgs a = step_args(c, 1, 1, k);
-        if (pme_at(c, k)) {
-            enqueue_pme(c, k);
-            if (c->p.respa_m > 0) a.rec_close = a.rec_open = 0.5 * c->p.dt * (double)c->p.respa_m;
-        }
+        enqueue_extra(c, k, k);
+        if (outer_at(c, k)) a.rec_close = a.rec_open = 0.5 * c->p.dt * (double)c->p.respa_m;
         launch_step(c->stream, a);
     }
     launch_advance(c->stream, c->d_st, c->p.rebuild_interval);
@@ -1395,7 +1416,7 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     HIPCHK(c, hipEventCreate(&e1));
     HIPCHK(c, hipEventRecord(e0, c->stream));
     for (int32_t k = 0; k < reps; ++k) {
-        if (which == 0) enqueue_force(c, 0);
+        if (which == 0) launch_step_pair(c, 0, c->d_fpair);
         else if (which == 1) enqueue_build(c, 0);
         else if (which == 4)     // into the RESPA buffer, which every outer kick recomputes first
             launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, 0, -1), c->pme_atoms,

@@ -40,7 +40,7 @@ struct StepArgs {
     int32_t max_proposals;
     int32_t step_off;             // step n = device counter + step_off
     int32_t single_rep;           // 1: one replica (its RepInfo read as reps[0])
-    int32_t pad0;
+    int32_t f0_pair;              // 1: F_0 includes fpair; 0: the pair force is on the outer step
     const RepInfo *reps;
     Topo tp;
     ListSet ls;
@@ -60,7 +60,7 @@ struct StepArgs {
     PairGlobals pg;
     double dt, half_dt, c1, beta;
     double skin_half2;            // (s/2)^2
-    const double *grec;           // [N][3] sorted: reciprocal-space gradient for RESPA kicks
+    const double *grec;           // [N][3] sorted: outer-step gradient for the RESPA kicks
     double rec_close, rec_open;   // kick lengths (fs) with grec after the closing B / before the opening B
 };
 

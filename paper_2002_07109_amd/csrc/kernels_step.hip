@@ -368,8 +368,10 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
 constexpr int LPA = 4;
 constexpr int JB_L1 = 3, JB_L2 = 1, JA_L1 = 2, JA_L2 = 0;
 
-// RESPA outer half kick (Sec. V): v -= H * grad_rec / m at the boundary of an
-// outer step, read where used (one step in respa_m is a boundary)
+// RESPA outer half kick (Sec. V): v -= H * grad_out / m at the boundary of an
+// outer step (grad_out: the mesh gradient, plus the short-range pair gradient
+// when that is on the outer step), read where used (one step in respa_m is a
+// boundary)
 __device__ __forceinline__ void outer_kick(const StepArgs &a, int32_t s, int32_t g, double H, double *v)
 {
     const double k = a.tp.acc_m[g];
@@ -410,9 +412,11 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         g = si.x;
         rep = si.y;
         xi = X[s];
-        F[0] = a.fpair[3 * (int64_t)s];
-        F[1] = a.fpair[3 * (int64_t)s + 1];
-        F[2] = a.fpair[3 * (int64_t)s + 2];
+        if (a.f0_pair) {
+            F[0] = a.fpair[3 * (int64_t)s];
+            F[1] = a.fpair[3 * (int64_t)s + 1];
+            F[2] = a.fpair[3 * (int64_t)s + 2];
+        }
         const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
         lid = g - (int32_t)ri.atom_off;
         v[0] = a.vel[3 * (int64_t)g];

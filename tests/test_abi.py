@@ -76,10 +76,14 @@ def test_argument_errors_need_no_gpu():
                dict(pme_grid=(32, 32, 32), pme_order=3), dict(pme_grid=(32, 32, 32), pme_order=7),
                dict(pme_grid=(32, 32, 32), periodic=0),
                dict(pme_grid=(32, 32, 32), respa_m=3, rebuild_interval=10),
-               dict(pme_grid=(32, 32, 32), respa_m=-1)):
+               dict(pme_grid=(32, 32, 32), respa_m=-1), dict(respa_outer=1, respa_m=0),
+               dict(respa_outer=2, respa_m=2), dict(respa_outer=1, respa_m=3, rebuild_interval=10)):
         p = make_params(**kw)
         assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.E_ARG, kw
     p = make_params(pme_grid=(16, 32, 64), pme_order=6, respa_m=5, rebuild_interval=10)
+    assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.OK
+    L.bounce_destroy(ctx)
+    p = make_params(periodic=0, respa_m=2, respa_outer=1)        # outer pair force, no mesh
     assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.OK
     L.bounce_destroy(ctx)
 

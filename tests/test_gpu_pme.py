@@ -5,7 +5,8 @@ as outer half kicks every m steps, and graph replay."""
 import numpy as np
 import pytest
 
-from helpers import BOX, event_keys, gpu_sim, oracle_params, rel_err_total, relaxed_box
+from helpers import (BOX, DROPLET, event_keys, gpu_sim, oracle_params, rel_err_total, relaxed_box,
+                     relaxed_droplet)
 from workloads import jitter_positions
 
 pytestmark = pytest.mark.gpu
@@ -108,3 +109,41 @@ def test_mesh_needs_one_periodic_replica(box):
     import paper_2002_07109_amd as B
     with pytest.raises(B.BounceError):
         gpu_sim([box, box], MESH)
+
+
+@pytest.mark.parametrize("case", ["box_mesh_m2", "box_mesh_m5", "box_m2", "drop_m2", "box_baoab_m5"])
+def test_trajectory_with_outer_nonbonded(orc, box, case):
+    """BOUNCE-RESPA with the short-range pair force (and the mesh force) on the
+    outer step (Sec. V): FP64 trajectory and jump events against the oracle."""
+    if case.startswith("drop"):
+        sys, cfg = relaxed_droplet("c0"), dict(DROPLET)
+    else:
+        sys, cfg = box, dict(MESH if "mesh" in case else BOX)
+    cfg.update(respa_outer=1, respa_m=5 if case.endswith("m5") else 2)
+    if "baoab" in case:
+        cfg["integrator"] = 1
+    nsteps = 60
+    sim = gpu_sim(sys, cfg, fp64=True, log_events=True, event_capacity=4_000_000)
+    sim.step(nsteps)
+    sim.sync()
+    o = orc.run(oracle_params(orc, sys, cfg), orc.Topology.from_system(sys), sys.pos, sys.vel, 0,
+                nsteps, ev_cap=4_000_000)
+    assert o["status"] == 0, o["status_name"]
+    dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
+    dv = np.abs(sim.vel.cpu().numpy() - o["v"]).max()
+    assert dq <= 1e-6 and dv <= 1e-6, (dq, dv)
+    if cfg["integrator"] == 0:
+        ev, n = sim.events()
+        assert n == o["n_events"] and n > 0
+        assert np.array_equal(event_keys(ev), event_keys(o["events"]))
+
+
+def test_outer_nonbonded_graph_replay_is_bit_exact(box):
+    cfg = dict(MESH, respa_m=2, respa_outer=1)
+    sa = gpu_sim(box, cfg, fp64=False, use_graph=False)
+    sb = gpu_sim(box, cfg, fp64=False, use_graph=True)
+    for sim in (sa, sb):
+        sim.step(35)
+        sim.sync()
+    assert np.array_equal(sa.pos.cpu().numpy(), sb.pos.cpu().numpy())
+    assert np.array_equal(sa.vel.cpu().numpy(), sb.vel.cpu().numpy())

@@ -137,3 +137,49 @@ def test_respa_outer_step_conserves_energy(orc):
                         pme_grid=[24, 24, 24], pme_order=5, respa_m=2)
     (er, _, _), g = orc.pme(p, topo, s.pos)
     assert np.abs(g).max() > 1.0
+
+
+def test_outer_nonbonded_with_one_inner_step_is_the_basic_scheme(orc):
+    """BOUNCE-RESPA with the short pair force on the outer step (Sec. V) and
+    m = 1: the outer half kicks and the inner B kicks add up to the basic
+    scheme's kicks, so the trajectory and the jump events are the same up to
+    rounding; with m = 2 they are not."""
+    from helpers import relaxed_box
+    s = relaxed_box("b8")
+    topo = orc.Topology.from_system(s)
+    kw = dict(integrator=orc.BOUNCE, dt=1.0, ewald_alpha=0.45, r_on=6.0, r_off=7.0, r_cut=9.0,
+              skin=2.0, pme_grid=[16, 16, 16], pme_order=5)
+    base = orc.run(orc.make_params(s, respa_m=0, **kw), topo, s.pos, s.vel, 0, 20, ev_cap=200000)
+    one = orc.run(orc.make_params(s, respa_m=1, respa_outer=orc.OUTER_NONBONDED, **kw), topo, s.pos,
+                  s.vel, 0, 20, ev_cap=200000)
+    two = orc.run(orc.make_params(s, respa_m=2, respa_outer=orc.OUTER_NONBONDED, **kw), topo, s.pos,
+                  s.vel, 0, 20, ev_cap=200000)
+    for o in (base, one, two):
+        assert o["status"] == 0, o["status_name"]
+    assert base["n_events"] > 0
+    assert np.abs(one["q"] - base["q"]).max() < 1e-9
+    assert np.abs(one["v"] - base["v"]).max() < 1e-9
+    key = lambda e: sorted(zip(e["step"], e["phase"], e["atom"], e["k"], e["partner"], e["accepted"]))
+    assert key(one["events"]) == key(base["events"])
+    assert np.abs(two["q"] - base["q"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("with_mesh", [False, True])
+def test_outer_nonbonded_conserves_energy(orc, with_mesh):
+    """BAOAB without friction, bonded forces on the inner step (0.5 fs) and the
+    short-range pair force (plus the mesh force) on an outer step of m = 4:
+    the total energy stays put, and moving the pair force to the outer step
+    with the wrong sign or size of kick would not."""
+    from helpers import relaxed_box
+    s = relaxed_box("b8")
+    topo = orc.Topology.from_system(s)
+    mesh = dict(pme_grid=[24, 24, 24], pme_order=5) if with_mesh else {}
+    p = orc.make_params(s, integrator=orc.BAOAB, dt=0.5, gamma=0.0, ewald_alpha=0.45, r_cut=9.0,
+                        skin=2.0, respa_m=4, respa_outer=orc.OUTER_NONBONDED, rebuild_interval=8,
+                        **mesh)
+    e0 = orc.energies(p, topo, s.pos, s.vel)
+    o = orc.run(p, topo, s.pos, s.vel, 0, 80)
+    assert o["status"] == 0, o["status_name"]
+    e1 = orc.energies(p, topo, o["q"], o["v"])
+    tot = lambda e: e["bond"] + e["angle"] + e["pair"] + e["kin"]
+    assert abs(tot(e1) - tot(e0)) < 2e-3 * e0["kin"], (tot(e1) - tot(e0), e0["kin"])
