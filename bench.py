@@ -88,13 +88,13 @@ def pair_count(pos, box, r, n_excl_within):
 RATE_MODES = {"atom": 0, "pair": 1}
 
 
-def run_gpu(args, system, ff, integrator, state, rate_mode=0, **mesh):
+def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=None, **mesh):
     import torch
     import paper_2002_07109_amd as B
     p = B.make_params(integrator=integrator, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
-                      periodic=1, dt=1.0, gamma=1e-3, temperature=300.0, r_on=args.r_on,
+                      periodic=1, dt=dt, gamma=1e-3, temperature=300.0, r_on=args.r_on,
                       r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
-                      rebuild_interval=args.rebuild, seed=0, cell_size=system.cell_size,
+                      rebuild_interval=rebuild or args.rebuild, seed=0, cell_size=system.cell_size,
                       use_graph=0 if args.no_graph else 1, rate_mode=rate_mode, **mesh)
     sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
     sim.set_state(pos=state[0], vel=state[1], step=0)
@@ -297,7 +297,9 @@ def run_mesh(args, ff):
     mesh, order-5 B-splines, alpha = 0.35/A, real-space cutoff 9 A): BAOAB 1 fs
     with the mesh force every step, BOUNCE with it in F_0 every step, and
     BOUNCE-RESPA with it on an outer step of m = 2 and 5 inner steps (m divides
-    the list interval, 10)."""
+    the list interval), and BOUNCE-RESPA with the short-range pair force on the
+    outer step too (bonded terms inner): 1/2 fs and 0.5/2 fs.  ns/day counts
+    simulated time, so runs with a 0.5 fs inner step take twice the steps."""
     from workloads import water_box
     system = water_box(n_side=32, box_len=98.3, seed=3)
     sub_args = argparse.Namespace(**vars(args))
@@ -313,25 +315,33 @@ def run_mesh(args, ff):
                        "Coulomb + LJ (9 A cutoff) plus smooth-PME reciprocal sum (64^3 mesh, "
                        "order 5, alpha 0.35/A)", "steps": args.mesh_steps,
            "split": list(args.mesh_split)}
-    runs = (("baoab", B.BAOAB, 0), ("bounce", B.BJAOAJB, 0), ("bounce_respa2", B.BJAOAJB, 2),
-            ("bounce_respa5", B.BJAOAJB, 5))
-    for name, integ, m in runs:
+    # (name, integrator, m, outer force, inner dt, list interval in steps)
+    runs = (("baoab", B.BAOAB, 0, B.OUTER_RECIP, 1.0, 10),
+            ("bounce", B.BJAOAJB, 0, B.OUTER_RECIP, 1.0, 10),
+            ("bounce_respa2", B.BJAOAJB, 2, B.OUTER_RECIP, 1.0, 10),
+            ("bounce_respa5", B.BJAOAJB, 5, B.OUTER_RECIP, 1.0, 10),
+            ("bounce_respa_nb_1_2", B.BJAOAJB, 2, B.OUTER_NONBONDED, 1.0, 10),
+            ("bounce_respa_nb_05_2", B.BJAOAJB, 4, B.OUTER_NONBONDED, 0.5, 20))
+    for name, integ, m, outer, dt, rebuild in runs:
+        steps = int(round(args.mesh_steps / dt))       # the same simulated time
+        sub_args.steps = steps
         try:
-            r = run_gpu(sub_args, system, ff, integ, state, pme_grid=grid, pme_order=5, respa_m=m)
+            r = run_gpu(sub_args, system, ff, integ, state, dt=dt, rebuild=rebuild, pme_grid=grid,
+                        pme_order=5, respa_m=m, respa_outer=outer)
         except B.BounceError as e:
             out[name] = {"failed": str(e), "respa_m": m}
             log(f"98k box with mesh, {name}: {e}")
             continue
-        out[name] = {"ms_per_step": round(r["ms_per_step"], 5),
-                     "ns_per_day": round(1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
-                     "respa_m": m, "mesh_us": round(r["mesh_ms"] * 1e3, 3),
+        out[name] = {"ms_per_step": round(r["ms_per_step"], 5), "dt_fs": dt, "steps": steps,
+                     "ns_per_day": round(dt * 1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
+                     "respa_m": m, "outer": "nonbonded+recip" if outer else "recip",
+                     "mesh_us": round(r["mesh_ms"] * 1e3, 3),
                      "pair_kernel_us": round(r["pair_kernel_ms"] * 1e3, 3),
                      "t_kin": round(r["t_kin"], 2)}
         log(f"98k box with mesh, {name}: {out[name]}")
     for name, *_ in runs[1:]:
-        if "ms_per_step" in out[name] and "ms_per_step" in out["baoab"]:
-            out[name]["speedup_vs_baoab"] = round(out["baoab"]["ms_per_step"] /
-                                                  out[name]["ms_per_step"], 4)
+        if "ns_per_day" in out[name] and "ns_per_day" in out["baoab"]:
+            out[name]["speedup_vs_baoab"] = round(out[name]["ns_per_day"] / out["baoab"]["ns_per_day"], 4)
     return out
 
 
