@@ -71,12 +71,13 @@ __device__ __forceinline__ const double4 *pme_mirror(const ListSet &ls, const Pm
 // the brick).  They come from the list cells that overlap that slab widened by
 // the skin margin (an atom is at most s/2 from the cell it was listed in);
 // the atoms of a (c0, c1) row of cells are contiguous in sorted order, the
-// rows' runs are laid end to end, and the workgroup's threads take BT
+// rows' runs are laid end to end, and the workgroup's NT threads take NT
 // candidates at a time, so their loads are all in flight together.
 constexpr int SB = 8;
-constexpr int BT = 256;               // threads of a brick workgroup
+constexpr int ST = 512;               // threads of a spread workgroup
+constexpr int GT = 256;               // threads of a gather workgroup
 constexpr int BROWS = 256;            // cell rows per batch (one per thread)
-constexpr int BNW = BT / 64;
+constexpr int MAXNW = ST / 64;
 
 struct Brick {
     int B[3], P[3];
@@ -96,13 +97,13 @@ __device__ __forceinline__ Brick brick_of(const PmeArgs &pa, int64_t bid)
 
 struct WalkLds {
     int32_t seg_s[2 * BROWS], seg_p[2 * BROWS];
-    int wsum[BNW];
+    int wsum[MAXNW];
 };
 
 // body(s) for each candidate (s = its sorted slot, or -1 for a thread without
-// one), BT per call; every thread of the workgroup makes the same calls, so
+// one), NT per call; every thread of the workgroup makes the same calls, so
 // body may synchronise the workgroup.
-template <class F>
+template <int NT, class F>
 __device__ __forceinline__ void walk_candidates(const ListSet &ls, const PmeArgs &pa, const Brick &bk, int hi,
                                                 WalkLds &wl, F &&body)
 {
@@ -155,7 +156,7 @@ __device__ __forceinline__ void walk_candidates(const ListSet &ls, const PmeArgs
         __syncthreads();
         int off = 0, total = 0;
 #pragma unroll
-        for (int w = 0; w < BNW; ++w) {
+        for (int w = 0; w < NT / 64; ++w) {
             off += w < wv ? wl.wsum[w] : 0;
             total += wl.wsum[w];
         }
@@ -167,7 +168,7 @@ __device__ __forceinline__ void walk_candidates(const ListSet &ls, const PmeArgs
             wl.seg_p[2 * tid + 1] = excl + len0;
         }
         __syncthreads();
-        for (int cb = 0; cb < total; cb += BT) {
+        for (int cb = 0; cb < total; cb += NT) {
             const int idx = cb + tid;
             int32_t s = -1;
             if (idx < total) {
@@ -188,6 +189,7 @@ __device__ __forceinline__ void walk_candidates(const ListSet &ls, const PmeArgs
 
 // compaction of the threads with flag set: returns this thread's slot (if
 // flag) and the workgroup's count; synchronises the workgroup
+template <int NT>
 __device__ __forceinline__ int compact_slot(bool flag, int *wq, int &count)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -197,7 +199,7 @@ __device__ __forceinline__ int compact_slot(bool flag, int *wq, int &count)
     int off = 0;
     count = 0;
 #pragma unroll
-    for (int w = 0; w < BNW; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         off += w < wv ? wq[w] : 0;
         count += wq[w];
     }
@@ -247,21 +249,21 @@ __device__ __forceinline__ long long round_small(double v)
 // banks.  The brick is then stored with plain writes (imaginary part 0), each
 // mesh point by the one workgroup that owns it.
 template <int NO>
-__global__ void __launch_bounds__(BT) k_pme_spread(PmeArgs pa, ListSet ls, PmeAtoms pm, int32_t n,
+__global__ void __launch_bounds__(ST) k_pme_spread(PmeArgs pa, ListSet ls, PmeAtoms pm, int32_t n,
                                                    double2 *__restrict__ grid)
 {
     constexpr int RS = SB + 1;
     __shared__ unsigned long long acc[SB * SB * RS];
     __shared__ WalkLds wl;
-    __shared__ double qw[BT][3 * NO];
-    __shared__ int qr[BT][3];
-    __shared__ int qm[BT];
-    __shared__ int wq[BNW];
+    __shared__ double qw[ST][3 * NO];
+    __shared__ int qr[ST][3];
+    __shared__ int qm[ST];
+    __shared__ int wq[ST / 64];
     const int tid = threadIdx.x;
     const Brick bk = brick_of(pa, blockIdx.x);
-    for (int k = tid; k < SB * SB * RS; k += BT) acc[k] = 0ull;
+    for (int k = tid; k < SB * SB * RS; k += ST) acc[k] = 0ull;
     __syncthreads();
-    walk_candidates(ls, pa, bk, NO - 1, wl, [&](int32_t s) {
+    walk_candidates<ST>(ls, pa, bk, NO - 1, wl, [&](int32_t s) {
         bool touch = false;
         int r[3] = {0, 0, 0}, m[3] = {0, 0, 0};
         if (s >= 0) {
@@ -285,7 +287,7 @@ __global__ void __launch_bounds__(BT) k_pme_spread(PmeArgs pa, ListSet ls, PmeAt
             }
         }
         int nq;
-        const int slot = compact_slot(touch, wq, nq);
+        const int slot = compact_slot<ST>(touch, wq, nq);
         if (touch) {
 #pragma unroll
             for (int k = 0; k < 3 * NO; ++k) qw[slot][k] = pm.w[(int64_t)k * n + s];
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(BT) k_pme_spread(PmeArgs pa, ListSet ls, PmeAt
             qm[slot] = m[0] | (m[1] << 8) | (m[2] << 16);
         }
         __syncthreads();
-        for (int it = tid; it < nq * NO * NO; it += BT) {
+        for (int it = tid; it < nq * NO * NO; it += ST) {
             const int e = it / (NO * NO), j0 = (it / NO) % NO, j1 = it % NO;
             const int mk = qm[e];
             if (!((mk >> j0) & 1) || !((mk >> (8 + j1)) & 1)) continue;
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(BT) k_pme_spread(PmeArgs pa, ListSet ls, PmeAt
         __syncthreads();
     });
     const int nbrick = bk.B[0] * bk.B[1] * bk.B[2];
-    for (int k = tid; k < nbrick; k += BT) {
+    for (int k = tid; k < nbrick; k += ST) {
         const int t2 = k % bk.B[2], t1 = (k / bk.B[2]) % bk.B[1], t0 = k / (bk.B[1] * bk.B[2]);
         const int64_t g = ((int64_t)(bk.P[0] + t0) * pa.K[1] + (bk.P[1] + t1)) * pa.K[2] + (bk.P[2] + t2);
         grid[g] = make_double2((double)(long long)acc[(t0 * SB + t1) * RS + t2] * pa.inv_qscale, 0.0);
@@ -429,7 +431,7 @@ int64_t pme_energy_parts(const PmeArgs &pa)
 // atoms whose floor(u) lies in the workgroup's brick (each atom has one such
 // brick).  The brick and the n - 1 mesh points below it on every axis (the
 // points its atoms' stencils reach) are staged in LDS; owned candidates are
-// queued and taken BT at a time, one thread per atom.  out[s] (sorted order)
+// queued and taken GT at a time, one thread per atom.  out[s] (sorted order)
 // or out[g] (caller order).
 template <int NO>
 __device__ __forceinline__ void gather_atom(int32_t s, const double4 *X, const PmeAtoms &pm, const ListSet &ls,
@@ -497,7 +499,7 @@ __device__ __forceinline__ void gather_atom(int32_t s, const double4 *X, const P
 }
 
 template <int NO>
-__global__ void __launch_bounds__(BT) k_pme_gather(ListSet ls, const double *__restrict__ pos,
+__global__ void __launch_bounds__(GT) k_pme_gather(ListSet ls, const double *__restrict__ pos,
                                                    const double *__restrict__ charge, Topo tp, PmeArgs pa,
                                                    PmeAtoms pm, const double2 *__restrict__ grid,
                                                    double *__restrict__ out, int32_t out_global, int32_t accumulate)
@@ -505,13 +507,13 @@ __global__ void __launch_bounds__(BT) k_pme_gather(ListSet ls, const double *__r
     constexpr int E = SB + NO - 1;
     __shared__ double ph[E * E * E];
     __shared__ WalkLds wl;
-    __shared__ int32_t own[2 * BT];
-    __shared__ int wq[BNW];
+    __shared__ int32_t own[2 * GT];
+    __shared__ int wq[GT / 64];
     const int tid = threadIdx.x;
     const Brick bk = brick_of(pa, blockIdx.x);
     const int E0 = bk.B[0] + NO - 1, E1 = bk.B[1] + NO - 1, E2 = bk.B[2] + NO - 1;
     // local a_c <-> mesh point (P_c - (n - 1) + a_c) mod K_c
-    for (int k = tid; k < E0 * E1 * E2; k += BT) {
+    for (int k = tid; k < E0 * E1 * E2; k += GT) {
         const int a2 = k % E2, a1 = (k / E2) % E1, a0 = k / (E1 * E2);
         int l[3] = {bk.P[0] - (NO - 1) + a0, bk.P[1] - (NO - 1) + a1, bk.P[2] - (NO - 1) + a2};
 #pragma unroll
@@ -524,7 +526,7 @@ __global__ void __launch_bounds__(BT) k_pme_gather(ListSet ls, const double *__r
     __syncthreads();
     const double4 *X = pme_mirror(ls, pa);
     int queued = 0;                       // uniform: owned atoms waiting in own[]
-    walk_candidates(ls, pa, bk, 0, wl, [&](int32_t s) {
+    walk_candidates<GT>(ls, pa, bk, 0, wl, [&](int32_t s) {
         bool mine = false;
         if (s >= 0) {
             const int4 fq = pm.fl[s];
@@ -538,14 +540,14 @@ __global__ void __launch_bounds__(BT) k_pme_gather(ListSet ls, const double *__r
             }
         }
         int nq;
-        const int slot = compact_slot(mine, wq, nq);
+        const int slot = compact_slot<GT>(mine, wq, nq);
         if (mine) own[queued + slot] = s;
         queued += nq;
         __syncthreads();
-        if (queued >= BT) {               // a full round: every thread takes one atom
+        if (queued >= GT) {               // a full round: every thread takes one atom
             gather_atom<NO>(own[tid], X, pm, ls, pos, charge, tp, pa, bk, ph, out, out_global, accumulate);
-            const int rest = queued - BT;
-            const int moved = tid < rest ? own[BT + tid] : 0;
+            const int rest = queued - GT;
+            const int moved = tid < rest ? own[GT + tid] : 0;
             __syncthreads();
             if (tid < rest) own[tid] = moved;
             queued = rest;
@@ -563,7 +565,7 @@ void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos,
     if (n <= 0) return;
     int64_t nbricks = 1;
     for (int c = 0; c < 3; ++c) nbricks *= pa.K[c] / (pa.K[c] < SB ? pa.K[c] : SB);
-    const dim3 gs((unsigned)nbricks), bs(BT), gp((n + 255) / 256), bp(256);
+    const dim3 gs((unsigned)nbricks), bs(ST), bg(GT), gp((n + 255) / 256), bp(256);
     switch (pa.order) {
         case 4:
             hipLaunchKernelGGL(k_pme_prep<4>, gp, bp, 0, sm, n, ls, charge, pa, pm);
@@ -594,11 +596,11 @@ void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos,
     fft(1, -1.0, nullptr, nullptr, 0);
     fft(0, -1.0, nullptr, nullptr, 0);
     switch (pa.order) {
-        case 4: hipLaunchKernelGGL(k_pme_gather<4>, gs, bs, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        case 4: hipLaunchKernelGGL(k_pme_gather<4>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                    out_global, accumulate); break;
-        case 6: hipLaunchKernelGGL(k_pme_gather<6>, gs, bs, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        case 6: hipLaunchKernelGGL(k_pme_gather<6>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                    out_global, accumulate); break;
-        default: hipLaunchKernelGGL(k_pme_gather<5>, gs, bs, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        default: hipLaunchKernelGGL(k_pme_gather<5>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                     out_global, accumulate); break;
     }
 }
