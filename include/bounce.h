@@ -174,7 +174,10 @@ bounce_status bounce_sync(bounce_ctx *ctx);
 
 /* Gradient dE/dq of the selected parts at the current positions into grad_dev
    ([N][3] float64, caller order): BONDED, SHORT = sum_j (1-chi) W'_sf d/r (r<r''),
-   LONG = sum_j chi W'_sf d/r (r'<r<rc), FULL = sum_j W'_sf d/r (r<rc).  Synchronous. */
+   LONG = sum_j chi W'_sf d/r (r'<r<rc), FULL = sum_j W'_sf d/r (r<rc), RECIP =
+   the smooth-PME reciprocal-space gradient plus that of the excluded pairs'
+   -k_e q_i q_j erf(alpha r)/r (Sec. V; needs pme_grid, else BOUNCE_E_ARG).
+   Synchronous. */
 bounce_status bounce_compute_gradient(bounce_ctx *ctx, int32_t which, double *grad_dev);
 /* Energies of every replica into out_host[n_replicas][7]:
    E_bond, E_angle, E_coul, E_lj, E_pair (= coul + lj, shifted force, r < rc),

@@ -79,10 +79,11 @@ def test_mesh_converges_to_plain_sum(orc):
     assert errs[0] > errs[1] > errs[2]
 
 
-def test_gradient_matches_finite_differences(orc):
+@pytest.mark.parametrize("order", [4, 5, 6])
+def test_gradient_matches_finite_differences(orc, order):
     from workloads import water_box
     s = water_box(n_side=4, box_len=12.4, seed=5)
-    p = orc.make_params(s, ewald_alpha=0.45, pme_grid=[24, 24, 24], pme_order=5)
+    p = orc.make_params(s, ewald_alpha=0.45, pme_grid=[24, 24, 24], pme_order=order)
     topo = orc.Topology.from_system(s)
     (_, _, ex), g = orc.pme(p, topo, s.pos)
     assert ex > 0.0        # removes the attraction of the excluded O-H pairs (net of H-H)
