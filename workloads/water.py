@@ -152,12 +152,17 @@ def maxwell_velocities(mass, temperature, seed, stream=3):
     return rng.standard_normal((mass.shape[0], 3)) * sd[:, None]
 
 
-def water_box(n_side=20, box_len=62.0, temperature=300.0, seed=0, cell_size=3.8):
-    """Periodic cube of n_side^3 waters on a lattice (the 24,000-atom box is n_side=20)."""
+def water_box(n_side=20, box_len=62.0, temperature=300.0, seed=0, cell_size=3.8, remove=0):
+    """Periodic cube of n_side^3 waters on a lattice (the 24,000-atom box is n_side=20);
+    remove > 0 drops that many lattice sites, chosen by a Philox stream of their
+    own (the 96,000-atom box is n_side=32, 98 A, remove=768)."""
     rng = _rng(seed, 4)
     spacing = box_len / n_side
     g = (np.arange(n_side) + 0.5) * spacing
     sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    if remove > 0:
+        drop = _rng(seed, 7).permutation(sites.shape[0])[:int(remove)]
+        sites = np.delete(sites, drop, axis=0)
     box = np.full(3, float(box_len))
     pos = _place_waters(sites, rng, box=box)
     topo = _topology(sites.shape[0])
