@@ -424,6 +424,20 @@ def main():
         res[name] = run_gpu(args, system, ff, integ, state, rate_mode=rm)
         log(f"{name}: {res[name]['ms_per_step']:.4f} ms/step, step kernel "
             f"{res[name]['step_kernel_ms']*1e3:.1f} us, T_kin {res[name]['t_kin']:.1f} K")
+    # BOUNCE-RESPA (Sec. V) on the same box: bonded terms and jumps on the inner
+    # step, the short-range pair force on an outer step of 2 fs; the same
+    # simulated time as the runs above
+    respa = {}
+    for name, dt, m in (("1/2 fs", 1.0, 2), ("0.5/2 fs", 0.5, 4)):
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = int(round(args.steps / dt)), int(round(args.warmup / dt))
+        log(f"timing BOUNCE-RESPA {name}: {sub.warmup} warmup + {sub.steps} steps")
+        r = run_gpu(sub, system, ff, B.BJAOAJB, state, rate_mode=mode, dt=dt,
+                    rebuild=int(round(args.rebuild / dt)), respa_m=m, respa_outer=B.OUTER_NONBONDED)
+        respa[name] = {"ms_per_step": round(r["ms_per_step"], 5), "dt_fs": dt, "respa_m": m,
+                       "ns_per_day": round(dt * 1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
+                       "t_kin_K": round(r["t_kin"], 2)}
+        log(f"BOUNCE-RESPA {name}: {respa[name]}")
 
     box = system.box
     bo, ba = res["bounce"], res["baoab"]
@@ -486,6 +500,8 @@ def main():
                   "pair_lanes": ba["lanes"], "autotune_ms": ba["tune_ms"],
                   "t_kin_K": round(ba["t_kin"], 2), "e_pot": round(ba["e_pot"], 2)},
         "speedup_vs_baoab": round(ba["ms_per_step"] / bo["ms_per_step"], 4),
+        "bounce_respa_nonbonded": {k: dict(v, speedup_vs_baoab=round(v["ns_per_day"] / ns_day(ba["ms_per_step"]), 4))
+                                   for k, v in respa.items()},
         "roofline": {"kernel": "F_0 pair kernel (BOUNCE short range)", "bound": "alu",
                      "achieved": round(achieved, 4), "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32, 5),
