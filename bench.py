@@ -220,7 +220,8 @@ def structure_summary(counts, n_samples, n_o, volume):
 
 
 def run_accuracy(args, system, ff, state):
-    """<T_kin> and <E_pot> per water of BOUNCE and BAOAB at 1 fs against BAOAB at
+    """<T_kin> and <E_pot> per water of BOUNCE and BAOAB at 1 fs and of BOUNCE-RESPA
+    (1 fs inner, short-range pair force on a 2 fs outer step) against BAOAB at
     0.25 fs (the reference), each over args.accuracy ps from the same state,
     sampled every 100 fs; errors are block standard errors (10 blocks).  Also
     the O-O radial distribution (first peak, coordination) accumulated over the
@@ -230,13 +231,17 @@ def run_accuracy(args, system, ff, state):
     out = {}
     n_o = int((system.atom_type == 0).sum())
     volume = float(np.prod(system.box))
-    for name, integ, dt in (("bounce_1fs", B.BJAOAJB, 1.0), ("baoab_1fs", B.BAOAB, 1.0),
-                            ("baoab_0.25fs", B.BAOAB, 0.25)):
+    # (name, integrator, inner dt, RESPA outer step in inner steps: the
+    # short-range pair force on it; 0 = none)
+    for name, integ, dt, m in (("bounce_1fs", B.BJAOAJB, 1.0, 0), ("baoab_1fs", B.BAOAB, 1.0, 0),
+                               ("bounce_respa_1_2fs", B.BJAOAJB, 1.0, 2),
+                               ("baoab_0.25fs", B.BAOAB, 0.25, 0)):
         p = B.make_params(integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
                           periodic=1, dt=dt, gamma=1e-3, temperature=300.0, r_on=args.r_on,
                           r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
                           rebuild_interval=args.rebuild if dt == 1.0 else 4 * args.rebuild,
-                          seed=7, cell_size=system.cell_size, use_graph=1)
+                          seed=7, cell_size=system.cell_size, use_graph=1, respa_m=m,
+                          respa_outer=B.OUTER_NONBONDED if m else B.OUTER_RECIP)
         sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
         sim.set_state(pos=state[0], vel=state[1], step=0)
         per = int(round(100.0 / dt))
