@@ -147,3 +147,21 @@ def test_outer_nonbonded_graph_replay_is_bit_exact(box):
         sim.sync()
     assert np.array_equal(sa.pos.cpu().numpy(), sb.pos.cpu().numpy())
     assert np.array_equal(sa.vel.cpu().numpy(), sb.vel.cpu().numpy())
+
+
+@pytest.mark.parametrize("respa_outer", [0, 1])
+def test_mesh_timing_leaves_the_trajectory(box, respa_outer):
+    """Timing the mesh sum (it writes the outer-gradient buffer) between steps,
+    also in the middle of an outer step, changes nothing: every outer kick
+    recomputes that buffer first."""
+    cfg = dict(MESH, respa_m=5, respa_outer=respa_outer)
+    a = gpu_sim(box, cfg, fp64=False, use_graph=True)
+    b = gpu_sim(box, cfg, fp64=False, use_graph=True)
+    a.step(23)
+    for k in (7, 9, 7):
+        b.step(k)
+        b.profile_kernel(4, 3)
+    for s in (a, b):
+        s.sync()
+    assert np.array_equal(a.pos.cpu().numpy(), b.pos.cpu().numpy())
+    assert np.array_equal(a.vel.cpu().numpy(), b.vel.cpu().numpy())
