@@ -73,21 +73,23 @@ __device__ __forceinline__ const double4 *pme_mirror(const ListSet &ls, const Pm
 // the atoms of a (c0, c1) row of cells are contiguous in sorted order, the
 // rows' runs are laid end to end, and the workgroup's NT threads take NT
 // candidates at a time, so their loads are all in flight together.
-constexpr int SB = 8;
+constexpr int SB = 8;                 // brick edge of the spread
+constexpr int GB = 8;                 // brick edge of the gather
 constexpr int ST = 512;               // threads of a spread workgroup
 constexpr int GT = 256;               // threads of a gather workgroup
-constexpr int BROWS = 256;            // cell rows per batch (one per thread)
+constexpr int BROWS = 256;            // most cell rows per batch (one per thread)
 constexpr int MAXNW = ST / 64;
 
 struct Brick {
     int B[3], P[3];
 };
 
+template <int BE>
 __device__ __forceinline__ Brick brick_of(const PmeArgs &pa, int64_t bid)
 {
     Brick bk;
     for (int c = 2; c >= 0; --c) {
-        bk.B[c] = pa.K[c] < SB ? pa.K[c] : SB;
+        bk.B[c] = pa.K[c] < BE ? pa.K[c] : BE;
         const int nb = pa.K[c] / bk.B[c];
         bk.P[c] = (int)(bid % nb) * bk.B[c];
         bid /= nb;
@@ -129,8 +131,9 @@ __device__ __forceinline__ void walk_candidates(const ListSet &ls, const PmeArgs
     }
     const int nrow = cnt[0] * cnt[1];
     const int n2 = pa.ncell[2];
-    for (int rb = 0; rb < nrow; rb += BROWS) {
-        const int nr = nrow - rb < BROWS ? nrow - rb : BROWS;
+    constexpr int ROWS = NT < BROWS ? NT : BROWS;
+    for (int rb = 0; rb < nrow; rb += ROWS) {
+        const int nr = nrow - rb < ROWS ? nrow - rb : ROWS;
         // this thread's row: the run of cells lo2 .. up to the row's end, then the wrapped part
         int32_t s0 = 0, s1 = 0, len0 = 0, len1 = 0;
         if (tid < nr) {
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(ST) k_pme_spread(PmeArgs pa, ListSet ls, PmeAt
     __shared__ int qm[ST];
     __shared__ int wq[ST / 64];
     const int tid = threadIdx.x;
-    const Brick bk = brick_of(pa, blockIdx.x);
+    const Brick bk = brick_of<SB>(pa, blockIdx.x);
     for (int k = tid; k < SB * SB * RS; k += ST) acc[k] = 0ull;
     __syncthreads();
     walk_candidates<ST>(ls, pa, bk, NO - 1, wl, [&](int32_t s) {
@@ -504,13 +507,13 @@ __global__ void __launch_bounds__(GT) k_pme_gather(ListSet ls, const double *__r
                                                    PmeAtoms pm, const double2 *__restrict__ grid,
                                                    double *__restrict__ out, int32_t out_global, int32_t accumulate)
 {
-    constexpr int E = SB + NO - 1;
+    constexpr int E = GB + NO - 1;
     __shared__ double ph[E * E * E];
     __shared__ WalkLds wl;
     __shared__ int32_t own[2 * GT];
     __shared__ int wq[GT / 64];
     const int tid = threadIdx.x;
-    const Brick bk = brick_of(pa, blockIdx.x);
+    const Brick bk = brick_of<GB>(pa, blockIdx.x);
     const int E0 = bk.B[0] + NO - 1, E1 = bk.B[1] + NO - 1, E2 = bk.B[2] + NO - 1;
     // local a_c <-> mesh point (P_c - (n - 1) + a_c) mod K_c
     for (int k = tid; k < E0 * E1 * E2; k += GT) {
@@ -563,9 +566,12 @@ void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos,
                 double *out, int32_t out_global, int32_t accumulate, double *energy_parts)
 {
     if (n <= 0) return;
-    int64_t nbricks = 1;
-    for (int c = 0; c < 3; ++c) nbricks *= pa.K[c] / (pa.K[c] < SB ? pa.K[c] : SB);
-    const dim3 gs((unsigned)nbricks), bs(ST), bg(GT), gp((n + 255) / 256), bp(256);
+    int64_t nbricks = 1, gbricks = 1;
+    for (int c = 0; c < 3; ++c) {
+        nbricks *= pa.K[c] / (pa.K[c] < SB ? pa.K[c] : SB);
+        gbricks *= pa.K[c] / (pa.K[c] < GB ? pa.K[c] : GB);
+    }
+    const dim3 gs((unsigned)nbricks), bs(ST), gg((unsigned)gbricks), bg(GT), gp((n + 255) / 256), bp(256);
     switch (pa.order) {
         case 4:
             hipLaunchKernelGGL(k_pme_prep<4>, gp, bp, 0, sm, n, ls, charge, pa, pm);
@@ -596,11 +602,11 @@ void launch_pme(hipStream_t sm, int32_t n, const ListSet &ls, const double *pos,
     fft(1, -1.0, nullptr, nullptr, 0);
     fft(0, -1.0, nullptr, nullptr, 0);
     switch (pa.order) {
-        case 4: hipLaunchKernelGGL(k_pme_gather<4>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        case 4: hipLaunchKernelGGL(k_pme_gather<4>, gg, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                    out_global, accumulate); break;
-        case 6: hipLaunchKernelGGL(k_pme_gather<6>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        case 6: hipLaunchKernelGGL(k_pme_gather<6>, gg, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                    out_global, accumulate); break;
-        default: hipLaunchKernelGGL(k_pme_gather<5>, gs, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
+        default: hipLaunchKernelGGL(k_pme_gather<5>, gg, bg, 0, sm, ls, pos, charge, tp, pa, pm, grid, out,
                                     out_global, accumulate); break;
     }
 }
