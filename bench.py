@@ -399,8 +399,9 @@ def main():
                     help="also time the 96,000-atom box with smooth PME (BAOAB, BOUNCE, BOUNCE-RESPA)")
     ap.add_argument("--mesh-steps", type=int, default=500)
     ap.add_argument("--mesh-split", type=lambda t: tuple(float(v) for v in t.split(",")),
-                    default=(6.0, 7.0), metavar="R_ON,R_OFF",
-                    help="switching window r', r'' of the mesh workload (A)")
+                    default=(7.0, 8.0), metavar="R_ON,R_OFF",
+                    help="switching window r', r'' of the mesh workload (A); at its alpha = "
+                         "0.35/A the 6/7 A split runs away within 1,000 steps")
     ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
                     help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
                          "BAOAB at 0.25 fs over PS picoseconds each")
