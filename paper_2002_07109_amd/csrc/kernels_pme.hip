@@ -46,7 +46,8 @@ __device__ __forceinline__ void spline_weights(double f, double *w, double *dw)
 }
 
 // mesh coordinate of a position: u = K x / L with x wrapped into [0, L);
-// fl = floor(u) reduced into [0, K) (x may round up to L), f = u - floor(u)
+// fl = floor(u) reduced into [0, K) (the wrapped x may round to L or to just
+// below 0), f = u - floor(u)
 __device__ __forceinline__ void grid_coord(double x, double L, int K, int &fl, double &f)
 {
     const double xw = x - L * floor(x / L);
@@ -55,6 +56,7 @@ __device__ __forceinline__ void grid_coord(double x, double L, int K, int &fl, d
     f = u - flr;
     fl = (int)flr;
     if (fl >= K) fl -= K;
+    if (fl < 0) fl += K;
 }
 
 __device__ __forceinline__ const double4 *pme_mirror(const ListSet &ls, const PmeArgs &pa)
@@ -64,7 +66,8 @@ __device__ __forceinline__ const double4 *pme_mirror(const ListSet &ls, const Pm
 }
 
 // Owner-computes bricks.  The spread and the gather give each workgroup a
-// brick of SB^3 mesh points (fewer along an axis with K < SB), P <= l < P + B.
+// brick of mesh points, P <= l < P + B on every axis (B = SB for the spread,
+// GB for the gather, or K along an axis with fewer points).
 // The atoms a brick needs have u = K x / L in [P, P + B + hi) on every axis
 // (hi = n - 1 for the spread: an atom at u reaches the points floor(u) - j,
 // j < n; hi = 0 for the gather, which takes the atoms whose floor(u) lies in
