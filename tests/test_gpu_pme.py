@@ -165,3 +165,21 @@ def test_mesh_timing_leaves_the_trajectory(box, respa_outer):
         s.sync()
     assert np.array_equal(a.pos.cpu().numpy(), b.pos.cpu().numpy())
     assert np.array_equal(a.vel.cpu().numpy(), b.vel.cpu().numpy())
+
+
+def test_outer_nonbonded_replicas_match_independent_oracle_runs(orc):
+    """Several droplets in one context with the short-range pair force on the
+    outer step: each replica follows its own oracle run."""
+    cfg = dict(DROPLET, respa_m=2, respa_outer=1)
+    systems = [relaxed_droplet(name) for name in ("r0", "r1", "r2")]
+    sim = gpu_sim(systems, cfg, fp64=True, use_graph=True)
+    sim.step(30)
+    sim.sync()
+    pos = sim.pos.cpu().numpy()
+    for r, s in enumerate(systems):
+        o = orc.run(oracle_params(orc, s, cfg, replica=r), orc.Topology.from_system(s), s.pos, s.vel,
+                    0, 30)
+        assert o["status"] == 0, o["status_name"]
+        b, e = sim.offsets[r], sim.offsets[r + 1]
+        assert np.abs(pos[b:e] - o["q"]).max() <= 1e-6
+        assert sim.counters(r)["proposals"] == o["counters"]["proposals"]
