@@ -184,3 +184,23 @@ def test_outer_nonbonded_conserves_energy(orc, with_mesh):
     e1 = orc.energies(p, topo, o["q"], o["v"])
     tot = lambda e: e["bond"] + e["angle"] + e["pair"] + e["kin"]
     assert abs(tot(e1) - tot(e0)) < 2e-3 * e0["kin"], (tot(e1) - tot(e0), e0["kin"])
+
+
+def test_mesh_outer_step_of_one_is_the_mesh_in_f0(orc):
+    """The mesh force on an outer step of m = 1 (half kicks of dt/2 around every
+    step) equals the mesh force in F_0 (the basic scheme) up to rounding, with
+    the same jump events."""
+    from helpers import relaxed_box
+    s = relaxed_box("b8")
+    topo = orc.Topology.from_system(s)
+    kw = dict(integrator=orc.BOUNCE, dt=1.0, ewald_alpha=0.45, r_on=6.0, r_off=7.0, r_cut=9.0,
+              skin=2.0, pme_grid=[16, 16, 16], pme_order=4)
+    f0 = orc.run(orc.make_params(s, respa_m=0, **kw), topo, s.pos, s.vel, 0, 20, ev_cap=200000)
+    one = orc.run(orc.make_params(s, respa_m=1, **kw), topo, s.pos, s.vel, 0, 20, ev_cap=200000)
+    for o in (f0, one):
+        assert o["status"] == 0, o["status_name"]
+    assert f0["n_events"] > 0
+    assert np.abs(one["q"] - f0["q"]).max() < 1e-9
+    assert np.abs(one["v"] - f0["v"]).max() < 1e-9
+    key = lambda e: sorted(zip(e["step"], e["phase"], e["atom"], e["k"], e["partner"], e["accepted"]))
+    assert key(one["events"]) == key(f0["events"])
