@@ -20,7 +20,7 @@ def box():
 
 
 @pytest.mark.parametrize("order,grid", [(4, (32, 32, 32)), (5, (32, 32, 32)), (6, (32, 32, 32)),
-                                        (5, (16, 32, 64))])
+                                        (5, (16, 32, 64)), (4, (8, 8, 8)), (6, (8, 16, 8))])
 def test_mesh_energy_and_gradient(orc, box, order, grid):
     import paper_2002_07109_amd as B
     cfg = dict(MESH, pme_order=order, pme_grid=grid)
