@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic FP32 operations per evaluated pair (adds, multiplies, each half of
-# an FMA, and each transcendental counted once): see the design doc
+# an FMA, and each transcendental counted once): r^2 5, rsqrt 1, r 1; Coulomb
+# alpha r 1, erfc 1, exp(-(alpha r)^2) 2, g 1, g' 3; Lennard-Jones 10;
+# W' = qq g' + LJ' - u'(rc) 3; switch 9; (1 - chi) W'/r 3; accumulation 6
 FLOPS_SHORT = 46     # (1 - chi) W'_sf d/r: distance, rsqrt, erfc + exp Coulomb, LJ, switch, accumulate
 FLOPS_FULL = 36      # W'_sf d/r without the switch
 PEAK_FP32 = 157.3    # TFLOP/s, MI355X vector FP32 (published)
@@ -409,8 +411,8 @@ def main():
                     help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); no multi-GPU "
+              "decomposition is built.", file=sys.stderr)
         sys.exit(2)
 
     from workloads import tip3p_params, water_box

@@ -122,7 +122,7 @@ def test_c4_direct_energy_autograd(orc, c1, seed, fp64):
     rms = np.sqrt(np.mean(np.sum(ogq * ogq, 1)))
     assert np.max(np.linalg.norm(gq - ogq, axis=1)) / rms < tol
     gp = par.grad.cpu().numpy()
-    # judged parameters: charge_O, charge_H, eps_O, sigma_O (eps_H = 0: d/deps_H undefined)
+    # checked parameters: charge_O, charge_H, eps_O, sigma_O (eps_H = 0: d/deps_H undefined)
     for k, ref in [(0, ogc[0]), (1, ogc[1]), (2, oge[0]), (4, ogs[0])]:
         assert gp[k] == pytest.approx(ref, rel=10 * tol), k
 
