@@ -111,7 +111,8 @@ def test_mesh_needs_one_periodic_replica(box):
         gpu_sim([box, box], MESH)
 
 
-@pytest.mark.parametrize("case", ["box_mesh_m2", "box_mesh_m5", "box_m2", "drop_m2", "box_baoab_m5"])
+@pytest.mark.parametrize("case", ["box_mesh_m2", "box_mesh_m5", "box_m2", "drop_m2", "box_baoab_m5",
+                                  "box_mesh_m2_pairbounds"])
 def test_trajectory_with_outer_nonbonded(orc, box, case):
     """BOUNCE-RESPA with the short-range pair force (and the mesh force) on the
     outer step (Sec. V): FP64 trajectory and jump events against the oracle."""
@@ -122,6 +123,8 @@ def test_trajectory_with_outer_nonbonded(orc, box, case):
     cfg.update(respa_outer=1, respa_m=5 if case.endswith("m5") else 2)
     if "baoab" in case:
         cfg["integrator"] = 1
+    if "pairbounds" in case:
+        cfg["rate_mode"] = 1
     nsteps = 60
     sim = gpu_sim(sys, cfg, fp64=True, log_events=True, event_capacity=4_000_000)
     sim.step(nsteps)
