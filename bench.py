@@ -32,6 +32,9 @@ sys.path.insert(0, ROOT)
 FLOPS_SHORT = 46     # (1 - chi) W'_sf d/r: distance, rsqrt, erfc + exp Coulomb, LJ, switch, accumulate
 FLOPS_FULL = 36      # W'_sf d/r without the switch
 PEAK_FP32 = 157.3    # TFLOP/s, MI355X vector FP32 (published)
+# transcendentals per pair among the counted operations (rsqrt, erfc, exp); the
+# op-mix bound issues them at a quarter of the unpacked FP32 rate
+TRANSC_PER_PAIR = 3
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_short_24k_box_traffic.md")
@@ -128,7 +131,7 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
                pair_kernel_ms=pair_ms, build_ms=build_ms, step_kernel_ms=step_ms, t_kin=e["tkin"],
                lanes=lanes, tune_ms={k: round(v, 5) for k, v in tune.items()},
                e_pot=e["pair"] + e["bond"] + e["angle"], mesh_ms=mesh_ms,
-               pos=sim.pos.cpu().numpy())
+               pos=sim.pos.cpu().numpy(), list_slots=sim.list_size(B.LIST_FORCE))
     sim.close()
     return out
 
@@ -459,6 +462,8 @@ def main():
     achieved = short_pairs * FLOPS_SHORT / (bo["pair_kernel_ms"] * 1e-3) / 1e12
     achieved_ba = full_pairs_ba * FLOPS_FULL / (ba["pair_kernel_ms"] * 1e-3) / 1e12
     traffic = measured_traffic(bo["lanes"])
+    # unpacked FP32 with the transcendentals at a quarter rate
+    peak_opmix = (PEAK_FP32 / 2) * FLOPS_SHORT / ((FLOPS_SHORT - TRANSC_PER_PAIR) + 4 * TRANSC_PER_PAIR)
     line = {
         "metric": "ns/day & pair-evals/s, BOUNCE vs BAOAB 1fs on same GPU, 24k-atom box",
         "value": round(ns_day(bo["ms_per_step"]), 3),
@@ -480,6 +485,7 @@ def main():
         "bounce": {"ns_per_day": round(ns_day(bo["ms_per_step"]), 3),
                    "ms_per_step": round(bo["ms_per_step"], 5),
                    "pair_evals_per_s": (short_pairs + bo["proposals_per_step"]) * steps_s_bo,
+                   "pair_slots_per_s": bo["list_slots"] * steps_s_bo,
                    "baoab_equivalent_pair_evals_per_s": full_pairs_bo * steps_s_bo,
                    "short_pairs_per_step": short_pairs,
                    "proposals_per_step": bo["proposals_per_step"],
@@ -500,6 +506,7 @@ def main():
         "baoab": {"ns_per_day": round(ns_day(ba["ms_per_step"]), 3),
                   "ms_per_step": round(ba["ms_per_step"], 5),
                   "pair_evals_per_s": full_pairs_ba * steps_s_ba,
+                  "pair_slots_per_s": ba["list_slots"] * steps_s_ba,
                   "pairs_per_step": full_pairs_ba,
                   "step_kernel_us": round(ba["step_kernel_ms"] * 1e3, 3),
                   "pair_kernel_us": round(ba["pair_kernel_ms"] * 1e3, 3),
@@ -517,6 +524,10 @@ def main():
                      "flops_per_pair": FLOPS_SHORT, "pairs_per_launch": short_pairs,
                      "peak_unpacked": PEAK_FP32 / 2,
                      "frac_unpacked": round(achieved / (PEAK_FP32 / 2), 5),
+                     "peak_opmix": round(peak_opmix, 3),
+                     "frac_opmix": round(achieved / peak_opmix, 5),
+                     "pair_slots_per_launch": bo["list_slots"],
+                     "useful_pairs_per_slot": round(short_pairs / bo["list_slots"], 4),
                      "hbm_frac": (round(traffic / (bo["pair_kernel_ms"] * 1e-3) / 8e12, 4)
                                   if traffic else None)},
     }

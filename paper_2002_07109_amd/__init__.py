@@ -216,6 +216,13 @@ class Simulation:
                   self.ctx, "bounce_get_list")
         return rp, col[:int(rp[-1])]
 
+    def list_size(self, which):
+        """Entries of a list set's rows (LIST_FORCE: the pair kernel's slots per launch)."""
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(1, np.int32)
+        self.L.bounce_get_list(self.ctx, int(which), _ptr(rp), _ptr(col), 1)   # sizes only
+        return int(rp[-1])
+
     def rate_bounds(self):
         nt = self.n_types
         lab, la = np.zeros(nt * nt), np.zeros(nt)
