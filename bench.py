@@ -124,6 +124,9 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
     build_ms = sim.profile_kernel(1, 10)
     mesh_ms = sim.profile_kernel(4, 20) if mesh.get("pme_grid") else None
     e = sim.energies()[0]
+    t_e = time.perf_counter()
+    sim.energies()                             # the energy pass, timed on its own
+    energy_ms = 1e3 * (time.perf_counter() - t_e)
     step_ms = sim.profile_kernel(3, 50)        # advances the state: taken last
     out = dict(wall_s=wall, gpu_ms=gpu_ms, ms_per_step=1e3 * wall / args.steps,
                proposals_per_step=(c1["proposals"] - c0["proposals"]) / args.steps,
@@ -131,7 +134,7 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
                pair_kernel_ms=pair_ms, build_ms=build_ms, step_kernel_ms=step_ms, t_kin=e["tkin"],
                lanes=lanes, tune_ms={k: round(v, 5) for k, v in tune.items()},
                e_pot=e["pair"] + e["bond"] + e["angle"], mesh_ms=mesh_ms,
-               pos=sim.pos.cpu().numpy(), list_slots=sim.list_size(B.LIST_FORCE))
+               pos=sim.pos.cpu().numpy(), list_slots=sim.list_size(B.LIST_FORCE), energy_ms=energy_ms)
     sim.close()
     return out
 
@@ -274,6 +277,13 @@ def run_accuracy(args, system, ff, state):
         res["d_o_1e-5_cm2_s"] = round(float(slope / 6.0 * 1e4), 3)
         out[name] = res
         log(f"accuracy {name}: {res}")
+    # matched accuracy: |X - X_ref| <= |X_BAOAB - X_ref| + 2 sigma (sigma of X)
+    ref, ba = out["baoab_0.25fs"], out["baoab_1fs"]
+    for name in ("bounce_1fs", "bounce_respa_1_2fs"):
+        out[name]["matched"] = {
+            key: bool(abs(out[name][key][0] - ref[key][0]) <= abs(ba[key][0] - ref[key][0]) +
+                      2.0 * out[name][key][1])
+            for key in ("t_kin_K", "e_pot_per_water")}
     return out
 
 
@@ -486,6 +496,7 @@ def main():
                    "ms_per_step": round(bo["ms_per_step"], 5),
                    "pair_evals_per_s": (short_pairs + bo["proposals_per_step"]) * steps_s_bo,
                    "pair_slots_per_s": bo["list_slots"] * steps_s_bo,
+                   "energy_pass_ms": round(bo["energy_ms"], 4),
                    "baoab_equivalent_pair_evals_per_s": full_pairs_bo * steps_s_bo,
                    "short_pairs_per_step": short_pairs,
                    "proposals_per_step": bo["proposals_per_step"],
