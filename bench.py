@@ -304,9 +304,16 @@ def run_big(args, ff):
                        "model and settings as the 24,000-atom box", "steps": args.big_steps}
     for name, integ in (("baoab", B.BAOAB), ("bounce", B.BJAOAJB)):
         r = run_gpu(sub_args, system, ff, integ, state)
+        # the pair kernel's roofline at this size (pairs within r'' for BOUNCE's
+        # short-range kernel, within rc for BAOAB's)
+        rlim, fl = (args.r_off, FLOPS_SHORT) if integ == B.BJAOAJB else (9.0, FLOPS_FULL)
+        pairs = pair_count(r["pos"], system.box, rlim, system.excl.shape[0])
+        tflops = pairs * fl / (r["pair_kernel_ms"] * 1e-3) / 1e12
         out[name] = {"ms_per_step": round(r["ms_per_step"], 5),
                      "ns_per_day": round(1e-6 / (r["ms_per_step"] * 1e-3) * 86400.0, 3),
                      "pair_kernel_us": round(r["pair_kernel_ms"] * 1e3, 3),
+                     "pair_kernel_tflops": round(tflops, 4),
+                     "pair_kernel_frac": round(tflops / PEAK_FP32, 5),
                      "list_build_us": round(r["build_ms"] * 1e3, 3), "pair_lanes": r["lanes"]}
         log(f"96k box {name}: {out[name]}")
     out["speedup_vs_baoab"] = round(out["baoab"]["ms_per_step"] / out["bounce"]["ms_per_step"], 4)
