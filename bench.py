@@ -81,6 +81,13 @@ def copy_calibration(mib):
     log(f"copy calibration: 3 copies of {mib} MiB")
 
 
+def pair_count_open(pos, r, n_excl_within):
+    """Unordered non-excluded pairs with |d| < r, no periodic images."""
+    from scipy.spatial import cKDTree
+    t = cKDTree(pos)
+    return int(t.count_neighbors(t, r) - pos.shape[0]) // 2 - n_excl_within
+
+
 def pair_count(pos, box, r, n_excl_within):
     """Unordered non-excluded pairs with |d| < r (minimum image)."""
     from scipy.spatial import cKDTree
@@ -198,12 +205,24 @@ def run_batch(args, ff):
         wall = time.perf_counter() - t0
         c1 = [sim.counters(r) for r in range(len(systems))]
         n = sim.n
+        # the short-range pair kernel's roofline over all droplets: pairs within
+        # r'' counted per droplet (no periodic images, exclusions removed)
+        pair_ms = sim.profile_kernel(0, 20)
+        q = sim.pos.cpu().numpy()
+        pairs = 0
+        for r, s in enumerate(systems):
+            b, e = sim.offsets[r], sim.offsets[r + 1]
+            pairs += pair_count_open(q[b:e], 8.0, s.excl.shape[0])
         sim.close()
+        tflops = pairs * FLOPS_SHORT / (pair_ms * 1e-3) / 1e12
         ms = 1e3 * wall / args.batch_steps
         diff = lambda k: (sum(c[k] for c in c1) - sum(c[k] for c in c0)) / args.batch_steps
         out[mode_name] = {"ms_per_step": round(ms, 5), "atom_steps_per_s": n * 1e3 / ms,
                           "proposals_per_step": diff("proposals"),
-                          "accepted_per_step": diff("accepted"), "pair_lanes": lanes}
+                          "accepted_per_step": diff("accepted"), "pair_lanes": lanes,
+                          "pair_kernel_us": round(pair_ms * 1e3, 3), "short_pairs": pairs,
+                          "pair_kernel_tflops": round(tflops, 4),
+                          "pair_kernel_frac": round(tflops / PEAK_FP32, 5)}
         log(f"batch {mode_name}: {out[mode_name]}")
     return out
 
