@@ -826,6 +826,7 @@ static void enqueue_build(bounce_ctx *c, int32_t step_off)
     BuildSpec b = main_spec(c);
     b.step_off = step_off;
     launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, b, c->d_st);
+    launch_reset_disp(c->stream, c->d_st);
 }
 
 static PairArgs pair_args(bounce_ctx *c, const ListSet &ls, int mirror_sel)
@@ -851,6 +852,9 @@ static void launch_step_pair(bounce_ctx *c, int32_t step_off, double *out)
 {
     PairArgs a = pair_args(c, c->main, -1);
     a.step_off = step_off;
+    // far partners (>= lim + s/2 at the build) stay out of range while
+    // 2 max|displacement| < s/2; the 1e-3 A margin covers rounding
+    a.far_gate = 0.5 * c->p.skin - 1e-3 > 0.0;
     a.out = out;
     a.out_global = 0;
     a.accumulate = 0;
@@ -949,6 +953,10 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     a.c1 = std::exp(-c->p.gamma * c->p.dt);
     a.beta = 1.0 / (KB * c->p.temperature);
     a.skin_half2 = 0.25 * c->p.skin * c->p.skin;
+    {
+        const double g = 0.5 * (0.5 * c->p.skin - 1e-3);
+        a.far_gate2 = g > 0.0 ? g * g : 0.0;
+    }
     return a;
 }
 

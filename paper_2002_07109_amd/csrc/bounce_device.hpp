@@ -46,7 +46,9 @@ struct DevState {
     int64_t step;
     int64_t n_events;
     uint32_t status;
-    uint32_t pad[3];
+    uint32_t far_flag;            // an atom has moved (s/2 - margin)/2 or more since the main
+                                  //   list's build: the force rows' far parts may be in range
+    uint64_t pad;
 };
 
 // jump counters of one replica, held in CNT_SPREAD copies (one 128-byte line

@@ -11,7 +11,7 @@ struct PairArgs {
     int32_t mirror_sel;           // -1: parity of step (device counter + step_off), 0/1 fixed
     int32_t step_off;
     int32_t single_rep;           // 1: one replica (its RepInfo read as reps[0])
-    int32_t pad0;
+    int32_t far_gate;             // 1: skip the rows' far parts while st->far_flag is clear
     const RepInfo *reps;
     Topo tp;
     ListSet ls;
@@ -60,6 +60,7 @@ struct StepArgs {
     PairGlobals pg;
     double dt, half_dt, c1, beta;
     double skin_half2;            // (s/2)^2
+    double far_gate2;             // ((s/2 - margin)/2)^2: a displacement at or above it sets st->far_flag
     const double *grec;           // [N][3] sorted: outer-step gradient for the RESPA kicks
     double rec_close, rec_open;   // kick lengths (fs) with grec after the closing B / before the opening B
 };
@@ -107,6 +108,8 @@ void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, c
 void launch_step(hipStream_t sm, const StepArgs &a);
 // device step counter += count (one thread; orders after the preceding launches)
 void launch_advance(hipStream_t sm, DevState *st, int32_t count);
+// st->far_flag = 0 (after a build of the main list)
+void launch_reset_disp(hipStream_t sm, DevState *st);
 void launch_jump(hipStream_t sm, const JumpArgs &a);
 void launch_rdf(hipStream_t sm, int32_t n, const RepInfo *reps, int32_t single_rep,
                 const ListSet &ls, double r_max, int32_t nbins, int32_t nt,

@@ -126,7 +126,10 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const int32_t *row = a.ls.flist + (int64_t)s * a.ls.fcap;
         const int32_t cap = a.ls.fcap;
         const int2 fc = a.ls.fcnt[s];   // the list build keeps fc.x + fc.y <= cap
-        const int32_t nn = fc.x, cnt = fc.x + fc.y;
+        // a far partner was at least lim + s/2 away at the build; while every
+        // atom has moved less than (s/2)/2 since (the flag clear), none is within lim
+        const bool near_only = a.far_gate && a.st->far_flag == 0u;
+        const int32_t nn = fc.x, cnt = near_only ? fc.x : fc.x + fc.y;
         const int32_t tail = cap - 1 + nn;
         if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
             pair_force_row<R, MODE, G>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);

@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     int32_t rep = 0, g = 0, lid = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
     double v[3] = {0.0, 0.0, 0.0}, fb[3] = {0.0, 0.0, 0.0};
-    double km = 0.0, c2 = 0.0;
+    double km = 0.0, c2 = 0.0, disp2 = 0.0;
+    const bool far_seen = a.st->far_flag != 0u;     // read once: set at most once per list
     Partners<KC> PT;
     no_partners<KC>(a, PT);
     U4 w = {0, 0, 0, 0};
@@ -541,7 +542,8 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             for (int k = 0; k < 3; ++k) q[k] = q[k] + a.half_dt * v[k];
             const double *qb = a.ls.q_build + 3 * (int64_t)g;
             const double ddx = q[0] - qb[0], ddy = q[1] - qb[1], ddz = q[2] - qb[2];
-            if (ddx * ddx + ddy * ddy + ddz * ddz >= a.skin_half2) atomicOr(&a.st->status, ST_SKIN);
+            disp2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            if (disp2 >= a.skin_half2) atomicOr(&a.st->status, ST_SKIN);
             a.pos[3 * (int64_t)g] = q[0];
             a.pos[3 * (int64_t)g + 1] = q[1];
             a.pos[3 * (int64_t)g + 2] = q[2];
@@ -554,12 +556,24 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
                    isfinite(q[1]) && isfinite(q[2]);
         if (!fin) atomicOr(&a.st->status, ST_NONFINITE);
     }
+    // an atom beyond the far-part gate since the build sets the flag: one atomic
+    // per wavefront that has such an atom, only while the flag read at the start
+    // was clear (a stale read adds atomics, it never misses one)
+    const bool beyond = __ballot(disp2 >= a.far_gate2) != 0ull;
+    if (!far_seen && beyond && (threadIdx.x & 63) == 0) atomicOr(&a.st->far_flag, 1u);
     if (BOUNCE) flush_tally(a, rep, active && sub == 0, tally);
 }
 
 // the device step counter moves once per batch of launched steps, in a kernel
 // of its own: kernels of one stream see it in launch order, with no fences
 __global__ void k_advance(DevState *st, int32_t count) { st->step += count; }
+
+__global__ void k_reset_disp(DevState *st) { st->far_flag = 0u; }
+
+void launch_reset_disp(hipStream_t sm, DevState *st)
+{
+    hipLaunchKernelGGL(k_reset_disp, dim3(1), dim3(1), 0, sm, st);
+}
 
 void launch_advance(hipStream_t sm, DevState *st, int32_t count)
 {

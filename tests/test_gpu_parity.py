@@ -151,6 +151,26 @@ def test_trajectory_fp64(orc, droplet, box, which, nsteps):
     assert c["bound_violations"] == 0
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+def test_trajectory_past_the_far_part_gate(orc, box, integrator):
+    """With a 1.2 A skin, over a hundred atoms move more than a quarter skin
+    within one rebuild interval (checked on the oracle first), so the force
+    rows' far parts come back into the pair sum part-way through each
+    interval: the trajectory and the jump events still follow the oracle."""
+    cfg = dict(BOX, skin=1.2, integrator=integrator)
+    p = oracle_params(orc, box, cfg)
+    o10 = orc.run(p, orc.Topology.from_system(box), box.pos, box.vel, 0, cfg["rebuild_interval"])
+    moved = np.sqrt(((o10["q"] - box.pos) ** 2).sum(axis=1))
+    assert (moved >= 0.5 * (0.5 * cfg["skin"] - 1e-3)).sum() > 50
+    sim, o = _traj(orc, box, cfg, 60, fp64=True)
+    assert np.abs(sim.pos.cpu().numpy() - o["q"]).max() <= 1e-6
+    assert np.abs(sim.vel.cpu().numpy() - o["v"]).max() <= 1e-6
+    if integrator == 0:
+        ev, n = sim.events()
+        assert n == o["n_events"] and n > 0
+        assert np.array_equal(event_keys(ev), event_keys(o["events"]))
+
+
 def test_trajectory_baoab_fp64(orc, droplet):
     cfg = dict(DROPLET, integrator=1, dt=1.0)
     sim, o = _traj(orc, droplet, cfg, 100, fp64=True)
