@@ -100,6 +100,18 @@ def pair_count(pos, box, r, n_excl_within):
 RATE_MODES = {"atom": 0, "pair": 1}
 
 
+def pair_ms_over_interval(sim, interval, reps):
+    """Mean duration (ms) of the F_0 pair kernel over one list-rebuild interval:
+    timed after each of `interval` single steps (the far parts of the force rows
+    are walked only on the later steps of an interval), `reps` launches each."""
+    t = 0.0
+    for _ in range(interval):
+        sim.step(1)
+        t += sim.profile_kernel(0, reps)
+    sim.sync()
+    return t / interval
+
+
 def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=None, **mesh):
     import torch
     import paper_2002_07109_amd as B
@@ -127,7 +139,7 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     c1 = sim.counters()
-    pair_ms = sim.profile_kernel(0, 50)
+    pair_ms = pair_ms_over_interval(sim, rebuild or args.rebuild, 10)
     build_ms = sim.profile_kernel(1, 10)
     mesh_ms = sim.profile_kernel(4, 20) if mesh.get("pme_grid") else None
     e = sim.energies()[0]
@@ -207,7 +219,7 @@ def run_batch(args, ff):
         n = sim.n
         # the short-range pair kernel's roofline over all droplets: pairs within
         # r'' counted per droplet (no periodic images, exclusions removed)
-        pair_ms = sim.profile_kernel(0, 20)
+        pair_ms = pair_ms_over_interval(sim, 10, 4)
         q = sim.pos.cpu().numpy()
         pairs = 0
         for r, s in enumerate(systems):
