@@ -613,6 +613,8 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
             orc_event *e = &ev[*n_ev];
             e->step = step; e->phase = phase; e->atom = i; e->k = (int32_t)k;
             e->partner = j; e->accepted = acc; e->pad = 0;
+            e->margin = u * v0 * L - s;
+            e->scale = v0 * sqrt(norm2(F));
         }
         if (ev) ++*n_ev;
     }

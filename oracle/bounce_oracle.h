@@ -104,9 +104,13 @@ typedef struct {
     int64_t proposals, accepted, bound_violations, rebuilds, pair_evals, steps;
 } orc_counters;
 
+/* one jump proposal; margin = U |v_i| L - v_i.F (accepted iff margin < 0) and
+   scale = |v_i| |F| (how far rounding of F can move v_i.F) let a test tell a
+   near-tie of the accept test from a real disagreement */
 typedef struct {
     int64_t step;
     int32_t phase, atom, k, partner, accepted, pad;
+    double margin, scale;
 } orc_event;
 
 /* Philox4x64-10 block (Salmon et al., SC'11). */

@@ -75,7 +75,7 @@ class Counters(C.Structure):
 
 EVENT_DTYPE = np.dtype([("step", np.int64), ("phase", np.int32), ("atom", np.int32),
                         ("k", np.int32), ("partner", np.int32), ("accepted", np.int32),
-                        ("pad", np.int32)])
+                        ("pad", np.int32), ("margin", np.float64), ("scale", np.float64)])
 
 _lib = None
 

@@ -87,9 +87,53 @@ def relaxed_box(name):
     return s
 
 
-def rel_err_total(a, b, total):
-    """max_i |a_i - b_i| / RMS_i |total_i|: error of one force part against the
-    scale of the whole force."""
-    a, b, total = np.asarray(a), np.asarray(b), np.asarray(total)
-    rms = np.sqrt(np.mean(np.sum(total * total, axis=-1)))
-    return float(np.max(np.linalg.norm(a - b, axis=-1)) / rms)
+def sum_abs_pair_energy(orc, p, topo, q, box=None):
+    """Sum over unordered non-excluded pairs within r_cut of |W_sf(r)| (the
+    oracle's shifted-force pair energy): the scale against which rounding of
+    pair energies of either sign is measured."""
+    rp, col = orc.build_list(p, topo, q, 0.0, p.r_cut)
+    n = q.shape[0]
+    i = np.repeat(np.arange(n), np.diff(rp))
+    keep = col > i
+    i, j = i[keep], col[keep]
+    d = q[i] - q[j]
+    if box is not None:
+        d -= box * np.rint(d / box)
+    r = np.sqrt((d * d).sum(1))
+    t = topo.type
+    return float(sum(abs(orc.pair_wsf(p, int(a), int(b), float(x))[0])
+                     for a, b, x in zip(t[i], t[j], r)))
+
+
+def first_divergence(gpu_ev, orc_ev):
+    """Walk the two event logs half-step by half-step in time order.  Returns
+    None if they are identical, else (step, phase, [(atom, k, oracle event or
+    None)]) for the first half-step that differs: per atom whose chain differs
+    there, its first differing proposal.  Atoms' chains within one half-step
+    are independent (positions are fixed during J), so each such atom's first
+    difference is a separate accept-test decision."""
+    keys = ("step", "phase", "atom", "k", "partner", "accepted")
+    a = event_keys(gpu_ev, keys)
+    o_sorted = np.sort(orc_ev, order=["step", "phase", "atom", "k"])
+    b = event_keys(o_sorted, keys)
+    if a.shape == b.shape and np.array_equal(a, b):
+        return None
+    half = lambda k: k[:, 0] * 4 + k[:, 1]
+    ha, hb = half(a), half(b)
+    for h in np.union1d(ha, hb):
+        ea, eb = a[ha == h], b[hb == h]
+        if ea.shape == eb.shape and np.array_equal(ea, eb):
+            continue
+        ob = o_sorted[hb == h]
+        out = []
+        for atom in np.union1d(ea[:, 2], eb[:, 2]):
+            ra, rb = ea[ea[:, 2] == atom], eb[eb[:, 2] == atom]
+            m = min(len(ra), len(rb))
+            diff = [k for k in range(m) if not np.array_equal(ra[k], rb[k])]
+            if not diff and len(ra) == len(rb):
+                continue
+            k = diff[0] if diff else m
+            orow = ob[ob["atom"] == atom]
+            out.append((int(atom), k + 1, orow[k] if k < len(orow) else None))
+        return int(h // 4), int(h % 4), out
+    return None

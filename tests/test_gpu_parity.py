@@ -1,15 +1,18 @@
 """GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-Tolerances (max_i |dF_i| / RMS_i |F_i| for per-atom vectors):
-  FP64 pair arithmetic: 1e-11 (summation order only), FP32 pair arithmetic: 1e-5.
-Lists and, in FP64, jump events are compared bit for bit."""
+Tolerances (max_i |dF_i| / RMS_i |F_i| for per-atom vectors, each force part
+against its own RMS): FP64 pair arithmetic 1e-11 (summation order only), FP32
+pair arithmetic 1e-5; pair energies in FP32 within 2e-6 of the sum over pairs of
+|u_pair|.  Lists and, in FP64, jump events are compared bit for bit; FP32 event
+logs must match the oracle until the first accept test whose oracle margin is a
+near-tie (|U |v| L - v.F| < 1e-5 |v| |F|)."""
 import math
 
 import numpy as np
 import pytest
 
-from helpers import (BOX, DROPLET, FF, event_keys, gpu_sim, oracle_params, rel_err,
-                     rel_err_total, relaxed_box, relaxed_droplet)
+from helpers import (BOX, DROPLET, FF, event_keys, first_divergence, gpu_sim, oracle_params,
+                     rel_err, relaxed_box, relaxed_droplet, sum_abs_pair_energy)
 from workloads import jitter_positions, water_box, water_droplet
 
 pytestmark = pytest.mark.gpu
@@ -68,14 +71,14 @@ def test_gradients(orc, droplet, box, which, fp64):
     p = oracle_params(orc, sys, cfg)
     topo = orc.Topology.from_system(sys)
     tol = 1e-11 if fp64 else 1e-5
-    # each part's error is measured against the scale of the whole force
-    total = orc.gradient(p, topo, q, orc.G_BONDED | orc.G_FULL)
+    # each part's error against that part's own RMS
     for gbit, obit in [(B.G_SHORT, orc.G_SHORT), (B.G_LONG, orc.G_LONG), (B.G_FULL, orc.G_FULL),
                        (B.G_BONDED, orc.G_BONDED), (B.G_BONDED | B.G_SHORT,
                                                     orc.G_BONDED | orc.G_SHORT)]:
         g = sim.gradient(gbit).cpu().numpy()
         o = orc.gradient(p, topo, q, obit)
-        err = rel_err_total(g, o, total)
+        err = rel_err(g, o)
+        print(f"{which} fp64={fp64} part {gbit}: max|dF|/RMS|F| = {err:.3e}")
         assert err < (1e-13 if gbit == B.G_BONDED else tol), (gbit, err)
 
 
@@ -91,9 +94,12 @@ def test_energies(orc, droplet, box, which):
     # energies of either sign, so the bound is taken against the sum of |u_pair|
     sim32 = gpu_sim(sys, cfg, fp64=False)
     e32 = sim32.energies()[0]
-    n_pairs = orc.build_list(oracle_params(orc, sys, cfg), orc.Topology.from_system(sys), sys.pos,
-                             0.0, cfg["r_cut"])[0][-1] // 2
-    assert abs(e32["pair"] - o["pair"]) < 1e-7 * 20.0 * n_pairs
+    p = oracle_params(orc, sys, cfg)
+    sabs = sum_abs_pair_energy(orc, p, orc.Topology.from_system(sys), sys.pos,
+                               sys.box if sys.periodic else None)
+    err = abs(e32["pair"] - o["pair"]) / sabs
+    print(f"{which}: FP32 pair energy error {err:.3e} of sum |u_pair| = {sabs:.1f}")
+    assert err < 2e-6, err
 
 
 @pytest.mark.parametrize("which", ["drop", "box"])
@@ -177,17 +183,39 @@ def test_trajectory_baoab_fp64(orc, droplet):
     assert np.abs(sim.pos.cpu().numpy() - o["q"]).max() <= 1e-6
 
 
-def test_trajectory_fp32_divergence(orc, droplet):
-    """FP32 pair arithmetic: positions after 100 steps stay close to the FP64
-    oracle; any differing event is explained by a near-tie of the accept test."""
+def assert_fp32_events_follow_oracle(ev, o_events, tol=1e-5):
+    """FP32 pair arithmetic in the jump field: the event log equals the FP64
+    oracle's until the first half-step where they differ, and there every
+    atom's first differing proposal is a near-tie of the oracle's accept test,
+    |U |v| L - v.F| < tol |v| |F| (FP32 rounding moves v.F by ~1e-7 |v| |F|).
+    Returns (number of identical leading events, the divergence or None)."""
+    div = first_divergence(ev, o_events)
+    if div is None:
+        return len(o_events), None
+    step, phase, atoms = div
+    for atom, k, oe in atoms:
+        assert oe is not None, f"step {step} phase {phase} atom {atom}: proposal count differs"
+        rel = abs(oe["margin"]) / oe["scale"] if oe["scale"] > 0 else np.inf
+        assert rel < tol, (step, phase, atom, k, rel)
+    before = int(np.sum(o_events["step"] * 4 + o_events["phase"] < step * 4 + phase))
+    return before, div
+
+
+def test_trajectory_fp32_events_and_positions(orc, droplet):
+    """FP32 pair arithmetic on the proposal-heavy droplet (~3,000 proposals a
+    step): the event log follows the FP64 oracle up to its first near-tie, and
+    positions after 100 steps stay close."""
     sim, o = _traj(orc, droplet, DROPLET, 100, fp64=False)
     dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
-    assert dq < 1e-2, dq
     ev, n = sim.events()
-    a, b = event_keys(ev[ev["step"] < 20]), event_keys(o["events"][o["events"]["step"] < 20])
-    same = a.shape == b.shape and np.array_equal(a, b)
-    print(f"FP32 vs FP64 oracle after 100 steps: max |dq| = {dq:.3e} A; "
-          f"events {n} vs {o['n_events']}; first 20 steps identical: {same}")
+    same, div = assert_fp32_events_follow_oracle(ev, o["events"])
+    print(f"FP32 vs FP64 oracle after 100 steps: max |dq| = {dq:.3e} A; events {n} vs "
+          f"{o['n_events']}; identical leading events {same}; first divergence {div}")
+    if div is None:
+        assert n == o["n_events"]
+        assert dq < 1e-4, dq
+    else:
+        assert dq < 1e-2, dq
 
 
 def test_graph_replay_equals_direct_launches(orc, box):

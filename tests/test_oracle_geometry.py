@@ -135,3 +135,40 @@ def test_energy_terms_closed_forms(orc):
     v = np.ones_like(q)
     e = orc.energies(p, topo, q, v)
     assert e["kin"] == pytest.approx(0.5 * sys.mass.sum() * 3 / 4.184e-4, rel=1e-14)
+
+
+@pytest.mark.parametrize("dtheta", [0.05, -0.12, 0.3])
+def test_angle_energy_and_gradient_closed_forms(orc, dtheta):
+    """A water whose H2 is rotated about O in the molecular plane by dtheta
+    keeps both bonds at r0 and has H-O-H = theta0 + dtheta: E_angle = k dtheta^2
+    exactly (the harmonic angle term of flexible water, with k = 55 kcal/mol/rad^2
+    and no factor 1/2), E_bond = 0, and the angle gradient on H2 is tangential
+    with magnitude 2 k dtheta / r0 (dtheta/ds = 1/r0 along the arc)."""
+    sys = water_droplet(n_waters=1, seed=0)
+    p = orc.make_params(sys)
+    topo = orc.Topology.from_system(sys)
+    q = sys.pos.copy()
+    o, h1, h2 = q[0], q[1], q[2]
+    n = np.cross(h1 - o, h2 - o)
+    n /= np.linalg.norm(n)
+    # rotate H2 about the normal so that the angle opens by dtheta
+    d = h2 - o
+    c, s = np.cos(dtheta), np.sin(dtheta)
+    rot = d * c + np.cross(n, d) * s + n * np.dot(n, d) * (1 - c)
+    ang0 = np.arccos(np.dot(h1 - o, d) / (np.linalg.norm(h1 - o) * np.linalg.norm(d)))
+    ang1 = np.arccos(np.dot(h1 - o, rot) / (np.linalg.norm(h1 - o) * np.linalg.norm(rot)))
+    if abs(ang1 - ang0 - dtheta) > 1e-9:        # rotated the other way: flip the sense
+        rot = d * c - np.cross(n, d) * s + n * np.dot(n, d) * (1 - c)
+    q[2] = o + rot
+    e = orc.energies(p, topo, q, np.zeros_like(q))
+    assert e["bond"] == pytest.approx(0.0, abs=1e-20)
+    assert e["angle"] == pytest.approx(55.0 * dtheta ** 2, rel=1e-10)
+    g = orc.gradient(p, topo, q, orc.G_BONDED)
+    r0 = np.linalg.norm(rot)
+    assert np.linalg.norm(g[2]) == pytest.approx(2.0 * 55.0 * abs(dtheta) / r0, rel=1e-10)
+    # tangential: orthogonal to the O-H2 bond, in the molecular plane
+    assert abs(np.dot(g[2], rot)) < 1e-10 * np.linalg.norm(g[2]) * r0
+    assert abs(np.dot(g[2], n)) < 1e-10 * np.linalg.norm(g[2])
+    # opening the angle raises the energy: the gradient points along the opening direction
+    opening = np.cross(n, rot) if np.dot(np.cross(n, rot), h1 - o) < 0 else -np.cross(n, rot)
+    assert np.sign(np.dot(g[2], opening)) == np.sign(dtheta)

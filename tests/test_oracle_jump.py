@@ -144,6 +144,14 @@ def _replay_compensator(orc, p, topo, q, v, rp, col, ev):
         v0 = np.linalg.norm(vv[i])
         pr = max(0.0, vv[i] @ F) / (v0 * L_a[ti])
         assert pr <= 1.0 + 1e-9
+        # the logged accept-test margin U |v| L - v.F and its scale |v| |F|:
+        # accepted iff the margin is negative, and margin + v.F = U |v| L lies
+        # in (0, |v| L)
+        s = vv[i] @ F
+        assert e["scale"] == pytest.approx(v0 * np.linalg.norm(F), rel=1e-9, abs=1e-300)
+        assert (e["margin"] < 0) == bool(e["accepted"])
+        ul = e["margin"] + s
+        assert -1e-9 * v0 * L_a[ti] < ul < v0 * L_a[ti] * (1 + 1e-9)
         if e["accepted"]:
             assert pr > 0
             vv[i] = vv[i] - 2 * (vv[i] @ F) / (F @ F) * F
