@@ -125,7 +125,11 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
     sim.step(args.warmup)
     sim.sync()
     lanes, tune = sim.autotune(reps=20)
-    sim.step(10)
+    # the autotuner drops the K-step graph: run to the next list interval and
+    # replay one whole interval, so that the graph is captured and instantiated
+    # before the timed region, which then starts at a list rebuild
+    K = rebuild or args.rebuild
+    sim.step((-sim.get_step()) % K + K)
     sim.sync()
     c0 = sim.counters()
     torch.cuda.synchronize()

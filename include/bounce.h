@@ -144,9 +144,16 @@ typedef struct {
 
 typedef struct bounce_ctx bounce_ctx;
 
-/* Create a context from parameters (copied).  *out receives the handle. */
+/* Create a context from parameters (copied).  *out receives the handle.
+   The parameters are those of the process and its discretisation: the target
+   measure exp(-beta H) at temperature T (Sec. II.A), the friction and step of
+   the Langevin splitting (Sec. III.C), the switch window [r', r''] and cutoff
+   of the force decomposition (Sec. IV.A, Sec. V), the Verlet skin and rebuild
+   interval of the neighbour lists (Sec. V), and the RESPA outer step (Sec. V).
+   Errors: BOUNCE_E_ARG for an inconsistent set (no context is made). */
 bounce_status bounce_create(const bounce_params *params, bounce_ctx **out);
-/* Release the context (not the caller's buffers).  NULL is ignored. */
+/* Release the context and its HIP graph (not the caller's buffers: the
+   library allocated no device memory).  NULL is ignored. */
 void bounce_destroy(bounce_ctx *ctx);
 /* Replace dt, gamma, temperature and bound_scale of a bound context (other fields ignored). */
 bounce_status bounce_update_params(bounce_ctx *ctx, const bounce_params *params);
@@ -158,18 +165,25 @@ bounce_status bounce_set_system(bounce_ctx *ctx, const bounce_system *sys);
 /* Device workspace bytes the context needs. */
 bounce_status bounce_workspace_size(const bounce_ctx *ctx, uint64_t *bytes);
 /* Bind caller-owned device memory: workspace (>= bounce_workspace_size bytes),
-   positions and velocities ([N][3] float64, updated in place), and the HIP
-   stream (hipStream_t, NULL = default).  Uploads the topology; step = 0. */
+   positions and velocities ([N][3] float64, updated in place: the state (q, p)
+   of the process, Sec. II.A, with p = M v), and the HIP stream (hipStream_t,
+   NULL = default).  Uploads the topology; step = 0.  Errors: BOUNCE_E_ARG,
+   BOUNCE_E_STATE (no system), BOUNCE_E_WORKSPACE (too small), BOUNCE_E_HIP. */
 bounce_status bounce_bind(bounce_ctx *ctx, void *workspace, uint64_t workspace_bytes,
                           double *pos_dev, double *vel_dev, void *stream);
 /* Set the step counter n (random-stream counter base); the next bounce_step
    rebuilds the lists.  Use after writing new positions or velocities. */
 bounce_status bounce_set_step(bounce_ctx *ctx, int64_t step);
 bounce_status bounce_get_step(const bounce_ctx *ctx, int64_t *step);
-/* Enqueue n_steps full steps (B J A O A J B, or B A O A B), leaving positions
-   and velocities at a step boundary.  Asynchronous. */
+/* Enqueue n_steps full steps of the algorithm of Sec. IV.B: B J A O A J B
+   (BOUNCE) or B A O A B (BAOAB), each J a thinned jump half-step (Sec. III.D),
+   lists rebuilt every rebuild_interval steps (Sec. V), leaving positions and
+   velocities at a step boundary.  Asynchronous: device conditions surface at
+   the next bounce_sync. */
 bounce_status bounce_step(bounce_ctx *ctx, int32_t n_steps);
-/* Wait for the bound stream and return the first latched device condition. */
+/* Wait for the bound stream and return the first latched device condition
+   (list capacity, skin overrun, rate-bound violation v.F > |v| L of the
+   thinning bound of Sec. IV.A, Poisson cap, non-finite state, droplet grid). */
 bounce_status bounce_sync(bounce_ctx *ctx);
 
 /* Gradient dE/dq of the selected parts at the current positions into grad_dev
@@ -183,10 +197,16 @@ bounce_status bounce_compute_gradient(bounce_ctx *ctx, int32_t which, double *gr
    E_bond, E_angle, E_coul, E_lj, E_pair (= coul + lj, shifted force, r < rc),
    E_kin, T_kin.  Synchronous. */
 bounce_status bounce_compute_energies(bounce_ctx *ctx, double *out_host);
+/* Jump counters of one replica (Sec. VI reports proposal rates per particle
+   and step): proposals, accepted reflections, bound violations, rebuilds and
+   steps.  Synchronous.  Errors: BOUNCE_E_ARG for a replica out of range. */
 bounce_status bounce_get_counters(bounce_ctx *ctx, int32_t replica, bounce_counters *out);
-/* Copy up to cap logged events (in no particular order) and their total count. */
+/* Copy up to cap logged jump proposals (in no particular order) and their
+   total count: each is one thinning proposal of Sec. III.D (step, phase,
+   atom, proposal index k, partner, accept decision U < lambda/lambda*).
+   Needs log_events; events beyond event_capacity are counted, not kept. */
 bounce_status bounce_get_events(bounce_ctx *ctx, bounce_event *host, int64_t cap, int64_t *n_total);
-/* The list built last (FORCE: r < r''+s for BOUNCE, r < rc+s for BAOAB; CAND:
+/* Neighbour lists of Sec. V.  The list built last (FORCE: r < r''+s for BOUNCE, r < rc+s for BAOAB; CAND:
    candidate partners r'-s <= r < rc+s) as CSR in caller ids: row_ptr_host[N+1],
    col_host[cap], rows in the library's canonical order (ascending list-grid cell,
    then id).  Synchronous. */

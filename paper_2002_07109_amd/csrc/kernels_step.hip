@@ -157,6 +157,10 @@ __device__ __forceinline__ int32_t poisson_count(const StepArgs &a, uint64_t W, 
     capped = false;
     if (W == 0 || v0 == 0.0 || unit == 0.0) return 0;
     const double mu = (double)W * a.beta * v0 * unit * a.half_dt;
+    // e^-mu >= 1 - mu: a uniform below 1 - mu, less 2^-50 (more than the
+    // rounding of this bound and of any faithfully rounded exp), is below the
+    // first CDF term, so the inversion stops at M = 0 without evaluating exp
+    if (U <= (1.0 - mu) - 0x1p-50) return 0;
     int32_t M = 0;
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
@@ -426,14 +430,12 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
         km = a.half_dt * a.tp.acc_m[g];
         c2 = a.ou_c2[g];
         if (BOUNCE) load_partners<KC>(a, s, mirror_type(xi.w), PT);
-        // one Philox block per lane
-        if (sub < 3) {
-            const int64_t dstep = sub == 1 ? n - 1 : n;
-            const int32_t dphase = sub == 0 ? 1 : (sub == 1 ? 2 : 0);
-            w = draw(ri, dstep, dphase, lid, 0);
-        } else if (BOUNCE && a.do_close) {
-            w = draw(ri, n - 1, 2, lid, 1);
-        }
+        // one Philox block per lane, drawn by one call for the whole group:
+        // lane 0 the O step (n, O), lane 1 the Poisson uniform of (n-1, JB),
+        // lane 2 that of (n, JA), lane 3 proposal 1 of (n-1, JB)
+        const int64_t dstep = (sub == 1 || sub == 3) ? n - 1 : n;
+        const int32_t dphase = sub == 0 ? 1 : (sub == 2 ? 0 : 2);
+        w = draw(ri, dstep, dphase, lid, sub == 3 ? 1 : 0);
     }
     const RepInfo ri = load_rep(a.reps, a.single_rep, rep);
     const int ti = mirror_type(xi.w);
@@ -457,27 +459,30 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     pp.u = 1.0;
     pp.lb = 1.0;
     pp.p = 0;
-    if (BOUNCE && active) {
+    if (BOUNCE) {
+        // both counts at the entry velocity in one evaluation: lanes 0, 1 the
+        // count of (n-1, JB), lanes 2, 3 the estimated count of (n, JA)
         const double v0 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        bool capped_b = false, capped_a = false;
-        if (a.do_close) M_jb = poisson_count(a, PT.W, v0, PT.unit, U_jb, capped_b);
-        if (a.do_open) M_est = poisson_count(a, PT.W, v0, PT.unit, U_ja, capped_a);
-        bool ev = false;
-        if (sub == JB_L1 && M_jb >= 1) {
-            block_proposal<KC>(w, PT, pp);          // drawn at entry
-            ev = true;
-        } else if (sub == JB_L2 && M_jb >= 2) {
-            draw_proposal<KC>(PT, ri, n - 1, 2, lid, 2, pp);
-            ev = true;
-        } else if (sub == JA_L1 && M_est >= 1) {
-            draw_proposal<KC>(PT, ri, n, 0, lid, 1, pp);
-            ev = true;
-        } else if (sub == JA_L2 && M_est >= 2) {
-            draw_proposal<KC>(PT, ri, n, 0, lid, 2, pp);
-            ev = true;
+        const bool jb_lane = sub < 2;
+        bool capped = false;
+        int32_t M = 0;
+        if (active && (jb_lane ? a.do_close : a.do_open))
+            M = poisson_count(a, PT.W, v0, PT.unit, jb_lane ? U_jb : U_ja, capped);
+        M_jb = group_get_i32<LPA>(M, 1);
+        M_est = group_get_i32<LPA>(M, 2);
+        if (capped && sub == 1) atomicOr(&a.st->status, ST_POISSON);
+        // the first two proposals of each half-step, one per lane; lane 3's
+        // block was drawn at entry, the others take one call together
+        const bool need = sub == JB_L1 ? M_jb >= 1
+                        : sub == JB_L2 ? M_jb >= 2
+                        : sub == JA_L1 ? M_est >= 1 : M_est >= 2;
+        U4 pw = w;
+        if (need && sub != JB_L1)
+            pw = draw(ri, sub == JB_L2 ? n - 1 : n, sub == JB_L2 ? 2 : 0, lid, sub == JA_L1 ? 1 : 2);
+        if (need) {
+            block_proposal<KC>(pw, PT, pp);
+            field_proposal<R>(a, ftab, X, ri, ti, q, pp);
         }
-        if (ev) field_proposal<R>(a, ftab, X, ri, ti, q, pp);
-        if (capped_b && sub == 0) atomicOr(&a.st->status, ST_POISSON);
     }
     if (active && e0.x >= 0) {
         // bonded terms shared by the lanes: k = sub, sub + LPA, ...
