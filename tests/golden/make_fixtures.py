@@ -1,7 +1,9 @@
 """Write tests/golden/relaxed_droplets.npz: seeded droplets and a small periodic
 box relaxed by the FP64 oracle (BAOAB, dt 0.5 fs, gamma 0.05/fs) so that short parity runs
-start near 300 K instead of from the hot random-orientation lattice.  Calls only
-oracle/ and workloads/."""
+start near 300 K instead of from the hot random-orientation lattice; and
+tests/golden/relaxed_box24k.npz, the 24,000-atom benchmark box (20^3 waters,
+62 A, seed 0) relaxed the same way (`python make_fixtures.py box24k`).  Calls
+only oracle/ and workloads/."""
 import os
 import sys
 
@@ -29,6 +31,13 @@ def relax(sys_, steps=3000):
     return o["q"], o["v"]
 
 
+def main_box24k():
+    s = water_box(n_side=20, box_len=62.0, seed=0)
+    q, v = relax(s, steps=1500)
+    np.savez_compressed(os.path.join(HERE, "relaxed_box24k.npz"), pos=q, vel=v)
+    print("24,000-atom box relaxed")
+
+
 def main():
     out = {}
     for name, nw, seed, stream in DROPLETS:
@@ -45,4 +54,7 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["box24k"]:
+        main_box24k()
+    else:
+        main()

@@ -77,6 +77,16 @@ def relaxed_droplet(name):
     return s
 
 
+def relaxed_box24k():
+    """The 24,000-atom benchmark box (20^3 waters, 62 A, seed 0) with the
+    oracle-relaxed state of tests/golden/relaxed_box24k.npz."""
+    from workloads import water_box
+    s = copy.deepcopy(water_box(n_side=20, box_len=62.0, seed=0))
+    z = np.load(os.path.join(os.path.dirname(_FIX), "relaxed_box24k.npz"))
+    s.pos, s.vel = z["pos"].copy(), z["vel"].copy()
+    return s
+
+
 def relaxed_box(name):
     """Seeded periodic box with the oracle-relaxed state of the fixture file."""
     from workloads import water_box

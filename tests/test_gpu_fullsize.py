@@ -8,7 +8,7 @@ GPU energy."""
 import numpy as np
 import pytest
 
-from helpers import BOX, FF, event_keys, first_divergence, gpu_sim, oracle_params
+from helpers import BOX, FF, event_keys, first_divergence, gpu_sim, oracle_params, relaxed_box24k
 from workloads import jitter_positions, water_box
 
 pytestmark = pytest.mark.gpu
@@ -104,11 +104,13 @@ def test_c1_bench_configuration_runs(c1):
 
 
 @pytest.mark.timeout(900)
-def test_c1_trajectory_fp64_100_steps(orc, c1):
-    """The whole 24,000-atom box, 100 steps of B J A O A J B with FP64 pair
-    arithmetic and the K = 10 step graph (ten list rebuilds, each interval
-    running past the far-part gate), against the oracle: positions and
-    velocities within 1e-6, the event logs and the counters identical."""
+def test_c1_trajectory_fp64_100_steps(orc):
+    """The whole 24,000-atom box (from its oracle-relaxed state), 100 steps of
+    B J A O A J B with FP64 pair arithmetic and the K = 10 step graph (ten list
+    rebuilds, each interval running past the far-part gate), against the
+    oracle: positions and velocities within 1e-6, the event logs and the
+    counters identical."""
+    c1 = relaxed_box24k()
     sim = gpu_sim(c1, BOX, fp64=True, log_events=True, event_capacity=2_000_000, use_graph=True)
     sim.step(100)
     sim.sync()
