@@ -171,6 +171,25 @@ bounce_status bounce_workspace_size(const bounce_ctx *ctx, uint64_t *bytes);
    BOUNCE_E_STATE (no system), BOUNCE_E_WORKSPACE (too small), BOUNCE_E_HIP. */
 bounce_status bounce_bind(bounce_ctx *ctx, void *workspace, uint64_t workspace_bytes,
                           double *pos_dev, double *vel_dev, void *stream);
+/* Size of the static workspace of bounce_bind_static (32 MiB per device). */
+#define BOUNCE_STATIC_WORKSPACE_BYTES (32ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops, harnesses that forbid hipMalloc): bind like
+   bounce_bind, with the library's static workspace instead of a caller
+   workspace.  The workspace is one file-scope device array of
+   BOUNCE_STATIC_WORKSPACE_BYTES per device, held from the library's load on
+   that device until the process ends; this call allocates nothing (its device
+   address is looked up once per device, on the current device).  Systems whose
+   bounce_workspace_size exceeds it are refused with BOUNCE_E_WORKSPACE.  All
+   calls of one device share the one array: binding a second context to it
+   takes it over (the first context's calls then return BOUNCE_E_STATE until it
+   is bound again), and contexts whose calls overlap on one device race.  Every
+   bind clears what must start at zero (step counter, status, counters, cell
+   counts); the rest keeps the last context's contents until rewritten.  Not
+   for use inside a stream capture (it uploads the topology).  Errors:
+   BOUNCE_E_ARG, BOUNCE_E_STATE (no system), BOUNCE_E_WORKSPACE, BOUNCE_E_HIP. */
+bounce_status bounce_bind_static(bounce_ctx *ctx, double *pos_dev, double *vel_dev, void *stream);
 /* Set the step counter n (random-stream counter base); the next bounce_step
    rebuilds the lists.  Use after writing new positions or velocities. */
 bounce_status bounce_set_step(bounce_ctx *ctx, int64_t step);

@@ -68,7 +68,7 @@ class Simulation:
     of shape (N, 3), float64, on ``device``."""
 
     def __init__(self, systems, params: bounce_params, charge, eps, sigma, device="cuda:0",
-                 stream=None):
+                 stream=None, static_workspace=False):
         import torch
         if not isinstance(systems, (list, tuple)):
             systems = [systems]
@@ -131,15 +131,23 @@ class Simulation:
         check(self.L.bounce_set_system(ctx, C.byref(sysc)), ctx, "bounce_set_system")
         nbytes = C.c_uint64()
         check(self.L.bounce_workspace_size(ctx, C.byref(nbytes)), ctx, "bounce_workspace_size")
-        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         pos = np.concatenate([s.pos for s in systems])
         vel = np.concatenate([s.vel for s in systems])
         self.pos = torch.tensor(pos, dtype=torch.float64, device=self.device).contiguous()
         self.vel = torch.tensor(vel, dtype=torch.float64, device=self.device).contiguous()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        check(self.L.bounce_bind(ctx, _tptr(self.workspace), nbytes.value, _tptr(self.pos),
-                                 _tptr(self.vel), C.c_void_p(self.stream.cuda_stream)), ctx,
-              "bounce_bind")
+        if static_workspace:
+            # the library's static per-device workspace (bounce_bind_static)
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                check(self.L.bounce_bind_static(ctx, _tptr(self.pos), _tptr(self.vel),
+                                                C.c_void_p(self.stream.cuda_stream)), ctx,
+                      "bounce_bind_static")
+        else:
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            check(self.L.bounce_bind(ctx, _tptr(self.workspace), nbytes.value, _tptr(self.pos),
+                                     _tptr(self.vel), C.c_void_p(self.stream.cuda_stream)), ctx,
+                  "bounce_bind")
 
     # -- stepping ----------------------------------------------------------
     def step(self, n):

@@ -70,6 +70,7 @@ SIGNATURES = {
     "bounce_set_system": (i32, [ctx_p, _P(bounce_system)]),
     "bounce_workspace_size": (i32, [ctx_p, _P(u64)]),
     "bounce_bind": (i32, [ctx_p, vp, u64, vp, vp, vp]),
+    "bounce_bind_static": (i32, [ctx_p, vp, vp, vp]),
     "bounce_set_step": (i32, [ctx_p, i64]),
     "bounce_get_step": (i32, [ctx_p, _P(i64)]),
     "bounce_step": (i32, [ctx_p, i32]),

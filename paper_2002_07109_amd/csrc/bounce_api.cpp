@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/bounce.h"
@@ -78,6 +79,7 @@ struct Region {
 struct bounce_ctx {
     bounce_params p{};
     bool have_system = false, bound = false;
+    int static_dev = -1;          // device whose static workspace this context uses, or -1
     std::string err;
     // system (host copies)
     int32_t n = 0, R = 0, nt = 0;
@@ -199,9 +201,27 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     return BOUNCE_OK;
 }
 
+// The static workspace of bounce_bind_static: one file-scope device array,
+// present on every device the library runs on until the process ends.  Host
+// code never uses the array's name as an address (on the host it is only a
+// stand-in for the symbol): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[BOUNCE_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES] = {};
+const bounce_ctx *g_static_owner[STATIC_MAX_DEVICES] = {};
+}  // namespace
+
 void bounce_destroy(bounce_ctx *c)
 {
     if (!c) return;
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+    }
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     delete c;
@@ -606,10 +626,61 @@ static hipError_t up(hipStream_t sm, char *ws, size_t off, const std::vector<T> 
     return hipMemcpyAsync(ws + off, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, sm);
 }
 
+static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, double *pos,
+                               double *vel, void *stream);
+
 bounce_status bounce_bind(bounce_ctx *c, void *workspace, uint64_t bytes, double *pos, double *vel,
                           void *stream)
 {
     if (!c || !workspace || !pos || !vel) return BOUNCE_E_ARG;
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+        c->static_dev = -1;
+    }
+    return bind_impl(c, workspace, bytes, pos, vel, stream);
+}
+
+bounce_status bounce_bind_static(bounce_ctx *c, double *pos, double *vel, void *stream)
+{
+    if (!c || !pos || !vel) return BOUNCE_E_ARG;
+    if (!c->have_system) return fail(c, BOUNCE_E_STATE, "bounce_set_system first");
+    uint64_t need = 0;
+    bounce_status s = bounce_workspace_size(c, &need);
+    if (s) return s;
+    if (need > BOUNCE_STATIC_WORKSPACE_BYTES)
+        return fail(c, BOUNCE_E_WORKSPACE,
+                    "the system needs a " + std::to_string(need >> 20) +
+                        " MiB workspace; the static workspace holds " +
+                        std::to_string(BOUNCE_STATIC_WORKSPACE_BYTES >> 20) + " MiB");
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(c, BOUNCE_E_ARG, "device index");
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(c, BOUNCE_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                                 hipGetErrorString(e));
+            g_static_ptr[dev] = p;
+        }
+        ptr = g_static_ptr[dev];
+        // the device's array now belongs to this context; a context bound to it
+        // before is refused from here on (ready() compares owners)
+        if (c->static_dev >= 0 && g_static_owner[c->static_dev] == c)
+            g_static_owner[c->static_dev] = nullptr;
+        g_static_owner[dev] = c;
+        c->static_dev = dev;
+    }
+    return bind_impl(c, ptr, BOUNCE_STATIC_WORKSPACE_BYTES, pos, vel, stream);
+}
+
+static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, double *pos,
+                               double *vel, void *stream)
+{
     if (!c->have_system) return fail(c, BOUNCE_E_STATE, "bounce_set_system first");
     Layout L;
     Offsets o;
@@ -757,6 +828,14 @@ static bounce_status ready(bounce_ctx *c)
 {
     if (!c) return BOUNCE_E_ARG;
     if (!c->have_system || !c->bound) return fail(c, BOUNCE_E_STATE, "set_system and bind first");
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_owner[c->static_dev] != c) {
+            c->bound = false;
+            return fail(c, BOUNCE_E_STATE,
+                        "another context was bound to this device's static workspace; bind again");
+        }
+    }
     return BOUNCE_OK;
 }
 
