@@ -63,7 +63,8 @@ enum { BOUNCE_PH_JA = 0, BOUNCE_PH_O = 1, BOUNCE_PH_JB = 2 };  /* random-stream 
 enum { BOUNCE_OUTER_RECIP = 0, BOUNCE_OUTER_NONBONDED = 1 };
 /* gradient parts for bounce_compute_gradient (bit mask) */
 enum { BOUNCE_G_BONDED = 1, BOUNCE_G_SHORT = 2, BOUNCE_G_LONG = 4, BOUNCE_G_FULL = 8,
-       BOUNCE_G_RECIP = 16 };   /* RECIP: smooth-PME mesh + excluded-pair correction */
+       BOUNCE_G_RECIP = 16,     /* RECIP: smooth-PME mesh + excluded-pair correction */
+       BOUNCE_G_STEP = 32 };    /* STEP: the pair part of F_0 as the integrator computes it */
 /* lists for bounce_get_list */
 enum { BOUNCE_LIST_FORCE = 0, BOUNCE_LIST_CAND = 1 };
 /* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may
@@ -209,7 +210,13 @@ bounce_status bounce_sync(bounce_ctx *ctx);
    ([N][3] float64, caller order): BONDED, SHORT = sum_j (1-chi) W'_sf d/r (r<r''),
    LONG = sum_j chi W'_sf d/r (r'<r<rc), FULL = sum_j W'_sf d/r (r<rc), RECIP =
    the smooth-PME reciprocal-space gradient plus that of the excluded pairs'
-   -k_e q_i q_j erf(alpha r)/r (Sec. V; needs pme_grid, else BOUNCE_E_ARG).
+   -k_e q_i q_j erf(alpha r)/r (Sec. V; needs pme_grid, else BOUNCE_E_ARG),
+   STEP = the pair part of F_0 (SHORT for BOUNCE, FULL for BAOAB, Sec. IV.A)
+   computed exactly as the next bounce_step will: the integrator's own force
+   list and position mirrors as the steps maintain them (rebuilt first only
+   where that step would rebuild them), and its pair kernel (with FP32 pair
+   arithmetic over the fixed-point position mirror).  The
+   other parts use a separate list built at the current positions.
    Synchronous. */
 bounce_status bounce_compute_gradient(bounce_ctx *ctx, int32_t which, double *grad_dev);
 /* Energies of every replica into out_host[n_replicas][7]:

@@ -13,7 +13,7 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_RECIP,
+from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LONG, G_RECIP, G_STEP,
                    G_SHORT,
                    LIST_CAND, LIST_FORCE, OUTER_NONBONDED, OUTER_RECIP, PAIR_FP32, PAIR_FP64, PH_JA, PH_JB, PH_O, RATE_ATOM,
                    RATE_PAIR, BounceError,
@@ -21,7 +21,7 @@ from ._abi import (BAOAB, BJAOAJB, COUL_BARE, COUL_EWALD, G_BONDED, G_FULL, G_LO
 
 __all__ = ["lib", "Simulation", "DirectEnergy", "make_params", "BounceError", "BJAOAJB", "BAOAB",
            "PAIR_FP32", "PAIR_FP64", "COUL_BARE", "COUL_EWALD", "PH_JA", "PH_O", "PH_JB",
-           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "G_RECIP", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
+           "G_BONDED", "G_SHORT", "G_LONG", "G_FULL", "G_RECIP", "G_STEP", "LIST_FORCE", "LIST_CAND", "RATE_ATOM",
            "RATE_PAIR", "OUTER_RECIP", "OUTER_NONBONDED"]
 
 

@@ -18,7 +18,7 @@ BJAOAJB, BAOAB = 0, 1
 PAIR_FP32, PAIR_FP64 = 0, 1
 COUL_BARE, COUL_EWALD = 0, 1
 PH_JA, PH_O, PH_JB = 0, 1, 2
-G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
+G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP, G_STEP = 1, 2, 4, 8, 16, 32
 OUTER_RECIP, OUTER_NONBONDED = 0, 1
 LIST_FORCE, LIST_CAND = 0, 1
 RATE_ATOM, RATE_PAIR = 0, 1

@@ -93,6 +93,7 @@ struct bounce_ctx {
     std::vector<TypePair<float>> tab_f;     // jump-field pair constants per type pair
     std::vector<TypePair<double>> tab_d;
     int32_t n_cells = 0, fcap = 0, ccap = 0, acap = 0, xcap = 0;
+    bool fixed = false;           // FP32 pair arithmetic: keep the fixed-point position mirror
     // workspace
     char *ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -424,6 +425,18 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
         max_rho = std::max(max_rho, rho);
     }
     c->n_cells = cell_off;
+    // fixed-point position mirror of the FP32 pair kernels: periodic, unit
+    // edge / 2^32 (positions modulo 2^32: the 32-bit difference is the minimum
+    // image); droplet, unit grid extent / 2^30 from the grid origin
+    c->fixed = c->p.pair_precision == BOUNCE_PAIR_FP32;
+    for (RepInfo &ri : c->reps)
+        for (int k = 0; k < 3; ++k) {
+            const double u = ri.periodic ? std::ldexp(ri.box[k], -32)
+                                         : std::ldexp(ri.cw[k] * ri.ncell[k], -30);
+            ri.finv[k] = 1.0 / u;
+            ri.forigin[k] = ri.periodic ? 0.0 : ri.origin[k];
+            ri.funit[k] = (float)u;
+        }
     c->cell_rep.assign(cell_off, 0);
     for (int32_t r = 0; r < R; ++r) {
         int32_t e = r + 1 < R ? c->reps[r + 1].cell_off : cell_off;
@@ -537,7 +550,7 @@ struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w;
-    size_t ls[2][15];
+    size_t ls[2][17];
 };
 
 // wavefront slots of the integrator and jump kernels (4 lanes per atom)
@@ -605,6 +618,9 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
         q[13] = L.take(sizeof(int2) * n);                               // sinfo
         q[14] = L.take(4 * ((size_t)c->n_cells / 1024 + 2));            // scan_part
+        const bool fx = k == 0 && c->fixed;
+        q[15] = fx ? L.take(16 * n) : 0;                                // xf[0]
+        q[16] = fx ? L.take(16 * n) : 0;                                // xf[1]
     }
 }
 
@@ -786,6 +802,9 @@ static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, d
         ls.fcap = k == 0 ? c->fcap : c->acap;
         ls.ccap = k == 0 ? c->ccap : 0;
         ls.n_cells = c->n_cells;
+        const bool fx = k == 0 && c->fixed;
+        ls.xf[0] = fx ? at<int4>(ws, q[15]) : nullptr;
+        ls.xf[1] = fx ? at<int4>(ws, q[16]) : nullptr;
         HIPCHK(c, hipMemsetAsync(ls.cell_count, 0, 4 * (size_t)c->n_cells, sm));
     }
     HIPCHK(c, hipStreamSynchronize(sm));
@@ -1179,12 +1198,31 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
 {
     bounce_status s = ready(c);
     if (s) return s;
-    if (!grad || (which & ~31) || !which) return BOUNCE_E_ARG;
+    if (!grad || (which & ~63) || !which) return BOUNCE_E_ARG;
     if ((which & BOUNCE_G_RECIP) && !c->pme) return fail(c, BOUNCE_E_ARG, "G_RECIP needs pme_grid");
     hipStream_t sm = c->stream;
     const int pairs[3] = {BOUNCE_G_SHORT, BOUNCE_G_LONG, BOUNCE_G_FULL};
     const int modes[3] = {MODE_SHORT, MODE_LONG, MODE_FULL};
     int first = 1;
+    if (which & BOUNCE_G_STEP) {
+        // the integrator's own list and pair kernel, into caller order: the
+        // lists and position mirrors the steps maintain, rebuilt first only
+        // where the next step would rebuild them
+        if (c->built_step < 0 ||
+            (c->step % c->p.rebuild_interval == 0 && c->built_step != c->step)) {
+            enqueue_build(c, 0);
+            c->built_step = c->step;
+            c->host_rebuilds++;
+        }
+        PairArgs a = pair_args(c, c->main, -1);
+        a.far_gate = 0.5 * c->p.skin - 1e-3 > 0.0;
+        a.out = grad;
+        a.out_global = 1;
+        a.accumulate = 0;
+        launch_pair(sm, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
+                    c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
+        first = 0;
+    }
     if (which & (BOUNCE_G_SHORT | BOUNCE_G_LONG | BOUNCE_G_FULL))
         launch_build(sm, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->aux, aux_spec(c), c->d_st);
     for (int k = 0; k < 3; ++k) {

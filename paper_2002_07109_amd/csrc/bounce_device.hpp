@@ -39,6 +39,11 @@ struct RepInfo {
     int32_t n_atoms;
     int32_t cell_off;
     uint64_t key0, key1;   // Philox key (seed, replica)
+    // fixed-point position mirror (FP32 pair arithmetic): x = forigin + n funit,
+    // finv = 1 / funit; periodic: funit = edge / 2^32, forigin = 0
+    double finv[3], forigin[3];
+    float funit[3];
+    float pad_f;
 };
 
 // small device-resident state: step counter, latched status, counters

@@ -23,10 +23,27 @@ struct ListSet {
     int32_t *clist;       // [N][ncls][ccap], each class in canonical order
     int4 *bslot;          // [N][BTMAX] bonded terms of each sorted atom with their
                           //   atoms as sorted positions (x = term code, -1: none); or NULL
+    // FP32 pair arithmetic: the positions of x[] again as fixed-point integers
+    // (x, y, z, type), one unit = funit of the atom's replica, taken modulo 2^32
+    // in a periodic box whose edge is 2^32 units: the difference of two such
+    // integers in 32-bit two's complement is the minimum-image displacement,
+    // exact to the rounding of the two positions (NULL when not kept)
+    int4 *xf[2];
     int32_t fcap, ccap;
     int32_t n_cells;
     int32_t ncls;         // candidate classes: the partner's type (per-type-pair bounds) or one
 };
+
+// fixed-point position of an atom on its replica: periodic, round(x / u) mod 2^32
+// with u = edge / 2^32; droplet, round((x - origin) / u) with u = grid extent / 2^30
+__device__ __forceinline__ int4 fixed_pos(const RepInfo &ri, double x, double y, double z, int32_t type)
+{
+    const int64_t fx = (int64_t)rint((x - ri.forigin[0]) * ri.finv[0]);
+    const int64_t fy = (int64_t)rint((y - ri.forigin[1]) * ri.finv[1]);
+    const int64_t fz = (int64_t)rint((z - ri.forigin[2]) * ri.finv[2]);
+    return make_int4((int32_t)(uint32_t)(uint64_t)fx, (int32_t)(uint32_t)(uint64_t)fy,
+                     (int32_t)(uint32_t)(uint64_t)fz, type);
+}
 
 // most bonded terms (bonds + angles) touching one atom
 constexpr int BTMAX = 8;

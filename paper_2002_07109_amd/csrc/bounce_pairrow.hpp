@@ -92,6 +92,73 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
     }
 }
 
+// The same sum in FP32 pair arithmetic over the fixed-point position mirror:
+// the displacement is the 32-bit difference of two fixed-point positions
+// (minimum image by two's-complement wrap in a periodic box), exact to their
+// rounding, and is converted to A by one FP32 rounding per axis.  Per entry:
+// the index load, one 16-byte gather, integer and FP32 arithmetic only.
+template <int MODE, int G>
+__device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF, const int4 &xi,
+                                                     const float fu[3],
+                                                     const int32_t *__restrict__ row, int32_t nn,
+                                                     int32_t cnt, int32_t cap, int lig, int32_t self,
+                                                     const TypePair<float> *tab_i,
+                                                     const PairGlobals &pg, double &ax, double &ay,
+                                                     double &az)
+{
+    const float alpha = (float)pg.alpha, r_on = (float)pg.r_on, inv_w = (float)pg.inv_w;
+    const float lim = MODE == MODE_SHORT ? (float)pg.r_off : (float)pg.r_cut;
+    const float lim2 = lim * lim;
+    constexpr int U = 4;
+    const int32_t tail = cap - 1 + nn;
+    int32_t pn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t e = lig + u * G;
+        pn[u] = e < cap ? row[e] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t e = lig + u * G;
+        if (e >= cnt) pn[u] = -1;
+        else if (e >= nn) pn[u] = row[tail - e];
+    }
+    for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
+        int32_t pj[U];
+        int4 xj[U];
+        float px = 0.0f, py = 0.0f, pz = 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) pj[u] = pn[u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = XF[pj[u] >= 0 ? pj[u] : self];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t e = e0 + (U + u) * G;
+            pn[u] = e < cnt ? row[row_slot(e, nn, tail)] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t dxf = (int32_t)((uint32_t)xi.x - (uint32_t)xj[u].x);
+            const int32_t dyf = (int32_t)((uint32_t)xi.y - (uint32_t)xj[u].y);
+            const int32_t dzf = (int32_t)((uint32_t)xi.z - (uint32_t)xj[u].z);
+            const float rx = (float)dxf * fu[0], ry = (float)dyf * fu[1], rz = (float)dzf * fu[2];
+            const float r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
+            if (!(r2 < lim2)) continue;
+            const TypePair<float> &tp = tab_i[xj[u].w];
+            float r, rinv;
+            const float dw = pair_dw<float>(r2, tp, alpha, pg.coulomb, r, rinv);
+            const float f = MODE == MODE_SHORT ? (1.0f - switch_chi<float>(r, r_on, inv_w)) * dw * rinv
+                                               : dw * rinv;
+            px += f * rx;
+            py += f * ry;
+            pz += f * rz;
+        }
+        ax += (double)px;
+        ay += (double)py;
+        az += (double)pz;
+    }
+}
+
 // sum over the G lanes of a group (fixed butterfly: deterministic)
 template <int G>
 __device__ __forceinline__ double group_sum(double v)

@@ -133,7 +133,8 @@ __device__ __forceinline__ void wave_sync()
 // One wavefront per cell: order the cell's atoms by caller id (rank sort over
 // the lanes; a serial insertion sort above 64 atoms) and fill the mirror.
 __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double *__restrict__ pos,
-                                                  Topo tp, ListSet ls, const DevState *st,
+                                                  const RepInfo *__restrict__ reps, Topo tp,
+                                                  ListSet ls, const DevState *st,
                                                   int32_t mirror_sel, int32_t step_off)
 {
     const int lane = threadIdx.x & 63;
@@ -164,6 +165,7 @@ __global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double 
         ls.sinfo[i] = make_int2(g, tp.rep_of[g]);
         const double *x = pos + 3 * (int64_t)g;
         X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
+        if (ls.xf[par]) ls.xf[par][i] = fixed_pos(reps[tp.rep_of[g]], x[0], x[1], x[2], tp.type[g]);
     }
 }
 
@@ -545,7 +547,7 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_scan_fin, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
     hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
-                       pos, tp, ls, st, bs.mirror_sel, bs.step_off);
+                       pos, reps, tp, ls, st, bs.mirror_sel, bs.step_off);
     // candidate classes rounded up to 1, 2, 4 or 8 (one class: no per-class appends)
     const int nc = bs.want_cand ? ls.ncls : 1;
     const dim3 grid(ls.n_cells), block(64 * LB);

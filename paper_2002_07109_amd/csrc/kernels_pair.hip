@@ -76,8 +76,9 @@ template <>
 __device__ __forceinline__ const TypePair<double> *pair_table<double>(const PairArgs &a) { return a.tab_d; }
 
 // G lanes per atom (4, 8, 16 or 32; chosen by the autotuner).  ONE: a single
-// replica, whose box the force modes keep in scalar registers.
-template <typename R, int MODE, int G, bool ONE = false>
+// replica, whose box the force modes keep in scalar registers.  FIXED: the
+// force modes over the fixed-point position mirror (FP32 pair arithmetic).
+template <typename R, int MODE, int G, bool ONE = false, bool FIXED = false>
 __global__ void __launch_bounds__(256) k_pair(PairArgs a)
 {
     __shared__ TypePair<R> tab[MAXT * MAXT];
@@ -131,7 +132,14 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const bool near_only = a.far_gate && a.st->far_flag == 0u;
         const int32_t nn = fc.x, cnt = near_only ? fc.x : fc.x + fc.y;
         const int32_t tail = cap - 1 + nn;
-        if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
+        if constexpr (FIXED) {
+            const RepInfo &rp = ONE ? a.reps[0] : a.reps[si.y];
+            const float fu[3] = {rp.funit[0], rp.funit[1], rp.funit[2]};
+            const int4 *__restrict__ XF = a.ls.xf[par];
+            pair_force_row_fixed<MODE, G>(XF, XF[s], fu, row, nn, cnt, cap, lig, s,
+                                          reinterpret_cast<const TypePair<float> *>(tab) + ti * nt,
+                                          a.pg, ax, ay, az);
+        } else if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
             pair_force_row<R, MODE, G>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
         } else {
         // energies and parameter-gradient bases: U entries per lane in flight
@@ -254,6 +262,17 @@ template <typename R, int G>
 static void launch_pair_g(hipStream_t sm, int mode, const PairArgs &a)
 {
     dim3 grid(((int64_t)a.n * G + 255) / 256), block(256);
+    if (a.ls.xf[0] && (mode == MODE_SHORT || mode == MODE_FULL)) {
+        // the fixed-point mirror exists only with FP32 pair arithmetic
+        if (mode == MODE_SHORT) {
+            if (a.single_rep) hipLaunchKernelGGL((k_pair<float, MODE_SHORT, G, true, true>), grid, block, 0, sm, a);
+            else hipLaunchKernelGGL((k_pair<float, MODE_SHORT, G, false, true>), grid, block, 0, sm, a);
+        } else {
+            if (a.single_rep) hipLaunchKernelGGL((k_pair<float, MODE_FULL, G, true, true>), grid, block, 0, sm, a);
+            else hipLaunchKernelGGL((k_pair<float, MODE_FULL, G, false, true>), grid, block, 0, sm, a);
+        }
+        return;
+    }
     switch (mode) {
         case MODE_SHORT:
             if (a.single_rep) hipLaunchKernelGGL((k_pair<R, MODE_SHORT, G, true>), grid, block, 0, sm, a);

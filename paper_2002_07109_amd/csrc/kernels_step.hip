@@ -553,6 +553,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
             a.pos[3 * (int64_t)g + 1] = q[1];
             a.pos[3 * (int64_t)g + 2] = q[2];
             Y[s] = make_double4(q[0], q[1], q[2], xi.w);
+            if (a.ls.xf[0]) a.ls.xf[par ^ 1][s] = fixed_pos(ri, q[0], q[1], q[2], mirror_type(xi.w));
         }
         a.vel[3 * (int64_t)g] = v[0];
         a.vel[3 * (int64_t)g + 1] = v[1];

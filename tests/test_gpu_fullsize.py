@@ -43,6 +43,32 @@ def test_c1_gradients_sampled(orc, c1, sample, fp64):
         assert err < tol, (gbit, err)
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_c1_step_pair_force_sampled(orc, sample, fp64, integrator):
+    """The integrator's own pair part of F_0 (the fixed-point mirror in FP32) at full
+    size after 5 steps from the relaxed box, on the sampled atoms, against the
+    oracle at its own positions after the same 5 steps: BOUNCE's short-range
+    force and BAOAB's full one."""
+    import paper_2002_07109_amd as B
+    c1 = relaxed_box24k()
+    cfg = dict(BOX, integrator=integrator)
+    sim = gpu_sim(c1, cfg, fp64=fp64, use_graph=True)
+    sim.step(5)
+    sim.sync()
+    g = sim.gradient(B.G_STEP).cpu().numpy()[sample]
+    p = oracle_params(orc, c1, cfg)
+    topo = orc.Topology.from_system(c1)
+    o5 = orc.run(p, topo, c1.pos, c1.vel, 0, 5)
+    assert o5["status"] == 0
+    obit = orc.G_SHORT if integrator == 0 else orc.G_FULL
+    o = np.stack([orc.gradient_atom(p, topo, o5["q"], obit, int(i)) for i in sample])
+    rms = np.sqrt(np.mean(np.sum(o * o, 1)))
+    err = np.max(np.linalg.norm(g - o, axis=1)) / rms
+    print(f"24k step pair force fp64={fp64}: {err:.3e}")
+    assert err < (1e-10 if fp64 else 1e-5), err
+
+
 def test_c1_candidate_rows_bit_exact(orc, c1, sample):
     import paper_2002_07109_amd as B
     sim = gpu_sim(c1, BOX, fp64=False)

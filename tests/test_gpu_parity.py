@@ -82,6 +82,40 @@ def test_gradients(orc, droplet, box, which, fp64):
         assert err < (1e-13 if gbit == B.G_BONDED else tol), (gbit, err)
 
 
+@pytest.mark.parametrize("integrator", [0, 1])
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_step_pair_force(orc, droplet, box, which, fp64, integrator):
+    """The pair part of F_0 exactly as the integrator computes it (its own
+    force list and pair kernel: with FP32 pair arithmetic over the fixed-point
+    position mirror) against the oracle's SHORT (BOUNCE) or
+    FULL (BAOAB) pair gradient: from a fresh build at jittered positions, and
+    after 7 steps with the list and position mirrors the steps maintained (the
+    oracle at its own positions after the same 7 steps)."""
+    import paper_2002_07109_amd as B
+    sys, cfg = _sys(droplet, box, which)
+    cfg = dict(cfg, integrator=integrator)
+    p = oracle_params(orc, sys, cfg)
+    topo = orc.Topology.from_system(sys)
+    obit = orc.G_SHORT if integrator == 0 else orc.G_FULL
+    sim = gpu_sim(sys, cfg, fp64=fp64)
+    q = jitter_positions(sys.pos, 0.05, seed=11)
+    sim.set_state(pos=q)
+    g = sim.gradient(B.G_STEP).cpu().numpy()
+    err = rel_err(g, orc.gradient(p, topo, q, obit))
+    print(f"{which} fp64={fp64} integrator={integrator}: step pair force {err:.3e}")
+    assert err < (1e-11 if fp64 else 1e-5), err
+    sim = gpu_sim(sys, cfg, fp64=fp64)
+    sim.step(7)
+    sim.sync()
+    g7 = sim.gradient(B.G_STEP).cpu().numpy()
+    o7 = orc.run(p, topo, sys.pos, sys.vel, 0, 7)
+    assert o7["status"] == 0
+    err7 = rel_err(g7, orc.gradient(p, topo, o7["q"], obit))
+    print(f"  after 7 steps: {err7:.3e}")
+    assert err7 < (1e-10 if fp64 else 1e-5), err7
+
+
 @pytest.mark.parametrize("which", ["drop", "box"])
 def test_energies(orc, droplet, box, which):
     sys, cfg = _sys(droplet, box, which)
@@ -201,11 +235,14 @@ def assert_fp32_events_follow_oracle(ev, o_events, tol=1e-5):
     return before, div
 
 
-def test_trajectory_fp32_events_and_positions(orc, droplet):
-    """FP32 pair arithmetic on the proposal-heavy droplet (~3,000 proposals a
-    step): the event log follows the FP64 oracle up to its first near-tie, and
-    positions after 100 steps stay close."""
-    sim, o = _traj(orc, droplet, DROPLET, 100, fp64=False)
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_trajectory_fp32_events_and_positions(orc, droplet, box, which):
+    """FP32 pair arithmetic (fixed-point position mirror) on the proposal-heavy droplet
+    (~3,000 proposals a step) and on the periodic box: the event log follows
+    the FP64 oracle up to its first near-tie, and positions after 100 steps
+    stay close."""
+    sys, cfg = _sys(droplet, box, which)
+    sim, o = _traj(orc, sys, cfg, 100, fp64=False)
     dq = np.abs(sim.pos.cpu().numpy() - o["q"]).max()
     ev, n = sim.events()
     same, div = assert_fp32_events_follow_oracle(ev, o["events"])
@@ -218,9 +255,11 @@ def test_trajectory_fp32_events_and_positions(orc, droplet):
         assert dq < 1e-2, dq
 
 
-def test_graph_replay_equals_direct_launches(orc, box):
-    sa = gpu_sim(box, BOX, fp64=False, use_graph=False)
-    sb = gpu_sim(box, BOX, fp64=False, use_graph=True)
+@pytest.mark.parametrize("which", ["drop", "box"])
+def test_graph_replay_equals_direct_launches(orc, droplet, box, which):
+    sys, cfg = _sys(droplet, box, which)
+    sa = gpu_sim(sys, cfg, fp64=False, use_graph=False)
+    sb = gpu_sim(sys, cfg, fp64=False, use_graph=True)
     for sim in (sa, sb):
         sim.step(35)
         sim.sync()
