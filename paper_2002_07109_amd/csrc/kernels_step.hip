@@ -102,7 +102,14 @@ __device__ __forceinline__ void load_partners(const StepArgs &a, int32_t s, int 
     const int32_t nc = a.ls.ncls;
     P.row = a.ls.clist + (int64_t)s * nc * a.ls.ccap;
     P.cap = a.ls.ccap;
-    P.unit = a.Lunit[ti];
+    // the type's bound unit from the whole (uniform, scalar-loaded) table, so
+    // that it does not wait for a load indexed by the atom's type
+    P.unit = 0.0;
+#pragma unroll
+    for (int b = 0; b < MAXT; ++b) {
+        const double ub = a.Lunit[b];
+        if (b == ti) P.unit = ub;
+    }
     P.W = 0;
 #pragma unroll
     for (int b = 0; b < KC; ++b) {
@@ -281,16 +288,19 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
     // one class: every partner has the atom's bound, no need to pass it around
     const double L1 = (double)(1u << WEIGHT_BITS) * PT.unit;
     const int32_t n_pre = min(min(M, M_pre), NPRE);
+    // (most wavefronts have no proposal at all and skip the exchange)
+    if (__any(n_pre > 0)) {
 #pragma unroll
-    for (int t = 0; t < NPRE; ++t) {
-        const int src = t == 0 ? pre_lane1 : pre_lane2;
-        const double Fx = group_get<GS>(pre.F[0], src), Fy = group_get<GS>(pre.F[1], src),
-                     Fz = group_get<GS>(pre.F[2], src);
-        const double ut = group_get<GS>(pre.u, src);
-        const double lb = KC == 1 ? L1 : group_get<GS>(pre.lb, src);
-        const int32_t pt = group_get_i32<GS>(pre.p, src);
-        if (t < n_pre)
-            apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+        for (int t = 0; t < NPRE; ++t) {
+            const int src = t == 0 ? pre_lane1 : pre_lane2;
+            const double Fx = group_get<GS>(pre.F[0], src), Fy = group_get<GS>(pre.F[1], src),
+                         Fz = group_get<GS>(pre.F[2], src);
+            const double ut = group_get<GS>(pre.u, src);
+            const double lb = KC == 1 ? L1 : group_get<GS>(pre.lb, src);
+            const int32_t pt = group_get_i32<GS>(pre.p, src);
+            if (t < n_pre)
+                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+        }
     }
     for (int32_t k0 = n_pre + 1; __any(k0 <= M); k0 += PB) {
         const int32_t k = k0 + sub;
@@ -322,6 +332,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t)
 {
+    if (!__any(active && (t.prop | t.acc | t.bound))) return;     // nothing to add (uniform)
     if (a.single_rep) {
         // one replica: each wavefront owns a slot of the per-wavefront counters
         // (launches of one stream never overlap), so no atomics are needed
@@ -385,15 +396,10 @@ __device__ __forceinline__ void outer_kick(const StepArgs &a, int32_t s, int32_t
 template <typename R, bool BOUNCE, int KC = 1>
 __global__ void __launch_bounds__(256) k_step(StepArgs a)
 {
-    __shared__ TypePair<R> ftab[MAXT * MAXT];
-    const int nt = a.pg.n_types;
-    if (BOUNCE) {
-        const TypePair<R> *tab = jump_table<R>(a);
-        for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) ftab[k] = tab[k];
-    }
-    // at entry: a barrier later in the kernel would make the workgroup's
-    // wavefronts wait for each other's load chains
-    __syncthreads();
+    // the jump field's pair constants are read where a proposal needs them
+    // (cached global loads): a copy into LDS would put a load and a barrier
+    // ahead of every wavefront's work
+    const TypePair<R> *__restrict__ ftab = jump_table<R>(a);
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = a.st->step + a.step_off;
     const int32_t par = (int32_t)(n & 1);
