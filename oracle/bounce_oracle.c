@@ -124,39 +124,96 @@ void orc_pair_wsf(const orc_params *p, int a, int b, double r, double *w, double
     *dw = du - duc;
 }
 
-/* switch chi: 0 below r', 1 above r'', quintic smoothstep between (C^2) */
-double orc_chi(const orc_params *p, double r)
+/* the two parts of W'_sf(r): Coulomb qq (g'(r) - g'(rc)) and Lennard-Jones
+   LJ'(r) - LJ'(rc); zero at and beyond the cutoff */
+void orc_pair_dw_parts(const orc_params *p, int a, int b, double r, double *dwc, double *dwv)
 {
-    double x = (r - p->r_on) / (p->r_off - p->r_on);
+    *dwc = *dwv = 0.0;
+    if (r >= p->r_cut) return;
+    double qq, eps, sig, g, dg, gc, dgc, u, du, uc, duc;
+    mix(p, a, b, &qq, &eps, &sig);
+    coul_g(p, r, &g, &dg);
+    coul_g(p, p->r_cut, &gc, &dgc);
+    lj(eps, sig, r, &u, &du);
+    lj(eps, sig, p->r_cut, &uc, &duc);
+    *dwc = qq * (dg - dgc);
+    *dwv = du - duc;
+}
+
+/* quintic smoothstep switch: 0 below lo, 1 above hi (C^2) */
+static double smoothstep(double lo, double hi, double r)
+{
+    double x = (r - lo) / (hi - lo);
     if (x <= 0.0) return 0.0;
     if (x >= 1.0) return 1.0;
     return x * x * x * (10.0 - 15.0 * x + 6.0 * x * x);
 }
 
+/* switch chi: 0 below r', 1 above r'', quintic smoothstep between (C^2) */
+double orc_chi(const orc_params *p, double r) { return smoothstep(p->r_on, p->r_off, r); }
+
+int orc_n_mech(const orc_params *p) { return p->jump_split ? 2 : 1; }
+
+/* the switch of jump mechanism m: the Lennard-Jones one has its own window
+   when the mechanisms are split */
+double orc_chi_mech(const orc_params *p, int m, double r)
+{
+    return m == 1 ? smoothstep(p->r_on_lj, p->r_off_lj, r) : orc_chi(p, r);
+}
+
+static double r_on_mech(const orc_params *p, int m) { return m == 1 ? p->r_on_lj : p->r_on; }
+
+/* the short-range part reaches to r'' (the larger of the two with split
+   mechanisms); the jump fields start at r' (the smaller of the two) */
+static double r_short(const orc_params *p)
+{
+    return p->jump_split && p->r_off_lj > p->r_off ? p->r_off_lj : p->r_off;
+}
+
+static double r_long(const orc_params *p)
+{
+    return p->jump_split && p->r_on_lj < p->r_on ? p->r_on_lj : p->r_on;
+}
+
+/* the pair field of mechanism m along d/r, as the scalar s with F = s d / r:
+   combined chi W'_sf; split: chi_C W'_C or chi_V W'_V (zero outside (r'_m, rc)) */
+static double mech_field(const orc_params *p, int m, int a, int b, double r)
+{
+    if (!(r > r_on_mech(p, m) && r < p->r_cut)) return 0.0;
+    if (!p->jump_split) {
+        double w, dw;
+        orc_pair_wsf(p, a, b, r, &w, &dw);
+        return orc_chi(p, r) * dw;
+    }
+    double dwc, dwv;
+    orc_pair_dw_parts(p, a, b, r, &dwc, &dwv);
+    return orc_chi_mech(p, m, r) * (m == 1 ? dwv : dwc);
+}
+
 /* Sec. IV.A: |F_ij| <= |chi W'|_inf computed numerically once; here the sup
-   over a 1e-4 A grid of [r', rc] times (1 + 1e-3) per type pair. */
+   over a 1e-4 A grid of [r'_m, rc] times (1 + 1e-3) per mechanism and type
+   pair. */
 void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a)
 {
     const double h = 1e-4;
-    int nt = p->n_types;
-    for (int a = 0; a < nt; ++a) {
-        L_a[a] = 0.0;
-        for (int b = 0; b < nt; ++b) {
-            double m = 0.0;
-            for (long k = 0;; ++k) {
-                double r = p->r_on + (double)k * h;
-                if (r >= p->r_cut) break;
-                double w, dw;
-                orc_pair_wsf(p, a, b, r, &w, &dw);
-                double f = fabs(orc_chi(p, r) * dw);
-                if (f > m) m = f;
+    const int nt = p->n_types, nm = orc_n_mech(p);
+    for (int a = 0; a < nt; ++a) L_a[a] = 0.0;
+    for (int m = 0; m < nm; ++m)
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b) {
+                double mx = 0.0;
+                for (long k = 0;; ++k) {
+                    double r = r_on_mech(p, m) + (double)k * h;
+                    if (r >= p->r_cut) break;
+                    double f = fabs(mech_field(p, m, a, b, r));
+                    if (f > mx) mx = f;
+                }
+                L_ab[(m * nt + a) * nt + b] = mx * (1.0 + 1e-3);
             }
-            L_ab[a * nt + b] = m * (1.0 + 1e-3);
-        }
-    }
-    for (int a = 0; a < nt; ++a)
-        for (int b = 0; b < nt; ++b)
-            if (L_ab[a * nt + b] > L_a[a]) L_a[a] = L_ab[a * nt + b];
+    for (int m = 0; m < nm; ++m)
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b)
+                if (L_ab[(m * nt + a) * nt + b] > L_a[a]) L_a[a] = L_ab[(m * nt + a) * nt + b];
 }
 
 /* The bounds as integer weights per atom type a: ORC_RATE_ATOM gives every
@@ -168,18 +225,20 @@ void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a)
    of row a is bound_scale L_a 2^-20. */
 void orc_rate_weights(const orc_params *p, uint32_t *Lq, double *unit)
 {
-    double L_ab[ORC_MAXT * ORC_MAXT], L_a[ORC_MAXT];
-    const int nt = p->n_types;
+    double L_ab[2 * ORC_MAXT * ORC_MAXT], L_a[ORC_MAXT];
+    const int nt = p->n_types, nm = orc_n_mech(p);
     const double one = (double)(1u << ORC_WEIGHT_BITS);
+    const int per_class = p->rate_mode == ORC_RATE_PAIR || p->jump_split;
     orc_rate_bounds(p, L_ab, L_a);
     for (int a = 0; a < nt; ++a) {
         unit[a] = p->bound_scale * L_a[a] / one;
-        for (int b = 0; b < nt; ++b) {
-            uint32_t w = 1u << ORC_WEIGHT_BITS;
-            if (p->rate_mode == ORC_RATE_PAIR && L_a[a] > 0.0)
-                w = (uint32_t)ceil(L_ab[a * nt + b] / L_a[a] * one - ORC_WEIGHT_SLACK);
-            Lq[a * nt + b] = w;
-        }
+        for (int m = 0; m < nm; ++m)
+            for (int b = 0; b < nt; ++b) {
+                uint32_t w = 1u << ORC_WEIGHT_BITS;
+                if (per_class && L_a[a] > 0.0)
+                    w = (uint32_t)ceil(L_ab[(m * nt + a) * nt + b] / L_a[a] * one - ORC_WEIGHT_SLACK);
+                Lq[a * nm * nt + m * nt + b] = w;
+            }
     }
 }
 
@@ -358,10 +417,26 @@ static void pair_grad(const orc_params *p, int which, int ti, int tj, const doub
     if (r >= p->r_cut) return;
     double w, dw;
     orc_pair_wsf(p, ti, tj, r, &w, &dw);
-    double chi = orc_chi(p, r);
     double s = 0.0;
-    if ((which & ORC_G_SHORT) && r < p->r_off) s += (1.0 - chi) * dw;
-    if ((which & ORC_G_LONG) && r > p->r_on) s += chi * dw;
+    if (!p->jump_split) {
+        double chi = orc_chi(p, r);
+        if ((which & ORC_G_SHORT) && r < p->r_off) s += (1.0 - chi) * dw;
+        if ((which & ORC_G_LONG) && r > p->r_on) s += chi * dw;
+    } else {
+        /* each part with its own switch: (1 - chi_C) W'_C + (1 - chi_V) W'_V,
+           and the long-range fields of the two jump mechanisms */
+        double dwc, dwv;
+        orc_pair_dw_parts(p, ti, tj, r, &dwc, &dwv);
+        double chc = orc_chi_mech(p, 0, r), chv = orc_chi_mech(p, 1, r);
+        if (which & ORC_G_SHORT) {
+            if (r < p->r_off) s += (1.0 - chc) * dwc;
+            if (r < p->r_off_lj) s += (1.0 - chv) * dwv;
+        }
+        if (which & ORC_G_LONG) {
+            if (r > p->r_on) s += chc * dwc;
+            if (r > p->r_on_lj) s += chv * dwv;
+        }
+    }
     if (which & ORC_G_FULL) s += dw;
     for (int k = 0; k < 3; ++k) g[k] = s * d[k] / r;
 }
@@ -511,7 +586,7 @@ void orc_energies(const orc_params *p, const orc_topology *t, const double *q, c
 /* J step (Sec. IV.B, with Sec. V partners and Sec. III.D thinning)          */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    uint32_t Lq[ORC_MAXT * ORC_MAXT];
+    uint32_t Lq[2 * ORC_MAXT * ORC_MAXT];
     double unit[ORC_MAXT];
     double beta;
 } jump_consts;
@@ -533,10 +608,14 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
     int status = ORC_OK;
     const int nt = p->n_types, a = t->type[i];
     double v0 = sqrt(vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]);
-    /* the candidates grouped by class -- the partner's type under ORC_RATE_PAIR,
-       a single class under ORC_RATE_ATOM -- each class in canonical order; a
-       partner of class b has the bound Lq[a][b] * unit[a] */
-    const int ncls = p->rate_mode == ORC_RATE_PAIR ? nt : 1;
+    /* the candidates grouped by the partner's type under ORC_RATE_PAIR or
+       jump_split (a single group under ORC_RATE_ATOM), each group in canonical
+       order; a proposal class k is a (mechanism m, group b) pair, k = m ncls + b,
+       and a partner of class k has the bound Lq[a][k] * unit[a] */
+    const int nm = orc_n_mech(p);
+    const int ncls = (p->rate_mode == ORC_RATE_PAIR || p->jump_split) ? nt : 1;
+    const int nw = nm * ncls;
+    const uint32_t *Lqa = jc->Lq + a * nm * nt;
     int32_t ncl[ORC_MAXT] = {0};
     int32_t *grp = (int32_t *)malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
     int32_t *cls_start[ORC_MAXT];
@@ -549,8 +628,8 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
             ncl[b] = (int32_t)(grp + k - cls_start[b]);
         }
     }
-    uint64_t W = 0;     /* sum over candidates of their integer weights */
-    for (int b = 0; b < ncls; ++b) W += (uint64_t)ncl[b] * jc->Lq[a * nt + b];
+    uint64_t W = 0;     /* sum over candidates and mechanisms of their integer weights */
+    for (int k = 0; k < nw; ++k) W += (uint64_t)ncl[k % ncls] * Lqa[k];
     const double unit = jc->unit[a];
     if (nc == 0 || v0 == 0.0 || W == 0 || unit == 0.0) {
         free(grp);
@@ -574,27 +653,25 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
     }
     for (int64_t k = 1; k <= M; ++k) {
         draw(p, step, phase, i, (uint64_t)k, w);
-        /* partner j with probability weight_j / W: X uniform on [0, W), then
-           the class whose weight range holds X and the member within it */
+        /* (mechanism, partner) with probability weight / W: X uniform on
+           [0, W), then the class whose weight range holds X and the member
+           within it */
         uint64_t X = orc_umulh(w[0], W), lo = 0;
-        int b = 0;
-        while (X >= lo + (uint64_t)ncl[b] * jc->Lq[a * nt + b]) {
-            lo += (uint64_t)ncl[b] * jc->Lq[a * nt + b];
-            ++b;
+        int cls = 0;
+        while (X >= lo + (uint64_t)ncl[cls % ncls] * Lqa[cls]) {
+            lo += (uint64_t)ncl[cls % ncls] * Lqa[cls];
+            ++cls;
         }
-        int32_t j = cls_start[b][(X - lo) / jc->Lq[a * nt + b]];
-        const double L = (double)jc->Lq[a * nt + b] * unit;   /* this proposal's bound */
+        const int mech = cls / ncls;
+        int32_t j = cls_start[cls % ncls][(X - lo) / Lqa[cls]];
+        const double L = (double)Lqa[cls] * unit;   /* this proposal's bound */
         double u = orc_u01(w[1]);
         double d[3], F[3];
         min_image(p, q + 3 * i, q + 3 * j, d);
         double r = sqrt(norm2(d));
-        F[0] = F[1] = F[2] = 0.0;
-        if (r > p->r_on && r < p->r_cut) {
-            double wsf, dwsf;
-            orc_pair_wsf(p, t->type[i], t->type[j], r, &wsf, &dwsf);
-            double s = orc_chi(p, r) * dwsf / r;
-            for (int c = 0; c < 3; ++c) F[c] = s * d[c];
-        }
+        /* the mechanism's long-range field chi W' d / r (zero outside (r'_m, rc)) */
+        const double fs = mech_field(p, mech, t->type[i], t->type[j], r);
+        for (int c = 0; c < 3; ++c) F[c] = fs * d[c] / r;
         double s = vi[0] * F[0] + vi[1] * F[1] + vi[2] * F[2];
         /* U < lambda / lambda* with lambda = beta max(0, v.F), lambda* = beta |v| L */
         int acc = (u * v0 * L) < s;
@@ -612,7 +689,7 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
         if (ev && *n_ev < ev_cap) {
             orc_event *e = &ev[*n_ev];
             e->step = step; e->phase = phase; e->atom = i; e->k = (int32_t)k;
-            e->partner = j; e->accepted = acc; e->pad = 0;
+            e->partner = j; e->accepted = acc; e->mech = mech;
             e->margin = u * v0 * L - s;
             e->scale = v0 * sqrt(norm2(F));
         }
@@ -655,7 +732,7 @@ static int build_run_lists(const orc_params *p, const orc_topology *t, const dou
     int32_t n = t->n_atoms;
     int s = orc_sort_order(p, n, q, L->order, L->cell);
     if (s != ORC_OK) return s;
-    double rf = (p->integrator == ORC_BOUNCE ? p->r_off : p->r_cut) + p->skin;
+    double rf = (p->integrator == ORC_BOUNCE ? r_short(p) : p->r_cut) + p->skin;
     free(L->s_col); free(L->c_col);
     L->s_col = NULL; L->c_col = NULL;
     int64_t ns = orc_build_list(p, t, q, 0.0, rf, L->order, L->s_ptr, NULL, 0);
@@ -663,7 +740,7 @@ static int build_run_lists(const orc_params *p, const orc_topology *t, const dou
     L->s_col = malloc(sizeof(int32_t) * (size_t)(L->s_ptr[n] + 1));
     orc_build_list(p, t, q, 0.0, rf, L->order, L->s_ptr, L->s_col, L->s_ptr[n]);
     if (p->integrator == ORC_BOUNCE) {
-        double rmin = p->r_on - p->skin, rmax = p->r_cut + p->skin;
+        double rmin = r_long(p) - p->skin, rmax = p->r_cut + p->skin;
         orc_build_list(p, t, q, rmin, rmax, L->order, L->c_ptr, NULL, 0);
         L->c_col = malloc(sizeof(int32_t) * (size_t)(L->c_ptr[n] + 1));
         orc_build_list(p, t, q, rmin, rmax, L->order, L->c_ptr, L->c_col, L->c_ptr[n]);
@@ -681,7 +758,7 @@ static void grad_parts(const orc_params *p, const orc_topology *t, const double 
                        const run_lists *L, double *g, orc_counters *cnt, int pair, int bonded)
 {
     int which = p->integrator == ORC_BOUNCE ? ORC_G_SHORT : ORC_G_FULL;
-    double rlim = p->integrator == ORC_BOUNCE ? p->r_off : p->r_cut;
+    double rlim = p->integrator == ORC_BOUNCE ? r_short(p) : p->r_cut;
     int64_t evals = 0;
 #pragma omp parallel for reduction(+ : evals) schedule(dynamic, 16)
     for (int32_t i = 0; i < t->n_atoms; ++i) {

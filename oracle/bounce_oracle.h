@@ -84,6 +84,15 @@ typedef struct {
     int32_t pme_order;
     int32_t respa_m;
     int32_t respa_outer;
+    /* jump_split = 1: the long-range part of every pair is carried by two jump
+       mechanisms of its own (Sec. V treats the Coulomb and the van der Waals
+       long-range forces as jumps, and Sec. VI reports the VdW jumps apart):
+       Coulomb (mechanism 0) with the switch on [r_on, r_off], Lennard-Jones
+       (mechanism 1) with its own switch on [r_on_lj, r_off_lj]; each has its own
+       bound per pair of types, L_C(a,b) and L_V(a,b), and the per-(mechanism,
+       partner type) clocks are superposed as with ORC_RATE_PAIR */
+    int32_t jump_split;
+    double r_on_lj, r_off_lj;
 } orc_params;
 
 enum { ORC_OUTER_RECIP = 0, ORC_OUTER_NONBONDED = 1 };
@@ -109,7 +118,8 @@ typedef struct {
    near-tie of the accept test from a real disagreement */
 typedef struct {
     int64_t step;
-    int32_t phase, atom, k, partner, accepted, pad;
+    int32_t phase, atom, k, partner, accepted;
+    int32_t mech;      /* jump mechanism: 0 (Coulomb, or the combined one), 1 (Lennard-Jones) */
     double margin, scale;
 } orc_event;
 
@@ -122,11 +132,19 @@ uint64_t orc_umulh(uint64_t a, uint64_t b);
 void orc_pair_u(const orc_params *p, int a, int b, double r, double *u, double *du);
 void orc_pair_wsf(const orc_params *p, int a, int b, double r, double *w, double *dw);
 double orc_chi(const orc_params *p, double r);
-/* L_ab >= sup |chi W'_sf| per type pair (n_types x n_types) and L_a = max_b L_ab */
+/* the Coulomb and Lennard-Jones parts of W'_sf (their sum is orc_pair_wsf's dw) */
+void orc_pair_dw_parts(const orc_params *p, int a, int b, double r, double *dwc, double *dwv);
+/* switch of mechanism m (0: Coulomb or combined, 1: Lennard-Jones with jump_split) */
+double orc_chi_mech(const orc_params *p, int m, double r);
+/* number of jump mechanisms per pair: 2 with jump_split, else 1 */
+int orc_n_mech(const orc_params *p);
+/* L[m][a][b] >= sup |chi_m W'_m| per mechanism and type pair (n_mech x n_types x
+   n_types; the combined mechanism: chi W'_sf) and L_a = max over m, b */
 void orc_rate_bounds(const orc_params *p, double *L_ab, double *L_a);
-/* integer bound weights Lq_ab = ceil(2^20 L_ab / L_a - 1e-4) (n_types x n_types) and
-   the unit of each row, bound_scale L_a 2^-20: the bound of pair type ab is
-   Lq_ab * unit_a (ORC_RATE_ATOM uses Lq_ab = 2^20 for every b) */
+/* integer bound weights Lq[a][m n_types + b] = ceil(2^20 L[m][a][b] / L_a - 1e-4)
+   (n_types x n_mech n_types) and the unit of each row, bound_scale L_a 2^-20:
+   the bound of a partner of type b under mechanism m is Lq * unit_a
+   (ORC_RATE_ATOM without jump_split: Lq = 2^20 for every b) */
 void orc_rate_weights(const orc_params *p, uint32_t *Lq, double *unit);
 /* reflection of v on F (scalar mass) */
 void orc_reflect(const double v[3], const double F[3], double out[3]);

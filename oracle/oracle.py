@@ -53,7 +53,8 @@ class Params(C.Structure):
                 ("rate_mode", C.c_int32), ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("charge", C.c_double * MAXT), ("eps", C.c_double * MAXT),
                 ("sigma", C.c_double * MAXT), ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32),
-                ("respa_m", C.c_int32), ("respa_outer", C.c_int32)]
+                ("respa_m", C.c_int32), ("respa_outer", C.c_int32), ("jump_split", C.c_int32),
+                ("r_on_lj", C.c_double), ("r_off_lj", C.c_double)]
 
 
 class Topo(C.Structure):
@@ -75,7 +76,7 @@ class Counters(C.Structure):
 
 EVENT_DTYPE = np.dtype([("step", np.int64), ("phase", np.int32), ("atom", np.int32),
                         ("k", np.int32), ("partner", np.int32), ("accepted", np.int32),
-                        ("pad", np.int32), ("margin", np.float64), ("scale", np.float64)])
+                        ("mech", np.int32), ("margin", np.float64), ("scale", np.float64)])
 
 _lib = None
 
@@ -129,7 +130,7 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
                 rebuild_interval=10, seed=0, replica=0, bound_scale=1.0, max_proposals=100000,
                 charge=None, eps=None, sigma=None, periodic=None, box=None, cell_size=None,
                 grid_origin=None, grid_dims=None, rate_mode=RATE_ATOM, pme_grid=None, pme_order=5,
-                respa_m=0, respa_outer=0):
+                respa_m=0, respa_outer=0, jump_split=0, r_on_lj=None, r_off_lj=None):
     """Parameters for the oracle; geometry defaults are taken from a WaterSystem."""
     p = Params()
     p.integrator = integrator
@@ -148,6 +149,11 @@ def make_params(sys=None, *, integrator=BOUNCE, coulomb=None, dt=1.0, gamma=1e-3
     for k in range(3):
         p.pme_grid[k] = int(pme_grid[k]) if pme_grid is not None else 0
     p.pme_order, p.respa_m, p.respa_outer = int(pme_order), int(respa_m), int(respa_outer)
+    # separate Coulomb and Lennard-Jones jump mechanisms; the LJ switch window
+    # defaults to the Coulomb one
+    p.jump_split = int(jump_split)
+    p.r_on_lj = r_on if r_on_lj is None else r_on_lj
+    p.r_off_lj = r_off if r_off_lj is None else r_off_lj
     if sys is not None:
         from workloads import tip3p_params
         ff = tip3p_params()
@@ -237,19 +243,21 @@ def chi(p, r):
 
 
 def rate_bounds(p):
-    nt = p.n_types
-    L_ab = np.zeros(nt * nt)
+    """(L_ab, L_a): L_ab[a, b] ([m, a, b] with separate mechanisms) and L_a."""
+    nt, nm = p.n_types, 2 if p.jump_split else 1
+    L_ab = np.zeros(nm * nt * nt)
     L_a = np.zeros(nt)
     lib().orc_rate_bounds(C.byref(p), _ptr(L_ab), _ptr(L_a))
-    return L_ab.reshape(nt, nt), L_a
+    return (L_ab.reshape(nt, nt) if nm == 1 else L_ab.reshape(nm, nt, nt)), L_a
 
 
 def rate_weights(p):
-    nt = p.n_types
-    Lq = np.zeros(nt * nt, np.uint32)
+    """(Lq, unit): Lq[a, m n_types + b], unit[a]."""
+    nt, nm = p.n_types, 2 if p.jump_split else 1
+    Lq = np.zeros(nt * nm * nt, np.uint32)
     unit = np.zeros(nt)
     lib().orc_rate_weights(C.byref(p), _ptr(Lq), _ptr(unit))
-    return Lq.reshape(nt, nt), unit
+    return Lq.reshape(nt, nm * nt), unit
 
 
 def reflect(v, F):
