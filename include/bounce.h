@@ -111,6 +111,16 @@ typedef struct {
                                /* BOUNCE_OUTER_NONBONDED: also the short-range pair force */
                                /* (Sec. V: F_out = short direct + short VdW + recip; F_0  */
                                /* keeps the bonded terms); needs respa_m >= 1, any box   */
+    /* Separate jump mechanisms (Sec. V treats the long-range Coulomb and van der Waals
+       forces by jumps; Sec. VI counts the VdW jumps apart).  0: one mechanism per
+       directed pair carries chi W'_sf of Coulomb plus Lennard-Jones.  1: two, the
+       Coulomb field chi_C qq (g'(r) - g'(rc)) d/r with chi_C on [r_on, r_off] and the
+       Lennard-Jones field chi_V (LJ'(r) - LJ'(rc)) d/r with chi_V on [r_on_lj, r_off_lj],
+       each with its own bound per type pair; the clocks of all (mechanism, partner)
+       pairs superpose into one Poisson count and a weighted draw (as BOUNCE_RATE_PAIR),
+       and F_0 keeps (1 - chi_C) W'_C + (1 - chi_V) W'_V.  Needs n_types <= 4.     */
+    int32_t jump_split;
+    double r_on_lj, r_off_lj;  /* the Lennard-Jones window (both 0: that of Coulomb)      */
 } bounce_params;
 
 typedef struct {
@@ -141,6 +151,8 @@ typedef struct {
 typedef struct {
     int64_t step;
     int32_t phase, atom, k, partner, accepted, replica;   /* atom/partner replica-local */
+    int32_t mech;              /* jump mechanism: 0 Coulomb (or combined), 1 Lennard-Jones */
+    int32_t pad;
 } bounce_event;
 
 typedef struct bounce_ctx bounce_ctx;
@@ -238,11 +250,14 @@ bounce_status bounce_get_events(bounce_ctx *ctx, bounce_event *host, int64_t cap
    then id).  Synchronous. */
 bounce_status bounce_get_list(bounce_ctx *ctx, int32_t which, int64_t *row_ptr_host,
                               int32_t *col_host, int64_t cap);
-/* Rate bounds: L_ab_host[n_types^2] and L_a_host[n_types] (before bound_scale). */
+/* Rate bounds (Sec. IV.A): L_ab_host[n_mech][n_types][n_types] (n_mech = 2 with
+   jump_split, mechanism 0 Coulomb and 1 Lennard-Jones, else 1) and
+   L_a_host[n_types] = max over mechanisms and partner types (before bound_scale). */
 bounce_status bounce_rate_bounds(const bounce_ctx *ctx, double *L_ab_host, double *L_a_host);
-/* The bounds the jump step uses (rate_mode): integer weights Lq_host[n_types^2]
-   and units unit_host[n_types] (bound_scale applied); the bound of a partner of
-   type b of an atom of type a is Lq[a][b] * unit[a].  Synchronous, host only. */
+/* The bounds the jump step uses (rate_mode, jump_split): integer weights
+   Lq_host[n_types][n_mech n_types] and units unit_host[n_types] (bound_scale
+   applied); the bound of a partner of type b of an atom of type a under mechanism
+   m is Lq[a][m n_types + b] * unit[a].  Synchronous, host only. */
 bounce_status bounce_rate_weights(const bounce_ctx *ctx, uint32_t *Lq_host, double *unit_host);
 /* Apply one J half-step alone (Sec. IV.B step J) at the current positions with
    the current candidate lists, random stream (step, phase).  Synchronous. */

@@ -36,13 +36,15 @@ def make_params(**kw) -> bounce_params:
     atom type (RATE_ATOM), no reciprocal-space mesh (pme_grid = (0, 0, 0); when
     set: B-spline order 5, mesh force in F_0 unless respa_m >= 1); with
     respa_m >= 1 and respa_outer = OUTER_NONBONDED the short-range pair force
-    moves to the outer step too."""
+    moves to the outer step too; jump_split = 1 gives the Coulomb and the
+    Lennard-Jones long-range parts separate jump mechanisms (the LJ window
+    r_on_lj, r_off_lj defaults to the Coulomb one)."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
              pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0,
-             respa_outer=OUTER_RECIP)
+             respa_outer=OUTER_RECIP, jump_split=0, r_on_lj=0.0, r_off_lj=0.0)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():
@@ -208,7 +210,7 @@ class Simulation:
               self.ctx, "bounce_get_events")
         dt = np.dtype([("step", np.int64), ("phase", np.int32), ("atom", np.int32),
                        ("k", np.int32), ("partner", np.int32), ("accepted", np.int32),
-                       ("replica", np.int32)])
+                       ("replica", np.int32), ("mech", np.int32), ("pad", np.int32)])
         arr = np.frombuffer(bytes(buf), dtype=dt, count=max(cap, 1))[:cap].copy()
         return arr, n.value
 
@@ -232,20 +234,22 @@ class Simulation:
         return int(rp[-1])
 
     def rate_bounds(self):
-        nt = self.n_types
-        lab, la = np.zeros(nt * nt), np.zeros(nt)
+        """(L_ab [a, b] or, with separate mechanisms, [m, a, b]; L_a [a])."""
+        nt, nm = self.n_types, 2 if self.params.jump_split else 1
+        lab, la = np.zeros(nm * nt * nt), np.zeros(nt)
         check(self.L.bounce_rate_bounds(self.ctx, _ptr(lab), _ptr(la)), self.ctx,
               "bounce_rate_bounds")
-        return lab.reshape(nt, nt), la
+        return (lab.reshape(nt, nt) if nm == 1 else lab.reshape(nm, nt, nt)), la
 
     def rate_weights(self):
-        """Integer bound weights Lq[a][b] and units unit[a] of the jump step: the
-        bound of a partner of type b of an atom of type a is Lq[a][b] * unit[a]."""
-        nt = self.n_types
-        lq, unit = np.zeros(nt * nt, np.uint32), np.zeros(nt)
+        """Integer bound weights Lq[a][m n_types + b] and units unit[a] of the
+        jump step: the bound of a partner of type b of an atom of type a under
+        mechanism m is Lq[a][m n_types + b] * unit[a]."""
+        nt, nm = self.n_types, 2 if self.params.jump_split else 1
+        lq, unit = np.zeros(nt * nm * nt, np.uint32), np.zeros(nt)
         check(self.L.bounce_rate_weights(self.ctx, _ptr(lq), _ptr(unit)), self.ctx,
               "bounce_rate_weights")
-        return lq.reshape(nt, nt), unit
+        return lq.reshape(nt, nm * nt), unit
 
     def rdf_counts(self, r_max, n_bins):
         """Ordered non-excluded pair counts [n_types, n_types, n_bins] with r < r_max

@@ -34,7 +34,8 @@ class bounce_params(C.Structure):
                 ("cell_size", C.c_double), ("seed", C.c_uint64), ("event_capacity", C.c_int64),
                 ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32),
                 ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32), ("respa_m", C.c_int32),
-                ("respa_outer", C.c_int32)]
+                ("respa_outer", C.c_int32), ("jump_split", C.c_int32), ("r_on_lj", C.c_double),
+                ("r_off_lj", C.c_double)]
 
 
 class bounce_system(C.Structure):
@@ -55,7 +56,8 @@ class bounce_counters(C.Structure):
 
 class bounce_event(C.Structure):
     _fields_ = [("step", C.c_int64), ("phase", C.c_int32), ("atom", C.c_int32), ("k", C.c_int32),
-                ("partner", C.c_int32), ("accepted", C.c_int32), ("replica", C.c_int32)]
+                ("partner", C.c_int32), ("accepted", C.c_int32), ("replica", C.c_int32),
+                ("mech", C.c_int32), ("pad", C.c_int32)]
 
 
 _P = C.POINTER

@@ -27,8 +27,11 @@ struct HostFF {
     double q[MAXT], eps[MAXT], sig[MAXT];
     int coulomb;
     double alpha, r_on, r_off, r_cut;
+    int split;                    // separate Coulomb and Lennard-Jones mechanisms
+    double r_on_v, r_off_v;       // the Lennard-Jones window
 
-    void du(int a, int b, double r, double &d) const
+    // the Coulomb and Lennard-Jones parts of u'(r)
+    void du_parts(int a, int b, double r, double &dc, double &dv) const
     {
         double qq = KE * q[a] * q[b];
         double e = std::sqrt(eps[a] * eps[b]);
@@ -45,34 +48,59 @@ struct HostFF {
             double x = s / r, x6 = x * x * x * x * x * x;
             dl = 4.0 * e * (6.0 * x6 - 12.0 * x6 * x6) / r;
         }
-        d = qq * dg + dl;
+        dc = qq * dg;
+        dv = dl;
     }
-    double chi(double r) const
+    void du(int a, int b, double r, double &d) const
     {
-        double x = (r - r_on) / (r_off - r_on);
+        double dc, dv;
+        du_parts(a, b, r, dc, dv);
+        d = dc + dv;
+    }
+    static double smooth(double lo, double hi, double r)
+    {
+        double x = (r - lo) / (hi - lo);
         x = std::min(1.0, std::max(0.0, x));
         return x * x * x * (10.0 + x * (6.0 * x - 15.0));
     }
-    // (1 + 1e-3) * max over the grid r' + k 1e-4 < rc of |chi(r) (u'(r) - u'(rc))|
-    double bound(int a, int b) const
+    double chi(double r) const { return smooth(r_on, r_off, r); }
+    // (1 + 1e-3) * max over the grid r'_m + k 1e-4 < rc of |chi_m(r) W'_m(r)| for
+    // mechanism m: the combined one (chi (u'(r) - u'(rc))), or with split
+    // mechanisms Coulomb (m = 0) and Lennard-Jones (m = 1) each with its window
+    double bound(int m, int a, int b) const
     {
-        double drc;
+        double drc, dcc, dvc;
         du(a, b, r_cut, drc);
-        double m = 0.0;
+        du_parts(a, b, r_cut, dcc, dvc);
+        const double lo = split && m == 1 ? r_on_v : r_on, hi = split && m == 1 ? r_off_v : r_off;
+        double mx = 0.0;
         for (long k = 0;; ++k) {
-            double r = r_on + (double)k * 1e-4;
+            double r = lo + (double)k * 1e-4;
             if (r >= r_cut) break;
-            double d;
-            du(a, b, r, d);
-            m = std::max(m, std::fabs(chi(r) * (d - drc)));
+            double w;
+            if (!split) {
+                double d;
+                du(a, b, r, d);
+                w = d - drc;
+            } else {
+                double dc, dv;
+                du_parts(a, b, r, dc, dv);
+                w = m == 1 ? dv - dvc : dc - dcc;
+            }
+            mx = std::max(mx, std::fabs(smooth(lo, hi, r) * w));
         }
-        return m * (1.0 + 1e-3);
+        return mx * (1.0 + 1e-3);
     }
 };
 
 struct Region {
     size_t off, bytes;
 };
+
+// the short-range force reaches to r'' (the larger window end of the two
+// mechanisms when they are separate); the jump fields start at r' (the smaller)
+static double r_short(const bounce_params &p) { return p.jump_split ? std::max(p.r_off, p.r_off_lj) : p.r_off; }
+static double r_long(const bounce_params &p) { return p.jump_split ? std::min(p.r_on, p.r_on_lj) : p.r_on; }
 
 }  // namespace
 
@@ -88,8 +116,9 @@ struct bounce_ctx {
     std::vector<int32_t> type, rep_of, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, angle_ijk;
     std::vector<double> mass, acc_m, inv_mass, ou_c2, bond_kr, angle_kt, tparams;
     std::vector<double> L_ab, L_a;
-    std::vector<uint32_t> Lq;     // [MAXT][MAXT] integer bound weights of the jump step
-    int32_t ncls = 1;             // candidate classes: n_types for BOUNCE_RATE_PAIR, else 1
+    std::vector<uint32_t> Lq;     // [MAXT][LQW] integer bound weights of the jump step
+    int32_t ncls = 1;             // candidate classes: n_types for BOUNCE_RATE_PAIR or split mechanisms, else 1
+    int32_t nmech = 1;            // jump mechanisms per pair: 2 with jump_split
     std::vector<TypePair<float>> tab_f;     // jump-field pair constants per type pair
     std::vector<TypePair<double>> tab_d;
     int32_t n_cells = 0, fcap = 0, ccap = 0, acap = 0, xcap = 0;
@@ -195,8 +224,17 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
+    if (p->jump_split != 0 && p->jump_split != 1) return BOUNCE_E_ARG;
+    const bool lj_window = p->r_on_lj != 0.0 || p->r_off_lj != 0.0;
+    if (p->jump_split && p->integrator == BOUNCE_BJAOAJB && lj_window &&
+        !(p->r_on_lj > 0 && p->r_off_lj > p->r_on_lj && p->r_off_lj < p->r_cut))
+        return BOUNCE_E_ARG;
     bounce_ctx *c = new bounce_ctx();
     c->p = *p;
+    if (!c->p.jump_split || !lj_window) {      // the Lennard-Jones window defaults to Coulomb's
+        c->p.r_on_lj = c->p.r_on;
+        c->p.r_off_lj = c->p.r_off;
+    }
     if (c->p.pair_lanes == 0) c->p.pair_lanes = 8;
     *out = c;
     return BOUNCE_OK;
@@ -306,41 +344,55 @@ static void make_bounds(bounce_ctx *c)
     ff.coulomb = c->p.coulomb;
     ff.alpha = c->p.ewald_alpha;
     ff.r_on = c->p.r_on; ff.r_off = c->p.r_off; ff.r_cut = c->p.r_cut;
-    c->L_ab.assign(c->nt * c->nt, 0.0);
-    c->L_a.assign(c->nt, 0.0);
-    // pair constants of the jump field chi W'_sf: q_a q_b, LJ, u'(rc)
+    ff.split = c->p.jump_split;
+    ff.r_on_v = c->p.r_on_lj; ff.r_off_v = c->p.r_off_lj;
+    const int nt = c->nt, nm = c->p.jump_split ? 2 : 1;
+    c->nmech = nm;
+    c->L_ab.assign(nm * nt * nt, 0.0);
+    c->L_a.assign(nt, 0.0);
+    // pair constants of the jump fields: q_a q_b, LJ, u'(rc) and its Coulomb
+    // and Lennard-Jones parts (pad[1], pad[0]) for the separate mechanisms
     c->tab_f.assign(MAXT * MAXT, TypePair<float>{});
     c->tab_d.assign(MAXT * MAXT, TypePair<double>{});
-    for (int a = 0; a < c->nt; ++a)
-        for (int b = 0; b < c->nt; ++b) {
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b) {
             const double qq = KE * ff.q[a] * ff.q[b], eps = std::sqrt(ff.eps[a] * ff.eps[b]);
             const double sig = 0.5 * (ff.sig[a] + ff.sig[b]);
-            double drc;
+            double drc, dcc, dvc;
             ff.du(a, b, ff.r_cut, drc);
-            TypePair<double> &td = c->tab_d[a * c->nt + b];
+            ff.du_parts(a, b, ff.r_cut, dcc, dvc);
+            TypePair<double> &td = c->tab_d[a * nt + b];
             td.qq = qq; td.eps4 = 4.0 * eps; td.sig2 = sig * sig; td.du_rc = drc;
-            TypePair<float> &tf = c->tab_f[a * c->nt + b];
+            td.pad[0] = dvc; td.pad[1] = dcc;
+            TypePair<float> &tf = c->tab_f[a * nt + b];
             tf.qq = (float)qq; tf.eps4 = (float)(4.0 * eps); tf.sig2 = (float)(sig * sig);
             tf.du_rc = (float)drc;
+            tf.pad[0] = (float)dvc; tf.pad[1] = (float)dcc;
         }
-    c->Lq.assign(MAXT * MAXT, 1u << WEIGHT_BITS);
+    c->Lq.assign(MAXT * LQW, 1u << WEIGHT_BITS);
     c->ncls = 1;
     if (c->p.integrator != BOUNCE_BJAOAJB) return;
-    for (int a = 0; a < c->nt; ++a)
-        for (int b = a; b < c->nt; ++b) c->L_ab[a * c->nt + b] = c->L_ab[b * c->nt + a] = ff.bound(a, b);
-    for (int a = 0; a < c->nt; ++a)
-        for (int b = 0; b < c->nt; ++b) c->L_a[a] = std::max(c->L_a[a], c->L_ab[a * c->nt + b]);
-    // per-type-pair bounds as integer weights of the row unit L_a 2^-20, rounded
-    // up after a slack of 1e-4 of a unit (bounds that agree to 1e-12 with
-    // another computation of them give the same weights)
-    if (c->p.rate_mode == BOUNCE_RATE_PAIR) {
-        c->ncls = c->nt;
+    for (int m = 0; m < nm; ++m)
+        for (int a = 0; a < nt; ++a)
+            for (int b = a; b < nt; ++b)
+                c->L_ab[(m * nt + a) * nt + b] = c->L_ab[(m * nt + b) * nt + a] = ff.bound(m, a, b);
+    for (int m = 0; m < nm; ++m)
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b) c->L_a[a] = std::max(c->L_a[a], c->L_ab[(m * nt + a) * nt + b]);
+    // per-type-pair (and per-mechanism) bounds as integer weights of the row unit
+    // L_a 2^-20, rounded up after a slack of 1e-4 of a unit (bounds that agree
+    // to 1e-12 with another computation of them give the same weights); the
+    // weight of mechanism m and partner type b of an atom of type a sits at
+    // Lq[a LQW + m n_types + b]
+    if (c->p.rate_mode == BOUNCE_RATE_PAIR || c->p.jump_split) {
+        c->ncls = nt;
         const double one = (double)(1u << WEIGHT_BITS);
-        for (int a = 0; a < c->nt; ++a)
-            for (int b = 0; b < c->nt; ++b)
-                if (c->L_a[a] > 0.0)
-                    c->Lq[a * c->nt + b] =
-                        (uint32_t)std::ceil(c->L_ab[a * c->nt + b] / c->L_a[a] * one - WEIGHT_SLACK);
+        for (int a = 0; a < nt; ++a)
+            for (int m = 0; m < nm; ++m)
+                for (int b = 0; b < nt; ++b)
+                    if (c->L_a[a] > 0.0)
+                        c->Lq[a * LQW + m * nt + b] =
+                            (uint32_t)std::ceil(c->L_ab[(m * nt + a) * nt + b] / c->L_a[a] * one - WEIGHT_SLACK);
     }
 }
 
@@ -360,6 +412,8 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
         return fail(c, BOUNCE_E_ARG, "missing replicas, atoms, types or masses");
     if (s->n_types < 1 || s->n_types > MAXT || !s->charge || !s->eps || !s->sigma)
         return fail(c, BOUNCE_E_ARG, "n_types must be in [1, 8] with charge/eps/sigma");
+    if (c->p.jump_split && s->n_types > MAXT / 2)
+        return fail(c, BOUNCE_E_ARG, "jump_split needs n_types <= 4");
     if (s->replica_offset[0] != 0 || s->replica_offset[s->n_replicas] != s->n_atoms)
         return fail(c, BOUNCE_E_ARG, "replica_offset must run from 0 to n_atoms");
     if (c->p.periodic && !s->box) return fail(c, BOUNCE_E_ARG, "periodic system needs box");
@@ -382,7 +436,7 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     c->reps.assign(R, RepInfo{});
     int32_t cell_off = 0;
     double max_rho = 0.0;
-    const double rsearch = std::max(c->p.r_cut, c->p.r_off) + c->p.skin;
+    const double rsearch = std::max(c->p.r_cut, r_short(c->p)) + c->p.skin;
     for (int32_t r = 0; r < R; ++r) {
         int64_t b = c->rep_off[r], e = c->rep_off[r + 1];
         if (e <= b) return fail(c, BOUNCE_E_ARG, "empty replica");
@@ -451,7 +505,7 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     for (int32_t r = 0; r < R; ++r) max_rep = std::max<int64_t>(max_rep, c->rep_off[r + 1] - c->rep_off[r]);
     auto clampcap = [&](int32_t k) { return (int32_t)std::min<int64_t>(k, std::max<int64_t>(32, ((max_rep + 31) / 32) * 32)); };
     bool bounce = c->p.integrator == BOUNCE_BJAOAJB;
-    c->fcap = clampcap(cap((bounce ? c->p.r_off : c->p.r_cut) + c->p.skin));
+    c->fcap = clampcap(cap((bounce ? r_short(c->p) : c->p.r_cut) + c->p.skin));
     c->ccap = bounce ? clampcap(cap(c->p.r_cut + c->p.skin)) : 0;
     c->acap = clampcap(cap(c->p.r_cut + 0.01));
     c->xcap = std::max(c->fcap, std::max(c->ccap, c->acap));
@@ -574,7 +628,7 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.angle_kt = L.take(8 * std::max<size_t>(1, c->angle_kt.size()));
     o.reps = L.take(sizeof(RepInfo) * R);
     o.unit = L.take(8 * MAXT);
-    o.Lq = L.take(4 * MAXT * MAXT);
+    o.Lq = L.take(4 * MAXT * LQW);
     o.tparams = L.take(8 * 3 * MAXT);
     o.tab_f = L.take(sizeof(TypePair<float>) * MAXT * MAXT);
     o.tab_d = L.take(sizeof(TypePair<double>) * MAXT * MAXT);
@@ -887,6 +941,10 @@ static PairGlobals pair_globals(const bounce_ctx *c)
     g.r_on = c->p.r_on;
     g.r_off = c->p.r_off;
     g.inv_w = c->p.r_off > c->p.r_on ? 1.0 / (c->p.r_off - c->p.r_on) : 0.0;
+    g.split = c->p.jump_split;
+    g.r_on_v = c->p.r_on_lj;
+    g.inv_w_v = c->p.r_off_lj > c->p.r_on_lj ? 1.0 / (c->p.r_off_lj - c->p.r_on_lj) : 0.0;
+    g.r_short = r_short(c->p);
     g.r_cut = c->p.r_cut;
     g.coulomb = c->p.coulomb;
     g.n_types = c->nt;
@@ -898,8 +956,8 @@ static BuildSpec main_spec(const bounce_ctx *c)
     BuildSpec b{};
     const bounce_params &p = c->p;
     if (p.integrator == BOUNCE_BJAOAJB) {
-        double rf = p.r_off + p.skin, rn = p.r_off + 0.5 * p.skin;
-        double rmin = p.r_on - p.skin, rmax = p.r_cut + p.skin;
+        double rf = r_short(p) + p.skin, rn = r_short(p) + 0.5 * p.skin;
+        double rmin = r_long(p) - p.skin, rmax = p.r_cut + p.skin;
         b.rf2 = rf * rf;
         b.rfn2 = rn * rn;
         b.rcmin2 = rmin > 0.0 ? rmin * rmin : 0.0;
@@ -1435,9 +1493,10 @@ bounce_status bounce_rate_weights(const bounce_ctx *c, uint32_t *Lq, double *uni
     if (!c || !Lq || !unit) return BOUNCE_E_ARG;
     if (!c->have_system) return BOUNCE_E_STATE;
     const std::vector<double> u = bound_units(c);
+    const int w = c->nmech * c->nt;
     for (int a = 0; a < c->nt; ++a) {
         unit[a] = u[a];
-        for (int b = 0; b < c->nt; ++b) Lq[a * c->nt + b] = c->Lq[a * c->nt + b];
+        for (int k = 0; k < w; ++k) Lq[a * w + k] = c->Lq[a * LQW + k];
     }
     return BOUNCE_OK;
 }

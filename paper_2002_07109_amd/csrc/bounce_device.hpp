@@ -15,6 +15,8 @@ constexpr int MAXT = 8;
 // jump bounds as integer weights: 2^WEIGHT_BITS units make the bound of an atom type
 constexpr int WEIGHT_BITS = 20;
 constexpr double WEIGHT_SLACK = 1e-4;
+// row stride of the bound-weight table: (mechanism, partner type) classes per atom type
+constexpr int LQW = 2 * MAXT;
 // pair-structure histogram: at most this many (type pair, bin) counters
 constexpr int RDF_MAX_BINS = 8192;
 // smooth-PME B-spline order limit
@@ -67,6 +69,7 @@ struct RepCounters {
 struct Event {
     int64_t step;
     int32_t phase, atom, k, partner, accepted, replica;
+    int32_t mech, pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -110,15 +113,19 @@ struct TypePair {
     R sig2;    // sigma_ab^2
     R du_rc;   // u'(rc)
     R u_rc;    // u(rc)
-    R pad[3];
+    R pad[3];  // [0]: the Lennard-Jones part of u'(rc), [1]: its Coulomb part
 };
 
 struct PairGlobals {
     double alpha;     // Ewald splitting (1/A)
-    double r_on, r_off, inv_w;  // switch window and 1/(r'' - r')
+    double r_on, r_off, inv_w;  // switch window and 1/(r'' - r') (Coulomb, or both parts)
+    double r_on_v, inv_w_v;     // separate mechanisms: the Lennard-Jones window
+    double r_short;             // the short-range force's reach: r'' (the larger one when split)
     double r_cut;
     int32_t coulomb;  // 0 bare, 1 erfc
     int32_t n_types;
+    int32_t split;    // 1: separate Coulomb and Lennard-Jones jump mechanisms
+    int32_t pad_i;
 };
 
 // Coulomb kernel g(r) and g'(r)
@@ -198,6 +205,26 @@ __device__ __forceinline__ R pair_dw(R r2, const TypePair<R> &tp, R alpha, int c
     r_out = r;
     rinv_out = rinv;
     return tp.qq * dg + dlj - tp.du_rc;
+}
+
+// the Coulomb and Lennard-Jones parts of W'_sf(r), qq (g'(r) - g'(rc)) and
+// LJ'(r) - LJ'(rc) (requires r < rc); also returns r and 1/r
+template <typename R>
+__device__ __forceinline__ void pair_dw_parts(R r2, const TypePair<R> &tp, R alpha, int coulomb,
+                                              R &r_out, R &rinv_out, R &dwc, R &dwv)
+{
+    R rinv = rsqrt_<R>(r2);
+    R r = r2 * rinv;
+    R g, dg;
+    coul_g<R>(r, rinv, alpha, coulomb, g, dg);
+    R rinv2 = rinv * rinv;
+    R s2 = tp.sig2 * rinv2;
+    R s6 = s2 * s2 * s2;
+    R dlj = tp.eps4 * ((R)6 * s6 - (R)12 * s6 * s6) * rinv;
+    r_out = r;
+    rinv_out = rinv;
+    dwc = tp.qq * dg - tp.pad[1];
+    dwv = dlj - tp.pad[0];
 }
 
 // quintic smoothstep switch on [r', r'']

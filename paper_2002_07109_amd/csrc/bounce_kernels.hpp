@@ -54,7 +54,7 @@ struct StepArgs {
     double *vel;                  // [N][3] caller order
     const double *ou_c2;          // [N] O-step noise amplitude
     const double *Lunit;          // [MAXT] unit of each atom type's bound weights (bound_scale applied)
-    const uint32_t *Lq;           // [n_types][n_types] integer bound weights of the partner types
+    const uint32_t *Lq;           // [MAXT][LQW] integer bound weights of the (mechanism, partner type) classes
     const TypePair<float> *tab_f; // [MAXT][MAXT] pair constants of the jump field
     const TypePair<double> *tab_d;
     PairGlobals pg;

@@ -20,6 +20,27 @@ __device__ __forceinline__ int32_t row_slot(int32_t e, int32_t nn, int32_t tail)
     return e < nn ? e : tail - e;
 }
 
+// The pair's scalar s with gradient s d: SHORT (1 - chi) W'_sf / r, LONG
+// chi W'_sf / r (r > r'), FULL W'_sf / r; with separate mechanisms each of the
+// Coulomb and Lennard-Jones parts with its own switch (pg.split is uniform).
+template <typename R, int MODE>
+__device__ __forceinline__ R pair_scalar(R r2, const TypePair<R> &tp, const PairGlobals &pg, R alpha,
+                                         R r_on, R inv_w, R r_on_v, R inv_w_v)
+{
+    R r, rinv;
+    if (MODE != MODE_FULL && pg.split) {
+        R dwc, dwv;
+        pair_dw_parts<R>(r2, tp, alpha, pg.coulomb, r, rinv, dwc, dwv);
+        const R cc = switch_chi<R>(r, r_on, inv_w), cv = switch_chi<R>(r, r_on_v, inv_w_v);
+        if (MODE == MODE_SHORT) return (((R)1 - cc) * dwc + ((R)1 - cv) * dwv) * rinv;
+        return ((r > r_on ? cc * dwc : (R)0) + (r > r_on_v ? cv * dwv : (R)0)) * rinv;
+    }
+    const R dw = pair_dw<R>(r2, tp, alpha, pg.coulomb, r, rinv);
+    if (MODE == MODE_SHORT) return ((R)1 - switch_chi<R>(r, r_on, inv_w)) * dw * rinv;
+    if (MODE == MODE_LONG) return r > r_on ? switch_chi<R>(r, r_on, inv_w) * dw * rinv : (R)0;
+    return dw * rinv;
+}
+
 template <typename R, int MODE, int G>
 __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, const double4 &xi,
                                                const BoxReg &box, const int32_t *__restrict__ row,
@@ -28,7 +49,8 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
                                                double &ax, double &ay, double &az)
 {
     const R alpha = (R)pg.alpha, r_on = (R)pg.r_on, inv_w = (R)pg.inv_w;
-    const R lim = MODE == MODE_SHORT ? (R)pg.r_off : (R)pg.r_cut;
+    const R r_on_v = (R)pg.r_on_v, inv_w_v = (R)pg.inv_w_v;
+    const R lim = MODE == MODE_SHORT ? (R)pg.r_short : (R)pg.r_cut;
     const R lim2 = lim * lim;
     // U entries per lane in flight: their position gathers are issued together,
     // and the row indices of the next block load during this block's arithmetic
@@ -72,16 +94,7 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
             const R r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
             if (!(r2 < lim2)) continue;
             const TypePair<R> &tp = tab_i[mirror_type(xj[u].w)];
-            R r, rinv;
-            const R dw = pair_dw<R>(r2, tp, alpha, pg.coulomb, r, rinv);
-            R f;
-            if (MODE == MODE_SHORT) {
-                f = ((R)1 - switch_chi<R>(r, r_on, inv_w)) * dw * rinv;
-            } else if (MODE == MODE_LONG) {
-                f = r > r_on ? switch_chi<R>(r, r_on, inv_w) * dw * rinv : (R)0;
-            } else {
-                f = dw * rinv;
-            }
+            const R f = pair_scalar<R, MODE>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
             px += f * rx;
             py += f * ry;
             pz += f * rz;
@@ -107,7 +120,8 @@ __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF
                                                      double &az)
 {
     const float alpha = (float)pg.alpha, r_on = (float)pg.r_on, inv_w = (float)pg.inv_w;
-    const float lim = MODE == MODE_SHORT ? (float)pg.r_off : (float)pg.r_cut;
+    const float r_on_v = (float)pg.r_on_v, inv_w_v = (float)pg.inv_w_v;
+    const float lim = MODE == MODE_SHORT ? (float)pg.r_short : (float)pg.r_cut;
     const float lim2 = lim * lim;
     constexpr int U = 4;
     const int32_t tail = cap - 1 + nn;
@@ -145,10 +159,7 @@ __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF
             const float r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
             if (!(r2 < lim2)) continue;
             const TypePair<float> &tp = tab_i[xj[u].w];
-            float r, rinv;
-            const float dw = pair_dw<float>(r2, tp, alpha, pg.coulomb, r, rinv);
-            const float f = MODE == MODE_SHORT ? (1.0f - switch_chi<float>(r, r_on, inv_w)) * dw * rinv
-                                               : dw * rinv;
+            const float f = pair_scalar<float, MODE>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
             px += f * rx;
             py += f * ry;
             pz += f * rz;

@@ -47,7 +47,7 @@ __device__ void init_tables(TypePair<R> *tab, TypePair<double> *tabc, DbwdConst<
         TypePair<R> t;
         t.qq = (R)qq; t.eps4 = (R)(4.0 * eps); t.sig2 = (R)(sig * sig);
         t.du_rc = (R)(qq * dg + dul); t.u_rc = (R)(qq * g + ul);
-        t.pad[0] = t.pad[1] = t.pad[2] = (R)0;
+        t.pad[0] = (R)dul; t.pad[1] = (R)(qq * dg); t.pad[2] = (R)0;
         tab[k] = t;
         if (tabc) {
             TypePair<double> c;
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
     const int nt = a.pg.n_types;
     const R alpha = (R)a.pg.alpha, r_on = (R)a.pg.r_on, inv_w = (R)a.pg.inv_w;
     const R r_cut = (R)a.pg.r_cut;
-    const R lim = MODE == MODE_SHORT ? (R)a.pg.r_off : r_cut;
+    const R lim = MODE == MODE_SHORT ? (R)a.pg.r_short : r_cut;
     const R lim2 = lim * lim;
 
     double ax = 0.0, ay = 0.0, az = 0.0, ec = 0.0, el = 0.0;

@@ -21,20 +21,31 @@ __device__ __forceinline__ const TypePair<float> *jump_table<float>(const StepAr
 template <>
 __device__ __forceinline__ const TypePair<double> *jump_table<double>(const StepArgs &a) { return a.tab_d; }
 
-// long-range field F_ij = chi(r) W'_sf(r) d/r on i (zero outside r' < r < rc)
+// long-range field of jump mechanism mech on i: F_ij = chi(r) W'_sf(r) d/r
+// (the combined mechanism), or with separate mechanisms chi_C W'_C d/r
+// (mech 0, Coulomb) or chi_V W'_V d/r (mech 1, Lennard-Jones); zero outside
+// r'_mech < r < rc
 template <typename R>
-__device__ __forceinline__ void long_field(const TypePair<R> &tp, const PairGlobals &pg, double dx,
-                                           double dy, double dz, double F[3])
+__device__ __forceinline__ void long_field(const TypePair<R> &tp, const PairGlobals &pg, int mech,
+                                           double dx, double dy, double dz, double F[3])
 {
     F[0] = F[1] = F[2] = 0.0;
     const R rx = (R)dx, ry = (R)dy, rz = (R)dz;
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R rc = (R)pg.r_cut;
     if (!(r2 < rc * rc)) return;
-    R r, rinv;
-    const R dw = pair_dw<R>(r2, tp, (R)pg.alpha, pg.coulomb, r, rinv);
-    if (!(r > (R)pg.r_on)) return;
-    const R f = switch_chi<R>(r, (R)pg.r_on, (R)pg.inv_w) * dw * rinv;
+    R r, rinv, f;
+    if (pg.split) {
+        R dwc, dwv;
+        pair_dw_parts<R>(r2, tp, (R)pg.alpha, pg.coulomb, r, rinv, dwc, dwv);
+        const R lo = mech ? (R)pg.r_on_v : (R)pg.r_on, iw = mech ? (R)pg.inv_w_v : (R)pg.inv_w;
+        if (!(r > lo)) return;
+        f = switch_chi<R>(r, lo, iw) * (mech ? dwv : dwc) * rinv;
+    } else {
+        const R dw = pair_dw<R>(r2, tp, (R)pg.alpha, pg.coulomb, r, rinv);
+        if (!(r > (R)pg.r_on)) return;
+        f = switch_chi<R>(r, (R)pg.r_on, (R)pg.inv_w) * dw * rinv;
+    }
     F[0] = (double)(f * rx);
     F[1] = (double)(f * ry);
     F[2] = (double)(f * rz);
@@ -69,13 +80,16 @@ __device__ __forceinline__ int32_t group_get_i32(int32_t v, int src)
     return __shfl(v, group_base<GS>() + src, 64);
 }
 
-// The atom's jump partners: KC classes in its candidate row (the partner's
-// type when the rate bounds are per type pair, else one class), c[b] members
-// in class b, each with the bound w[b] * unit (integer weight w[b]).
+// The atom's jump partners: its candidate row holds ncls groups (the
+// partner's type when the rate bounds are per type pair or the mechanisms are
+// separate, else one group), each in canonical order.  A proposal class b < KC
+// is a (mechanism, group) pair, b = mech ncls + group, with c[b] members, each
+// with the bound w[b] * unit (integer weight w[b]).
 template <int KC>
 struct Partners {
-    const int32_t *row;     // class b at row + b * cap, in canonical order
+    const int32_t *row;     // group g at row + g * cap, in canonical order
     int32_t cap;
+    int32_t ncls;           // groups in the row
     int32_t c[KC];
     uint32_t w[KC];
     uint64_t W;             // sum of the members' weights
@@ -87,6 +101,7 @@ __device__ __forceinline__ void no_partners(const StepArgs &a, Partners<KC> &P)
 {
     P.row = a.ls.clist;
     P.cap = a.ls.ccap;
+    P.ncls = a.ls.ncls;
     P.W = 0;
     P.unit = 0.0;
 #pragma unroll
@@ -102,6 +117,7 @@ __device__ __forceinline__ void load_partners(const StepArgs &a, int32_t s, int 
     const int32_t nc = a.ls.ncls;
     P.row = a.ls.clist + (int64_t)s * nc * a.ls.ccap;
     P.cap = a.ls.ccap;
+    P.ncls = nc;
     // the type's bound unit from the whole (uniform, scalar-loaded) table, so
     // that it does not wait for a load indexed by the atom's type
     P.unit = 0.0;
@@ -111,11 +127,13 @@ __device__ __forceinline__ void load_partners(const StepArgs &a, int32_t s, int 
         if (b == ti) P.unit = ub;
     }
     P.W = 0;
+    const int32_t nw = a.pg.split ? 2 * nc : nc;     // proposal classes
 #pragma unroll
     for (int b = 0; b < KC; ++b) {
-        const bool on = b < nc;
-        P.c[b] = on ? min(a.ls.ccnt[(int64_t)s * nc + b], a.ls.ccap) : 0;
-        P.w[b] = KC == 1 ? (1u << WEIGHT_BITS) : (on ? a.Lq[ti * a.pg.n_types + b] : 0u);
+        const bool on = b < nw;
+        const int32_t grp = b >= nc ? b - nc : b;
+        P.c[b] = on ? min(a.ls.ccnt[(int64_t)s * nc + grp], a.ls.ccap) : 0;
+        P.w[b] = KC == 1 ? (1u << WEIGHT_BITS) : (on ? a.Lq[ti * LQW + b] : 0u);
         P.W += (uint64_t)P.c[b] * P.w[b];
     }
 }
@@ -126,8 +144,9 @@ __device__ __forceinline__ void load_partners(const StepArgs &a, int32_t s, int 
 // of weight 2^20 this is the uniform draw umulh(w0, c).
 template <int KC>
 __device__ __forceinline__ void pick_partner(const Partners<KC> &P, uint64_t w0, int32_t &slot,
-                                             double &lb)
+                                             double &lb, int32_t &mech)
 {
+    mech = 0;
     if (KC == 1) {
         slot = P.row[(int32_t)__umul64hi(w0, (uint64_t)P.c[0])];
         lb = (double)(1u << WEIGHT_BITS) * P.unit;
@@ -144,7 +163,8 @@ __device__ __forceinline__ void pick_partner(const Partners<KC> &P, uint64_t w0,
         if (!found && X < hi) {
             found = true;
             wb = P.w[b];
-            off = b * P.cap;
+            mech = b >= P.ncls;
+            off = (b >= P.ncls ? b - P.ncls : b) * P.cap;
         }
         if (!found) lo = hi;
     }
@@ -187,15 +207,16 @@ __device__ __forceinline__ int32_t poisson_count(const StepArgs &a, uint64_t W, 
 struct Proposal {
     double F[3];
     double u;
-    double lb;      // the rate bound of this partner
+    double lb;      // the rate bound of this partner and mechanism
     int32_t p;
+    int32_t mech;   // the jump mechanism (0: Coulomb or combined, 1: Lennard-Jones)
 };
 
 // first stage: the partner and the uniform from the proposal's Philox block
 template <int KC>
 __device__ __forceinline__ void block_proposal(const U4 &w, const Partners<KC> &P, Proposal &o)
 {
-    pick_partner<KC>(P, w.x, o.p, o.lb);
+    pick_partner<KC>(P, w.x, o.p, o.lb, o.mech);
     o.u = u01(w.y);
 }
 
@@ -216,7 +237,7 @@ __device__ __forceinline__ void field_proposal(const StepArgs &a, const TypePair
     const double4 xj = X[o.p];
     double dx = q[0] - xj.x, dy = q[1] - xj.y, dz = q[2] - xj.z;
     BoxReg(ri).apply(dx, dy, dz);
-    long_field<R>(tab[ti * a.pg.n_types + mirror_type(xj.w)], a.pg, dx, dy, dz, o.F);
+    long_field<R>(tab[ti * a.pg.n_types + mirror_type(xj.w)], a.pg, o.mech, dx, dy, dz, o.F);
 }
 
 template <typename R, int KC>
@@ -236,8 +257,8 @@ __device__ __forceinline__ void eval_proposal(const StepArgs &a, const TypePair<
 __device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo &ri, int32_t lid,
                                                int32_t rep, double v[3], double v0, double L,   // L: the partner's bound
                                                int64_t step, int32_t phase, int32_t k, double Fx,
-                                               double Fy, double Fz, double ut, int32_t pt, int sub,
-                                               JumpTally &tally)
+                                               double Fy, double Fz, double ut, int32_t pt,
+                                               int32_t mech, int sub, JumpTally &tally)
 {
     const double sdot = v[0] * Fx + v[1] * Fy + v[2] * Fz;
     // U < lambda / lambda*  <=>  U |v| L < v.F  (beta cancels)
@@ -263,6 +284,7 @@ __device__ __forceinline__ void apply_proposal(const StepArgs &a, const RepInfo 
                 ev.step = step; ev.phase = phase; ev.atom = lid; ev.k = k;
                 ev.partner = a.ls.perm[pt] - (int32_t)ri.atom_off;
                 ev.accepted = acc; ev.replica = rep;
+                ev.mech = mech; ev.pad = 0;
                 a.events[slot] = ev;
             }
         }
@@ -298,8 +320,10 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
             const double ut = group_get<GS>(pre.u, src);
             const double lb = KC == 1 ? L1 : group_get<GS>(pre.lb, src);
             const int32_t pt = group_get_i32<GS>(pre.p, src);
+            const int32_t mc = KC == 1 ? 0 : group_get_i32<GS>(pre.mech, src);
             if (t < n_pre)
-                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, 1 + t, Fx, Fy, Fz, ut, pt, mc, sub,
+                               tally);
         }
     }
     for (int32_t k0 = n_pre + 1; __any(k0 <= M); k0 += PB) {
@@ -309,6 +333,7 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
         P.u = 1.0;
         P.lb = 1.0;
         P.p = 0;
+        P.mech = 0;
         if (k <= M && sub < PB) eval_proposal<R, KC>(a, tab, X, PT, ri, ti, q, step, phase, lid, k, P);
 #pragma unroll
         for (int t = 0; t < PB; ++t) {
@@ -317,8 +342,10 @@ __device__ void jump_chain(const StepArgs &a, const TypePair<R> *tab, const doub
             const double ut = group_get<GS>(P.u, t);
             const double lb = KC == 1 ? L1 : group_get<GS>(P.lb, t);
             const int32_t pt = group_get_i32<GS>(P.p, t);
+            const int32_t mc = KC == 1 ? 0 : group_get_i32<GS>(P.mech, t);
             if (k0 + t <= M)
-                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, k0 + t, Fx, Fy, Fz, ut, pt, sub, tally);
+                apply_proposal(a, ri, lid, rep, v, v0, lb, step, phase, k0 + t, Fx, Fy, Fz, ut, pt, mc,
+                               sub, tally);
         }
     }
 }
@@ -465,6 +492,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     pp.u = 1.0;
     pp.lb = 1.0;
     pp.p = 0;
+    pp.mech = 0;
     if (BOUNCE) {
         // both counts at the entry velocity in one evaluation: lanes 0, 1 the
         // count of (n-1, JB), lanes 2, 3 the estimated count of (n, JA)
@@ -597,8 +625,9 @@ void launch_step(hipStream_t sm, const StepArgs &a)
     if (a.n <= 0) return;
     dim3 grid(((int64_t)a.n * LPA + 255) / 256), block(256);
     if (a.bounce) {
-        // classes of jump partners rounded up to 1, 2, 4 or 8
-        const int kc = a.ls.ncls <= 1 ? 1 : (a.ls.ncls <= 2 ? 2 : (a.ls.ncls <= 4 ? 4 : 8));
+        // proposal classes ((mechanism, partner group) pairs) rounded up to 1, 2, 4 or 8
+        const int nw = a.ls.ncls * (a.pg.split ? 2 : 1);
+        const int kc = nw <= 1 ? 1 : (nw <= 2 ? 2 : (nw <= 4 ? 4 : 8));
         switch (kc * 2 + a.pair_fp64) {
             case 2: hipLaunchKernelGGL((k_step<float, true, 1>), grid, block, 0, sm, a); break;
             case 3: hipLaunchKernelGGL((k_step<double, true, 1>), grid, block, 0, sm, a); break;
@@ -654,6 +683,7 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
     none.u = 1.0;
     none.lb = 1.0;
     none.p = 0;
+    none.mech = 0;
     jump_chain<R, PB, 1, KC>(a, tab, X, PT, lid, rep, ri, mirror_type(xi.w), q, v, v0, ja.step,
                              ja.phase, M, 0, 0, 0, none, sub, tally);
     if (active && sub == 0) {
@@ -668,7 +698,7 @@ void launch_jump(hipStream_t sm, const JumpArgs &a)
 {
     if (a.s.n <= 0) return;
     dim3 grid(((int64_t)a.s.n * PB + 255) / 256), block(256);
-    const int nc = a.s.ls.ncls;
+    const int nc = a.s.ls.ncls * (a.s.pg.split ? 2 : 1);
     const int kc = nc <= 1 ? 1 : (nc <= 2 ? 2 : (nc <= 4 ? 4 : 8));
     switch (kc * 2 + a.s.pair_fp64) {
         case 2: hipLaunchKernelGGL((k_jump<float, 1>), grid, block, 0, sm, a); break;

@@ -28,7 +28,9 @@ def oracle_params(orc, sys, cfg, replica=0):
                            replica=replica, bound_scale=cfg["bound_scale"],
                            periodic=bool(cfg["periodic"]), rate_mode=cfg.get("rate_mode", 0),
                            pme_grid=cfg.get("pme_grid"), pme_order=cfg.get("pme_order", 5),
-                           respa_m=cfg.get("respa_m", 0), respa_outer=cfg.get("respa_outer", 0))
+                           respa_m=cfg.get("respa_m", 0), respa_outer=cfg.get("respa_outer", 0),
+                           jump_split=cfg.get("jump_split", 0), r_on_lj=cfg.get("r_on_lj"),
+                           r_off_lj=cfg.get("r_off_lj"))
 
 
 def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_graph=False):
@@ -44,7 +46,9 @@ def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_gr
                       log_events=int(log_events), event_capacity=event_capacity,
                       use_graph=int(use_graph), rate_mode=cfg.get("rate_mode", 0),
                       pme_grid=cfg.get("pme_grid") or (0, 0, 0), pme_order=cfg.get("pme_order", 5),
-                      respa_m=cfg.get("respa_m", 0), respa_outer=cfg.get("respa_outer", 0))
+                      respa_m=cfg.get("respa_m", 0), respa_outer=cfg.get("respa_outer", 0),
+                      jump_split=cfg.get("jump_split", 0), r_on_lj=cfg.get("r_on_lj") or 0.0,
+                      r_off_lj=cfg.get("r_off_lj") or 0.0)
     return B.Simulation(systems, p, FF["charge"], FF["eps"], FF["sigma"])
 
 
