@@ -262,63 +262,93 @@ def structure_summary(counts, n_samples, n_o, volume):
             "oo_min_r": round(float(mid[kmin]), 3), "oo_coordination": round(coord, 3)}
 
 
+def accuracy_run(args, system, ff, state, integ, dt, m=0, r_on=None, r_off=None):
+    """One run for the accuracy comparison: 2 ps to decorrelate from the start,
+    then args.accuracy ps sampled every 100 fs.  Returns <T_kin> and <E_pot>
+    per water with block standard errors (10 blocks), the O-O radial
+    distribution summary accumulated over the samples and the O self-diffusion
+    coefficient from the slope of the unwrapped mean squared displacement over
+    the second half of the run."""
+    import paper_2002_07109_amd as B
+    n_o = int((system.atom_type == 0).sum())
+    volume = float(np.prod(system.box))
+    p = B.make_params(integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
+                      periodic=1, dt=dt, gamma=1e-3, temperature=300.0,
+                      r_on=args.r_on if r_on is None else r_on,
+                      r_off=args.r_off if r_off is None else r_off, r_cut=9.0, skin=args.skin,
+                      ewald_alpha=args.alpha,
+                      rebuild_interval=args.rebuild if dt == 1.0 else 4 * args.rebuild,
+                      seed=7, cell_size=system.cell_size, use_graph=1, respa_m=m,
+                      respa_outer=B.OUTER_NONBONDED if m else B.OUTER_RECIP)
+    sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
+    sim.set_state(pos=state[0], vel=state[1], step=0)
+    per = int(round(100.0 / dt))
+    n_samples = int(round(args.accuracy * 1000.0 / 100.0))
+    sim.step(int(round(2000.0 / dt)))        # 2 ps to decorrelate from the start
+    ref = sim.pos.clone()
+    T, E, msd = [], [], []
+    counts = np.zeros((2, 2, RDF_BINS))
+    for _ in range(n_samples):
+        sim.step(per)
+        e = sim.energies()[0]
+        T.append(e["tkin"])
+        E.append((e["pair"] + e["bond"] + e["angle"]) / (system.n_atoms / 3))
+        counts += sim.rdf_counts(RDF_RMAX, RDF_BINS)
+        msd.append(sim.msd(ref)[0, 0])
+    sim.close()
+    res = {}
+    for key, x in (("t_kin_K", np.array(T)), ("e_pot_per_water", np.array(E))):
+        blocks = x[: len(x) // 10 * 10].reshape(10, -1).mean(1)
+        res[key] = [round(float(x.mean()), 4), round(float(blocks.std(ddof=1) / np.sqrt(10)), 4)]
+    res.update(structure_summary(counts, n_samples, n_o, volume))
+    t_fs = 100.0 * np.arange(1, n_samples + 1)
+    half = n_samples // 2
+    slope = np.polyfit(t_fs[half:], np.array(msd)[half:], 1)[0]    # A^2 / fs
+    res["d_o_1e-5_cm2_s"] = round(float(slope / 6.0 * 1e4), 3)
+    return res
+
+
+def matched(res, ref, ba):
+    """|X - X_ref| <= |X_BAOAB - X_ref| + 2 sigma (sigma of X), per quantity."""
+    return {key: bool(abs(res[key][0] - ref[key][0]) <= abs(ba[key][0] - ref[key][0]) +
+                      2.0 * res[key][1])
+            for key in ("t_kin_K", "e_pot_per_water")}
+
+
 def run_accuracy(args, system, ff, state):
     """<T_kin> and <E_pot> per water of BOUNCE and BAOAB at 1 fs and of BOUNCE-RESPA
     (1 fs inner, short-range pair force on a 2 fs outer step) against BAOAB at
-    0.25 fs (the reference), each over args.accuracy ps from the same state,
-    sampled every 100 fs; errors are block standard errors (10 blocks).  Also
-    the O-O radial distribution (first peak, coordination) accumulated over the
-    samples and the O self-diffusion coefficient from the slope of the
-    unwrapped mean squared displacement over the second half of the run."""
+    0.25 fs (the reference), each over args.accuracy ps from the same state
+    (accuracy_run).  With --accuracy-splits, BOUNCE at 1 fs is also run and
+    timed at each switching window r'/r'' given, against the same reference."""
     import paper_2002_07109_amd as B
     out = {}
-    n_o = int((system.atom_type == 0).sum())
-    volume = float(np.prod(system.box))
     # (name, integrator, inner dt, RESPA outer step in inner steps: the
     # short-range pair force on it; 0 = none)
     for name, integ, dt, m in (("bounce_1fs", B.BJAOAJB, 1.0, 0), ("baoab_1fs", B.BAOAB, 1.0, 0),
                                ("bounce_respa_1_2fs", B.BJAOAJB, 1.0, 2),
                                ("baoab_0.25fs", B.BAOAB, 0.25, 0)):
-        p = B.make_params(integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD,
-                          periodic=1, dt=dt, gamma=1e-3, temperature=300.0, r_on=args.r_on,
-                          r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
-                          rebuild_interval=args.rebuild if dt == 1.0 else 4 * args.rebuild,
-                          seed=7, cell_size=system.cell_size, use_graph=1, respa_m=m,
-                          respa_outer=B.OUTER_NONBONDED if m else B.OUTER_RECIP)
-        sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
-        sim.set_state(pos=state[0], vel=state[1], step=0)
-        per = int(round(100.0 / dt))
-        n_samples = int(round(args.accuracy * 1000.0 / 100.0))
-        sim.step(int(round(2000.0 / dt)))        # 2 ps to decorrelate from the start
-        ref = sim.pos.clone()
-        T, E, msd = [], [], []
-        counts = np.zeros((2, 2, RDF_BINS))
-        for _ in range(n_samples):
-            sim.step(per)
-            e = sim.energies()[0]
-            T.append(e["tkin"])
-            E.append((e["pair"] + e["bond"] + e["angle"]) / (system.n_atoms / 3))
-            counts += sim.rdf_counts(RDF_RMAX, RDF_BINS)
-            msd.append(sim.msd(ref)[0, 0])
-        sim.close()
-        res = {}
-        for key, x in (("t_kin_K", np.array(T)), ("e_pot_per_water", np.array(E))):
-            blocks = x[: len(x) // 10 * 10].reshape(10, -1).mean(1)
-            res[key] = [round(float(x.mean()), 4), round(float(blocks.std(ddof=1) / np.sqrt(10)), 4)]
-        res.update(structure_summary(counts, n_samples, n_o, volume))
-        t_fs = 100.0 * np.arange(1, n_samples + 1)
-        half = n_samples // 2
-        slope = np.polyfit(t_fs[half:], np.array(msd)[half:], 1)[0]    # A^2 / fs
-        res["d_o_1e-5_cm2_s"] = round(float(slope / 6.0 * 1e4), 3)
-        out[name] = res
-        log(f"accuracy {name}: {res}")
-    # matched accuracy: |X - X_ref| <= |X_BAOAB - X_ref| + 2 sigma (sigma of X)
+        out[name] = accuracy_run(args, system, ff, state, integ, dt, m)
+        log(f"accuracy {name}: {out[name]}")
     ref, ba = out["baoab_0.25fs"], out["baoab_1fs"]
     for name in ("bounce_1fs", "bounce_respa_1_2fs"):
-        out[name]["matched"] = {
-            key: bool(abs(out[name][key][0] - ref[key][0]) <= abs(ba[key][0] - ref[key][0]) +
-                      2.0 * out[name][key][1])
-            for key in ("t_kin_K", "e_pot_per_water")}
+        out[name]["matched"] = matched(out[name], ref, ba)
+    if args.accuracy_splits:
+        sweep = {}
+        base = run_gpu(args, system, ff, B.BAOAB, state)
+        for r_on, r_off in args.accuracy_splits:
+            key = f"{r_on:g}/{r_off:g}"
+            res = accuracy_run(args, system, ff, state, B.BJAOAJB, 1.0, 0, r_on, r_off)
+            res["matched"] = matched(res, ref, ba)
+            sub = argparse.Namespace(**vars(args))
+            sub.r_on, sub.r_off = r_on, r_off
+            tm = run_gpu(sub, system, ff, B.BJAOAJB, state)
+            res["ms_per_step"] = round(tm["ms_per_step"], 5)
+            res["speedup_vs_baoab"] = round(base["ms_per_step"] / tm["ms_per_step"], 4)
+            res["proposals_per_step"] = tm["proposals_per_step"]
+            sweep[key] = res
+            log(f"accuracy sweep {key}: {res}")
+        out["split_sweep"] = dict(sweep, baoab_ms_per_step=round(base["ms_per_step"], 5))
     return out
 
 
@@ -408,6 +438,69 @@ def run_mesh(args, ff):
     return out
 
 
+def run_split(args, system, ff, state):
+    """The separate Coulomb and Lennard-Jones jump mechanisms (jump_split)
+    against the combined one on the same box and state, at the benchmark's
+    alpha and at 0.35/A: ms per step, jump proposals per atom and step (all,
+    and the Lennard-Jones share from a logged run), and the kinetic temperature
+    over the second of 2 ps (BAOAB at 1 fs alongside).  A run stopped by a
+    device condition (e.g. the skin guard after heating) is reported as such."""
+    import paper_2002_07109_amd as B
+    out = {"workload": "24,000-atom box, Coulomb window r'/r'' = %g/%g A; split: Lennard-Jones "
+                       "window %g/%g A" % (args.r_on, args.r_off, *args.split_lj)}
+    n = system.n_atoms
+    for alpha in sorted({args.alpha, 0.35}, reverse=True):
+        res = {}
+        for name, integ, split in (("baoab", B.BAOAB, 0), ("combined", B.BJAOAJB, 0),
+                                   ("split", B.BJAOAJB, 1)):
+            mk = lambda log: B.make_params(
+                integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_EWALD, periodic=1,
+                dt=1.0, gamma=1e-3, temperature=300.0, r_on=args.r_on, r_off=args.r_off, r_cut=9.0,
+                skin=args.skin, ewald_alpha=alpha, rebuild_interval=args.rebuild, seed=5,
+                cell_size=system.cell_size, use_graph=1, jump_split=split,
+                r_on_lj=args.split_lj[0] if split else 0.0,
+                r_off_lj=args.split_lj[1] if split else 0.0,
+                log_events=log, event_capacity=400000 if log else 0)
+            sim = B.Simulation(system, mk(0), ff["charge"], ff["eps"], ff["sigma"])
+            sim.set_state(pos=state[0], vel=state[1], step=0)
+            r = {}
+            try:
+                sim.step(1000)
+                sim.sync()
+                T = []
+                c0 = sim.counters()
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    sim.step(100)
+                    T.append(sim.energies()[0]["tkin"])
+                c1 = sim.counters()
+                r["t_kin_K"] = round(float(np.mean(T)), 2)
+                r["proposals_per_atom_step"] = (c1["proposals"] - c0["proposals"]) / (1000 * n)
+                r["accepted_per_atom_step"] = (c1["accepted"] - c0["accepted"]) / (1000 * n)
+                sim.step((-sim.get_step()) % args.rebuild + args.rebuild)
+                sim.sync()
+                t0 = time.perf_counter()
+                sim.step(500)
+                sim.sync()
+                r["ms_per_step"] = round(1e3 * (time.perf_counter() - t0) / 500, 5)
+            except B.BounceError as e:
+                r["stopped"] = str(e)
+            sim.close()
+            if integ == B.BJAOAJB and "stopped" not in r:
+                lg = B.Simulation(system, mk(1), ff["charge"], ff["eps"], ff["sigma"])
+                lg.set_state(pos=state[0], vel=state[1], step=0)
+                lg.step(50)
+                lg.sync()
+                ev, ne = lg.events()
+                lg.close()
+                r["lj_share_of_proposals"] = round(float((ev["mech"] == 1).mean()), 4) if len(ev) else 0.0
+                r["lj_proposals_per_atom_step"] = float((ev["mech"] == 1).sum()) / (50 * n)
+            res[name] = r
+            log(f"split mechanisms, alpha {alpha}: {name}: {r}")
+        out["alpha_%g" % alpha] = res
+    return out
+
+
 def cpu_baseline(args, system):
     """The FP64 oracle on a bounded sample of the same workload (its seeded
     input state), on all host cores."""
@@ -459,9 +552,19 @@ def main():
                     default=(7.0, 8.0), metavar="R_ON,R_OFF",
                     help="switching window r', r'' of the mesh workload (A); at its alpha = "
                          "0.35/A the 6/7 A split runs away within 1,000 steps")
+    ap.add_argument("--split", action="store_true",
+                    help="also compare separate Coulomb and Lennard-Jones jump mechanisms with "
+                         "the combined one (at the benchmark's alpha and at 0.35/A)")
+    ap.add_argument("--split-lj", type=lambda t: tuple(float(v) for v in t.split(",")),
+                    default=(5.0, 6.0), metavar="R_ON,R_OFF",
+                    help="Lennard-Jones switching window of the separate mechanisms (A)")
     ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
                     help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
                          "BAOAB at 0.25 fs over PS picoseconds each")
+    ap.add_argument("--accuracy-splits", default="",
+                    type=lambda t: [tuple(float(v) for v in p.split(",")) for p in t.split(";") if p],
+                    metavar="R_ON,R_OFF;...",
+                    help="with --accuracy: also run and time BOUNCE at these switching windows")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
@@ -593,6 +696,9 @@ def main():
     if args.mesh:
         log("timing the 96,000-atom box with the PME mesh")
         line["mesh_box"] = run_mesh(args, ff)
+    if args.split:
+        log("comparing separate and combined jump mechanisms")
+        line["split_mechanisms"] = run_split(args, system, ff, state)
     if args.accuracy > 0:
         line["accuracy"] = run_accuracy(args, system, ff, state)
     if not args.skip_cpu:
