@@ -38,7 +38,8 @@ TRANSC_PER_PAIR = 3
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_short_24k_box_traffic.md")
-PAIR_SOURCES = ("kernels_pair.hip", "bounce_device.hpp", "bounce_kernels.hpp", "bounce_lists.hpp")
+PAIR_SOURCES = ("kernels_pair.hip", "bounce_pairrow.hpp", "bounce_device.hpp", "bounce_kernels.hpp",
+                "bounce_lists.hpp")
 
 
 def log(msg):
@@ -501,24 +502,83 @@ def run_split(args, system, ff, state):
     return out
 
 
-def cpu_baseline(args, system):
-    """The FP64 oracle on a bounded sample of the same workload (its seeded
-    input state), on all host cores."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(args):
+    """One oracle leg, run in a child process whose OMP_NUM_THREADS fixes the
+    thread count: `steps` steps of the seeded 24,000-atom box (the list search
+    runs at step 0 and every `rebuild` steps), then one list search of the same
+    kind timed alone so that its share of the wall time can be stated."""
+    import ctypes
     from oracle import oracle as orc
-    orc.build(force=False)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    p = orc.make_params(system, integrator=orc.BOUNCE, r_on=args.r_on, r_off=args.r_off,
+    from workloads import water_box
+    integ = {"bounce": orc.BOUNCE, "baoab": orc.BAOAB}[args.cpu_leg]
+    system = water_box(n_side=20, box_len=62.0, seed=0)
+    p = orc.make_params(system, integrator=integ, r_on=args.r_on, r_off=args.r_off,
                         r_cut=9.0, skin=args.skin, rebuild_interval=args.rebuild,
                         ewald_alpha=args.alpha)
     topo = orc.Topology.from_system(system)
     t0 = time.perf_counter()
     o = orc.run(p, topo, system.pos, system.vel, 0, args.cpu_steps)
     wall = time.perf_counter() - t0
-    ns_day = args.cpu_steps * 1.0 * 1e-6 / wall * 86400.0
-    return dict(value=ns_day, unit="ns/day", cores=cores, kind="oracle",
-                sample=f"{args.cpu_steps} BOUNCE steps (list rebuilt every {args.rebuild}, O(N^2) "
-                       f"search) of the 24,000-atom box from its seeded input, {wall:.1f} s wall",
-                status=o["status_name"])
+    order, _ = orc.sort_order(p, system.pos)
+    t0 = time.perf_counter()
+    r_force = (args.r_off if integ == orc.BOUNCE else 9.0) + args.skin
+    orc.build_list(p, topo, system.pos, 0.0, r_force, order)
+    if integ == orc.BOUNCE:
+        orc.build_list(p, topo, system.pos, args.r_on - args.skin, 9.0 + args.skin, order)
+    t_list = time.perf_counter() - t0
+    try:
+        threads = ctypes.CDLL("libgomp.so.1").omp_get_max_threads()
+    except OSError:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    rebuilds = int(o["counters"]["rebuilds"])
+    print(json.dumps(dict(integrator=args.cpu_leg, steps=args.cpu_steps, wall_s=wall,
+                          threads=threads, rebuilds=rebuilds, list_search_s=t_list,
+                          status=o["status_name"])), flush=True)
+
+
+def cpu_baseline(args, system):
+    """The FP64 oracle on bounded samples of the same workload (its seeded input
+    state): BOUNCE and BAOAB, on one thread and on all host threads, each in a
+    child process.  `value` is BOUNCE on all threads.  The oracle's list search
+    is a plain O(N^2) loop; each leg states its share of the wall time and the
+    rate with it taken out."""
+    import subprocess
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    legs = {}
+    for integ in ("bounce", "baoab"):
+        for threads, steps in ((all_threads, args.cpu_steps), (1, args.cpu_steps_single)):
+            env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+            cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", integ,
+                   "--cpu-steps", str(steps), "--r-on", str(args.r_on), "--r-off", str(args.r_off),
+                   "--skin", str(args.skin), "--rebuild", str(args.rebuild), "--alpha", str(args.alpha)]
+            log(f"oracle leg: {integ}, {threads} thread(s), {steps} steps")
+            out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True)
+            r = json.loads(out.stdout.strip().splitlines()[-1])
+            list_s = r["rebuilds"] * r["list_search_s"]
+            rest = max(r["wall_s"] - list_s, 1e-9)
+            legs[f"{integ}_{r['threads']}t"] = {
+                "ns_per_day": round(steps * 1e-6 / r["wall_s"] * 86400.0, 5),
+                "ns_per_day_without_list_search": round(steps * 1e-6 / rest * 86400.0, 5),
+                "threads": r["threads"], "steps": steps, "wall_s": round(r["wall_s"], 2),
+                "list_searches": r["rebuilds"], "list_search_share": round(min(list_s / r["wall_s"], 1.0), 3),
+                "status": r["status"]}
+    main_leg = legs[f"bounce_{all_threads}t"] if f"bounce_{all_threads}t" in legs else next(iter(legs.values()))
+    return dict(value=main_leg["ns_per_day"], unit="ns/day", cores=main_leg["threads"], kind="oracle",
+                sample=f"{main_leg['steps']} BOUNCE steps of the 24,000-atom box from its seeded input "
+                       f"(list search at step 0 and every {args.rebuild} steps), "
+                       f"{main_leg['wall_s']:.1f} s wall on {main_leg['threads']} threads",
+                cpu_model=cpu_model(), host_threads=len(os.sched_getaffinity(0)), legs=legs)
 
 
 def main():
@@ -536,7 +596,11 @@ def main():
     ap.add_argument("--rate-mode", choices=sorted(RATE_MODES), default="atom",
                     help="jump rate bounds of the headline BOUNCE run: one per atom type "
                          "(atom) or per type pair, superposed (pair); the other is also timed")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps-single", type=int, default=2,
+                    help="steps of the one-thread oracle legs")
+    ap.add_argument("--cpu-leg", choices=("bounce", "baoab"), default=None,
+                    help=argparse.SUPPRESS)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--batch", action="store_true",
                     help="also time 64 uneven droplets in one context")
@@ -568,6 +632,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); no multi-GPU "
               "decomposition is built.", file=sys.stderr)

@@ -604,7 +604,7 @@ struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w;
-    size_t ls[2][17];
+    size_t ls[2][18];
 };
 
 // wavefront slots of the integrator and jump kernels (4 lanes per atom)
@@ -671,7 +671,8 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
         q[11] = L.take(4 * n * ncls * std::max<size_t>(1, ccap) + 4 * n * ncls);  // ccnt + clist
         q[12] = k == 0 ? L.take(sizeof(int4) * BTMAX * n) : 0;       // bslot (main set)
         q[13] = L.take(sizeof(int2) * n);                               // sinfo
-        q[14] = L.take(4 * ((size_t)c->n_cells / 1024 + 2));            // scan_part
+        q[14] = L.take(8 * ((size_t)c->n_cells / 1024 + 2));            // scan_part
+        q[17] = L.take(4 * ((size_t)c->n_cells + 1));                   // busy
         const bool fx = k == 0 && c->fixed;
         q[15] = fx ? L.take(16 * n) : 0;                                // xf[0]
         q[16] = fx ? L.take(16 * n) : 0;                                // xf[1]
@@ -853,6 +854,7 @@ static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, d
         ls.bslot = k == 0 ? at<int4>(ws, q[12]) : nullptr;
         ls.sinfo = at<int2>(ws, q[13]);
         ls.scan_part = at<int32_t>(ws, q[14]);
+        ls.busy = at<int32_t>(ws, q[17]);
         ls.fcap = k == 0 ? c->fcap : c->acap;
         ls.ccap = k == 0 ? c->ccap : 0;
         ls.n_cells = c->n_cells;

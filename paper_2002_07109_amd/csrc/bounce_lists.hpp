@@ -11,7 +11,10 @@ struct ListSet {
     int32_t *slot;        // caller id -> arrival slot in its cell
     int32_t *cell_count;  // [n_cells]
     int32_t *cell_start;  // [n_cells + 1]
-    int32_t *scan_part;   // [ceil(n_cells / 1024)] block sums of the cell-count scan
+    int32_t *scan_part;   // [2 ceil(n_cells / 1024)] block sums of the cell-count scan
+                          //   and of the occupied-cell count
+    int32_t *busy;        // [n_cells + 1] occupied cells: [0] their number, then their
+                          //   indices in ascending order
     int2 *sinfo;          // sorted position -> (caller id, replica)
     double4 *x[2];        // sorted positions (x, y, z, type), double-buffered by step parity
     double *q_build;      // [N][3] positions at the build (skin guard)

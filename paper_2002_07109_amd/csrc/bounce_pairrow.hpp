@@ -21,14 +21,14 @@ __device__ __forceinline__ int32_t row_slot(int32_t e, int32_t nn, int32_t tail)
 }
 
 // The pair's scalar s with gradient s d: SHORT (1 - chi) W'_sf / r, LONG
-// chi W'_sf / r (r > r'), FULL W'_sf / r; with separate mechanisms each of the
-// Coulomb and Lennard-Jones parts with its own switch (pg.split is uniform).
-template <typename R, int MODE>
+// chi W'_sf / r (r > r'), FULL W'_sf / r; with separate mechanisms (SPLIT) each of
+// the Coulomb and Lennard-Jones parts with its own switch.
+template <typename R, int MODE, bool SPLIT>
 __device__ __forceinline__ R pair_scalar(R r2, const TypePair<R> &tp, const PairGlobals &pg, R alpha,
                                          R r_on, R inv_w, R r_on_v, R inv_w_v)
 {
     R r, rinv;
-    if (MODE != MODE_FULL && pg.split) {
+    if (MODE != MODE_FULL && SPLIT) {
         R dwc, dwv;
         pair_dw_parts<R>(r2, tp, alpha, pg.coulomb, r, rinv, dwc, dwv);
         const R cc = switch_chi<R>(r, r_on, inv_w), cv = switch_chi<R>(r, r_on_v, inv_w_v);
@@ -41,7 +41,7 @@ __device__ __forceinline__ R pair_scalar(R r2, const TypePair<R> &tp, const Pair
     return dw * rinv;
 }
 
-template <typename R, int MODE, int G>
+template <typename R, int MODE, int G, bool SPLIT>
 __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, const double4 &xi,
                                                const BoxReg &box, const int32_t *__restrict__ row,
                                                int32_t nn, int32_t cnt, int32_t cap, int lig, int32_t self,
@@ -94,7 +94,7 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
             const R r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
             if (!(r2 < lim2)) continue;
             const TypePair<R> &tp = tab_i[mirror_type(xj[u].w)];
-            const R f = pair_scalar<R, MODE>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
+            const R f = pair_scalar<R, MODE, SPLIT>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
             px += f * rx;
             py += f * ry;
             pz += f * rz;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
 // (minimum image by two's-complement wrap in a periodic box), exact to their
 // rounding, and is converted to A by one FP32 rounding per axis.  Per entry:
 // the index load, one 16-byte gather, integer and FP32 arithmetic only.
-template <int MODE, int G>
+template <int MODE, int G, bool SPLIT>
 __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF, const int4 &xi,
                                                      const float fu[3],
                                                      const int32_t *__restrict__ row, int32_t nn,
@@ -159,7 +159,7 @@ __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF
             const float r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
             if (!(r2 < lim2)) continue;
             const TypePair<float> &tp = tab_i[xj[u].w];
-            const float f = pair_scalar<float, MODE>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
+            const float f = pair_scalar<float, MODE, SPLIT>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
             px += f * rx;
             py += f * ry;
             pz += f * rz;

@@ -54,6 +54,9 @@ __global__ void k_bin(int32_t n, const double *__restrict__ pos, const RepInfo *
 // Exclusive scan of the cell counts into cell_start (and the counts cleared
 // for the next build), in two launches: the totals of blocks of 1024 cells,
 // then the scan inside each block offset by the totals of the blocks before it.
+// The same two passes scan the flags "cell holds an atom" into the list of
+// occupied cells (busy), which the later build kernels walk instead of the
+// whole grid (a droplet's grid is mostly empty).
 constexpr int SCAN_B = 1024;
 
 __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t *wsum)
@@ -80,40 +83,65 @@ __device__ __forceinline__ int32_t block_incl_scan(int32_t v, int32_t *wsum)
     return v + (w > 0 ? wsum[w - 1] : 0);
 }
 
+// scan_part[b]: atoms in block b of cells; scan_part[nsb + b]: occupied cells there
 __global__ void __launch_bounds__(SCAN_B) k_scan_part(int32_t n_cells, ListSet ls)
 {
-    __shared__ int32_t wsum[SCAN_B / 64];
+    __shared__ int32_t wsum[SCAN_B / 64], wsum_b[SCAN_B / 64];
+    const int32_t nsb = (n_cells + SCAN_B - 1) / SCAN_B;
     const int32_t k = blockIdx.x * SCAN_B + threadIdx.x;
     const int32_t v = k < n_cells ? ls.cell_count[k] : 0;
     const int32_t incl = block_incl_scan(v, wsum);
-    if (threadIdx.x == SCAN_B - 1) ls.scan_part[blockIdx.x] = incl;
+    const int32_t incl_b = block_incl_scan(v > 0 ? 1 : 0, wsum_b);
+    if (threadIdx.x == SCAN_B - 1) {
+        ls.scan_part[blockIdx.x] = incl;
+        ls.scan_part[nsb + blockIdx.x] = incl_b;
+    }
 }
 
 // the scan inside each block, offset by the sum of the earlier blocks' totals
 __global__ void __launch_bounds__(SCAN_B) k_scan_fin(int32_t n_cells, ListSet ls)
 {
-    __shared__ int32_t wsum[SCAN_B / 64];
-    __shared__ int32_t s_off;
-    int32_t o = 0;
-    for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += SCAN_B) o += ls.scan_part[b];
+    __shared__ int32_t wsum[SCAN_B / 64], wsum_b[SCAN_B / 64];
+    __shared__ int32_t s_off, s_off_b;
+    const int32_t nsb = (n_cells + SCAN_B - 1) / SCAN_B;
+    int32_t o = 0, ob = 0;
+    for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += SCAN_B) {
+        o += ls.scan_part[b];
+        ob += ls.scan_part[nsb + b];
+    }
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) o += __shfl_xor(o, m, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = o;
+    for (int m = 32; m >= 1; m >>= 1) {
+        o += __shfl_xor(o, m, 64);
+        ob += __shfl_xor(ob, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = o;
+        wsum_b[threadIdx.x >> 6] = ob;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t t = 0;
-        for (int w = 0; w < SCAN_B / 64; ++w) t += wsum[w];
+        int32_t t = 0, tb = 0;
+        for (int w = 0; w < SCAN_B / 64; ++w) {
+            t += wsum[w];
+            tb += wsum_b[w];
+        }
         s_off = t;
+        s_off_b = tb;
     }
     __syncthreads();
     const int32_t k = blockIdx.x * SCAN_B + threadIdx.x;
     const int32_t v = k < n_cells ? ls.cell_count[k] : 0;
     const int32_t incl = block_incl_scan(v, wsum) + s_off;
+    const int32_t incl_b = block_incl_scan(v > 0 ? 1 : 0, wsum_b) + s_off_b;
     if (k < n_cells) {
         ls.cell_start[k] = incl - v;
         ls.cell_count[k] = 0;
+        if (v > 0) ls.busy[incl_b] = k;          // busy[1 + rank among occupied cells]
     }
-    if (k == n_cells - 1) ls.cell_start[n_cells] = incl;
+    if (k == n_cells - 1) {
+        ls.cell_start[n_cells] = incl;
+        ls.busy[0] = incl_b;
+    }
 }
 
 __global__ void k_scatter(int32_t n, ListSet ls)
@@ -130,42 +158,46 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wavefront per cell: order the cell's atoms by caller id (rank sort over
-// the lanes; a serial insertion sort above 64 atoms) and fill the mirror.
-__global__ void __launch_bounds__(256) k_cellsort(int32_t n_cells, const double *__restrict__ pos,
+// One wavefront per occupied cell (grid-stride over the busy list): order the
+// cell's atoms by caller id (rank sort over the lanes; a serial insertion sort
+// above 64 atoms) and fill the mirror.
+__global__ void __launch_bounds__(256) k_cellsort(const double *__restrict__ pos,
                                                   const RepInfo *__restrict__ reps, Topo tp,
                                                   ListSet ls, const DevState *st,
                                                   int32_t mirror_sel, int32_t step_off)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (c >= n_cells) return;                       // uniform per wavefront
-    const int32_t b = ls.cell_start[c], e = ls.cell_start[c + 1], m = e - b;
-    int32_t *p = ls.perm;
-    if (m <= 64) {
-        const int32_t mine = lane < m ? p[b + lane] : 0x7fffffff;
-        int32_t rank = 0;
-        for (int32_t k = 0; k < m; ++k) rank += __shfl(mine, k, 64) < mine;
-        wave_sync();
-        if (lane < m) p[b + rank] = mine;
-    } else if (lane == 0) {
-        for (int32_t i = b + 1; i < e; ++i) {
-            int32_t v = p[i], j = i - 1;
-            while (j >= b && p[j] > v) { p[j + 1] = p[j]; --j; }
-            p[j + 1] = v;
-        }
-    }
-    __threadfence_block();
-    wave_sync();
+    const int32_t nbusy = ls.busy[0];
+    const int32_t waves = gridDim.x * (blockDim.x >> 6);
     const int32_t par = mirror_sel >= 0 ? mirror_sel : (int32_t)((st->step + step_off) & 1);
     double4 *X = ls.x[par];
-    for (int32_t i = b + lane; i < e; i += 64) {
-        const int32_t g = p[i];
-        ls.inv_perm[g] = i;
-        ls.sinfo[i] = make_int2(g, tp.rep_of[g]);
-        const double *x = pos + 3 * (int64_t)g;
-        X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
-        if (ls.xf[par]) ls.xf[par][i] = fixed_pos(reps[tp.rep_of[g]], x[0], x[1], x[2], tp.type[g]);
+    int32_t *p = ls.perm;
+    for (int32_t idx = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); idx < nbusy; idx += waves) {
+        const int32_t c = ls.busy[1 + idx];             // uniform per wavefront
+        const int32_t b = ls.cell_start[c], e = ls.cell_start[c + 1], m = e - b;
+        if (m <= 64) {
+            const int32_t mine = lane < m ? p[b + lane] : 0x7fffffff;
+            int32_t rank = 0;
+            for (int32_t k = 0; k < m; ++k) rank += __shfl(mine, k, 64) < mine;
+            wave_sync();
+            if (lane < m) p[b + rank] = mine;
+        } else if (lane == 0) {
+            for (int32_t i = b + 1; i < e; ++i) {
+                int32_t v = p[i], j = i - 1;
+                while (j >= b && p[j] > v) { p[j + 1] = p[j]; --j; }
+                p[j + 1] = v;
+            }
+        }
+        __threadfence_block();
+        wave_sync();
+        for (int32_t i = b + lane; i < e; i += 64) {
+            const int32_t g = p[i];
+            ls.inv_perm[g] = i;
+            ls.sinfo[i] = make_int2(g, tp.rep_of[g]);
+            const double *x = pos + 3 * (int64_t)g;
+            X[i] = make_double4(x[0], x[1], x[2], mirror_w(g, tp.type[g]));
+            if (ls.xf[par]) ls.xf[par][i] = fixed_pos(reps[tp.rep_of[g]], x[0], x[1], x[2], tp.type[g]);
+        }
     }
 }
 
@@ -208,8 +240,10 @@ constexpr int LMAXI = 64;      // atoms per cell handled
 constexpr int LDIM = 12;       // candidate cells per dimension
 constexpr int LCELLS = 352;    // candidate cells kept per cell
 constexpr int LEXCL = 8;       // exclusions per atom held in registers
+constexpr int LGRID = 4096;    // workgroups of the list kernel (it strides over further cells)
 
-// One workgroup per cell.  (1) Wavefront 0 enumerates the candidate cells
+// Workgroups walk the occupied cells (grid-stride over the busy list), one
+// cell at a time.  (1) Wavefront 0 enumerates the candidate cells
 // (cell gap below the search radius) in ascending cell index, fetching their
 // atom ranges in parallel and compacting them by ballots, and prefix-sums the
 // range sizes.  (2) The workgroup stages a batch of candidate atoms (slot,
@@ -235,7 +269,9 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     __shared__ int32_t iex[LMAXI][LEXCL];
     __shared__ int32_t s_ncells;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int32_t ci = blockIdx.x;
+    const int32_t nbusy = ls.busy[0];
+    for (int32_t idx = blockIdx.x; idx < nbusy; idx += gridDim.x) {
+    const int32_t ci = ls.busy[1 + idx];              // uniform per workgroup
     const int32_t bi = ls.cell_start[ci], ei_all = ls.cell_start[ci + 1];
     const int32_t ei = min(ei_all, bi + LMAXI), ni = ei - bi;
     if (ls.bslot)     // this cell's rows of the bonded-term table
@@ -246,7 +282,7 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
         if (bs.want_cand)
             for (int b = 0; b < ls.ncls; ++b) ls.ccnt[(int64_t)i * ls.ncls + b] = 0;
     }
-    if (ni == 0) return;                             // uniform per workgroup
+    if (ni == 0) continue;                           // uniform per workgroup
     const RepInfo &ri = reps[cell_rep[ci]];
     const BoxReg box(ri);
     const int32_t par = bs.mirror_sel >= 0 ? bs.mirror_sel : (int32_t)((st->step + bs.step_off) & 1);
@@ -477,7 +513,9 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                 if (nc > ls.ccap) overflow = true;
             }
     }
+    // (the barrier also ends every use of this cell's shared arrays)
     if (__syncthreads_or(overflow) && threadIdx.x == 0) atomicOr(&st->status, ST_CAPACITY);
+    }
 }
 
 // Pair-structure histogram over the rows of a list set built at or beyond
@@ -546,11 +584,14 @@ void launch_build(hipStream_t sm, int32_t n, const double *pos, const RepInfo *r
     hipLaunchKernelGGL(k_scan_part, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scan_fin, dim3(nsb), dim3(SCAN_B), 0, sm, ls.n_cells, ls);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, sm, n, ls);
-    hipLaunchKernelGGL(k_cellsort, dim3((ls.n_cells + 3) / 4), dim3(256), 0, sm, ls.n_cells,
+    // occupied cells: at most min(n_cells, n); the grids are sized for one
+    // pass over the occupied cells of a dense box and stride over the rest
+    const int32_t maxbusy = std::min(ls.n_cells, n);
+    hipLaunchKernelGGL(k_cellsort, dim3(std::min((maxbusy + 3) / 4, 2048)), dim3(256), 0, sm,
                        pos, reps, tp, ls, st, bs.mirror_sel, bs.step_off);
     // candidate classes rounded up to 1, 2, 4 or 8 (one class: no per-class appends)
     const int nc = bs.want_cand ? ls.ncls : 1;
-    const dim3 grid(ls.n_cells), block(64 * LB);
+    const dim3 grid(std::min(maxbusy, LGRID)), block(64 * LB);
     if (nc <= 1)
         hipLaunchKernelGGL(k_lists<1>, grid, block, 0, sm, ls.n_cells, reps, cell_rep, pos, tp, ls, bs, st);
     else if (nc <= 2)

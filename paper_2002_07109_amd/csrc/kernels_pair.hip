@@ -136,11 +136,17 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
             const RepInfo &rp = ONE ? a.reps[0] : a.reps[si.y];
             const float fu[3] = {rp.funit[0], rp.funit[1], rp.funit[2]};
             const int4 *__restrict__ XF = a.ls.xf[par];
-            pair_force_row_fixed<MODE, G>(XF, XF[s], fu, row, nn, cnt, cap, lig, s,
-                                          reinterpret_cast<const TypePair<float> *>(tab) + ti * nt,
-                                          a.pg, ax, ay, az);
+            const TypePair<float> *tf = reinterpret_cast<const TypePair<float> *>(tab) + ti * nt;
+            // the separate-mechanism flag is uniform: one branch outside the loop
+            if (MODE != MODE_FULL && a.pg.split)
+                pair_force_row_fixed<MODE, G, true>(XF, XF[s], fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
+            else
+                pair_force_row_fixed<MODE, G, false>(XF, XF[s], fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
         } else if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
-            pair_force_row<R, MODE, G>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
+            if (MODE != MODE_FULL && a.pg.split)
+                pair_force_row<R, MODE, G, true>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
+            else
+                pair_force_row<R, MODE, G, false>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
         } else {
         // energies and parameter-gradient bases: U entries per lane in flight
         constexpr int U = 4;
