@@ -121,6 +121,14 @@ typedef struct {
        and F_0 keeps (1 - chi_C) W'_C + (1 - chi_V) W'_V.  Needs n_types <= 4.     */
     int32_t jump_split;
     double r_on_lj, r_off_lj;  /* the Lennard-Jones window (both 0: that of Coulomb)      */
+    /* 1: each step (F_0 pair force plus the integrator of every replica) is one
+       persistent launch whose workgroups take (replica, atom tile) items from a
+       queue, with a per-replica counter of finished pair items in place of a
+       grid-wide barrier; 8 lanes per atom in its pair part.  0: a pair-force and
+       an integrator launch per step.  Both give bit-identical results.  Applies
+       when the short-range pair force is in F_0 and no mesh force is (else 0). */
+    int32_t persistent;
+    int32_t pad_p;
 } bounce_params;
 
 typedef struct {
@@ -311,7 +319,11 @@ bounce_status bounce_direct_energy_bwd(bounce_ctx *ctx, const double *pos_dev,
                 trajectory by reps + 1 steps; only that kernel is timed);
      which = 4: the reciprocal-space mesh sum (spread, FFT, convolution, FFT
                 back, gather) at the current positions, reps times; needs
-                pme_grid; the trajectory is unchanged. */
+                pme_grid; the trajectory is unchanged;
+     which = 5: a dry step as two launches: the F_0 pair kernel, then the
+                integrator with its kicks, jumps and drifts off (trajectory
+                unchanged);
+     which = 6: the same dry step as one fused launch (needs persistent = 1). */
 bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps, double *avg_ms);
 
 /* Autotuner: time the F_0 pair kernel (reps launches each) with 4, 8, 16 and 32
@@ -319,6 +331,30 @@ bounce_status bounce_profile_kernel(bounce_ctx *ctx, int32_t which, int32_t reps
    return it in *lanes_out; ms_out (NULL or [4]) receives the mean times.
    Synchronous; leaves the trajectory unchanged. */
 bounce_status bounce_autotune(bounce_ctx *ctx, int32_t reps, int32_t *lanes_out, double *ms_out);
+
+/* What bounce_autotune_cached chose and measured (ms; -1: not timed). */
+typedef struct {
+    int32_t pair_lanes;        /* lanes per atom of the F_0 pair kernel                   */
+    int32_t persistent;        /* 1: one fused launch per step                            */
+    double pair_ms[4];         /* the pair kernel with 4, 8, 16, 32 lanes                 */
+    double step_ms[2];         /* a dry step (which = 5, 6 of bounce_profile_kernel):     */
+                               /*   two launches with the chosen lanes, one fused launch  */
+    int32_t from_cache;        /* 1: read from the cache file, nothing timed              */
+    int32_t pad;
+} bounce_tuning;
+
+/* Autotuner over the pair kernel's lanes per atom and the launch structure
+   (two launches per step, or one fused persistent launch where the schedule
+   allows it: bounce_params.persistent).  The choice is kept in the context
+   (bit-identical results either way) and, with cache_path non-NULL, in a cache
+   file of JSON lines keyed by the device (name, architecture, compute units)
+   and the system and parameters the kernels depend on: a later call with the
+   same key reads the choice back and times nothing.  The file is appended to
+   and never rewritten; concurrent writers are not coordinated.  Synchronous;
+   leaves the trajectory unchanged.  BOUNCE_E_ARG: reps < 1, out NULL, or the
+   cache file cannot be written. */
+bounce_status bounce_autotune_cached(bounce_ctx *ctx, int32_t reps, const char *cache_path,
+                                     bounce_tuning *out);
 
 const char *bounce_status_string(int32_t status);
 const char *bounce_last_error(const bounce_ctx *ctx);

@@ -9,6 +9,7 @@ marshals torch tensors (device memory, current HIP stream) into those calls and
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -38,13 +39,14 @@ def make_params(**kw) -> bounce_params:
     respa_m >= 1 and respa_outer = OUTER_NONBONDED the short-range pair force
     moves to the outer step too; jump_split = 1 gives the Coulomb and the
     Lennard-Jones long-range parts separate jump mechanisms (the LJ window
-    r_on_lj, r_off_lj defaults to the Coulomb one)."""
+    r_on_lj, r_off_lj defaults to the Coulomb one); persistent = 1 makes each step one
+    persistent launch over all replicas."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
              pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0,
-             respa_outer=OUTER_RECIP, jump_split=0, r_on_lj=0.0, r_off_lj=0.0)
+             respa_outer=OUTER_RECIP, jump_split=0, r_on_lj=0.0, r_off_lj=0.0, persistent=0)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():
@@ -301,6 +303,20 @@ class Simulation:
         check(self.L.bounce_autotune(self.ctx, int(reps), C.byref(lanes), _ptr(ms)), self.ctx,
               "bounce_autotune")
         return lanes.value, dict(zip((4, 8, 16, 32), ms.tolist()))
+
+    def tune(self, reps=20, cache=None):
+        """Pick the pair kernel's lanes per atom and the launch structure (two
+        launches or one fused launch per step) by timing, or read them from the
+        JSON-lines cache file `cache` when it holds this device and
+        configuration; returns the choice and the times as a dict."""
+        t = _abi.bounce_tuning()
+        path = None if cache is None else os.fsencode(os.fspath(cache))
+        check(self.L.bounce_autotune_cached(self.ctx, int(reps), path, C.byref(t)), self.ctx,
+              "bounce_autotune_cached")
+        return {"pair_lanes": t.pair_lanes, "persistent": t.persistent,
+                "pair_ms": dict(zip((4, 8, 16, 32), list(t.pair_ms))),
+                "step_ms": {"two_launches": t.step_ms[0], "fused": t.step_ms[1]},
+                "from_cache": bool(t.from_cache)}
 
     def close(self):
         if getattr(self, "ctx", None):

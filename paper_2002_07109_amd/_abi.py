@@ -35,7 +35,7 @@ class bounce_params(C.Structure):
                 ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32),
                 ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32), ("respa_m", C.c_int32),
                 ("respa_outer", C.c_int32), ("jump_split", C.c_int32), ("r_on_lj", C.c_double),
-                ("r_off_lj", C.c_double)]
+                ("r_off_lj", C.c_double), ("persistent", C.c_int32), ("pad_p", C.c_int32)]
 
 
 class bounce_system(C.Structure):
@@ -65,6 +65,11 @@ vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
 ctx_p = C.c_void_p
 
 # name -> (restype, argtypes); one entry per function of include/bounce.h
+class bounce_tuning(C.Structure):
+    _fields_ = [("pair_lanes", C.c_int32), ("persistent", C.c_int32), ("pair_ms", C.c_double * 4),
+                ("step_ms", C.c_double * 2), ("from_cache", C.c_int32), ("pad", C.c_int32)]
+
+
 SIGNATURES = {
     "bounce_create": (i32, [_P(bounce_params), _P(ctx_p)]),
     "bounce_destroy": (None, [ctx_p]),
@@ -92,6 +97,7 @@ SIGNATURES = {
     "bounce_direct_energy_bwd": (i32, [ctx_p, vp, vp, vp, vp, vp]),
     "bounce_profile_kernel": (i32, [ctx_p, i32, i32, _P(C.c_double)]),
     "bounce_autotune": (i32, [ctx_p, i32, _P(i32), vp]),
+    "bounce_autotune_cached": (i32, [ctx_p, i32, C.c_char_p, _P(bounce_tuning)]),
     "bounce_status_string": (C.c_char_p, [i32]),
     "bounce_last_error": (C.c_char_p, [ctx_p]),
 }

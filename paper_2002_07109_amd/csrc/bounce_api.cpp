@@ -155,6 +155,12 @@ struct bounce_ctx {
     PmeAtoms pme_atoms{};
     std::vector<int32_t> cell_rep;
     int32_t *d_xcnt = nullptr, *d_xcol = nullptr;
+    // fused step launch: items (replica, first sorted atom, end, kind), pair
+    // items per replica, the queue counters, and the launch's workgroups
+    std::vector<int4> fitems;
+    std::vector<int32_t> fneed;
+    FusedArgs fused{};
+    int32_t fused_grid = 0;
     // schedule
     int64_t step = 0;             // host view: device counter + pending
     int32_t pending = 0;          // steps opened since the device counter last moved
@@ -221,6 +227,7 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->respa_m < 0 || (p->respa_m > 0 && p->rebuild_interval % p->respa_m)) return BOUNCE_E_ARG;
     if (p->respa_outer != BOUNCE_OUTER_RECIP && p->respa_outer != BOUNCE_OUTER_NONBONDED) return BOUNCE_E_ARG;
     if (p->respa_outer == BOUNCE_OUTER_NONBONDED && p->respa_m < 1) return BOUNCE_E_ARG;
+    if (p->persistent != 0 && p->persistent != 1) return BOUNCE_E_ARG;
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
@@ -496,6 +503,20 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
         int32_t e = r + 1 < R ? c->reps[r + 1].cell_off : cell_off;
         for (int32_t k = c->reps[r].cell_off; k < e; ++k) c->cell_rep[k] = r;
     }
+    // fused step items: a replica's atoms occupy its own cells, so in sorted
+    // order they are the contiguous range [offset_r, offset_r+1); every pair
+    // item ahead of every integrator item
+    c->fitems.clear();
+    c->fneed.assign(R, 0);
+    for (int kind = 0; kind < 2; ++kind)
+        for (int32_t r = 0; r < R; ++r) {
+            const int32_t tile = kind == 0 ? PAIR_ATOMS : STEP_ATOMS;
+            for (int64_t b = c->rep_off[r]; b < c->rep_off[r + 1]; b += tile) {
+                const int64_t e = std::min<int64_t>(b + tile, c->rep_off[r + 1]);
+                c->fitems.push_back(make_int4(r, (int32_t)b, (int32_t)e, kind));
+                if (kind == 0) c->fneed[r]++;
+            }
+        }
     // row capacities: 1.5 x the mean count in the list sphere at the densest replica
     auto cap = [&](double r) {
         double m = 1.5 * max_rho * 4.18879020478639 * r * r * r + 64.0;
@@ -603,12 +624,15 @@ static T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off);
 struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
-        seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w;
+        seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w, fitems, fneed,
+        fqueue;
     size_t ls[2][18];
 };
 
-// wavefront slots of the integrator and jump kernels (4 lanes per atom)
-static int64_t wave_slots(const bounce_ctx *c) { return ((int64_t)c->n * 4 + 63) / 64 + 1; }
+// wavefront slots of the integrator and jump kernels (4 lanes per atom, 64
+// atoms per workgroup of 4 wavefronts; the fused launch has at most as many
+// workgroups)
+static int64_t wave_slots(const bounce_ctx *c) { return 4 * (((int64_t)c->n + 63) / 64) + 4; }
 
 static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
 {
@@ -653,6 +677,9 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.pme_w = L.take(8 * 3 * (size_t)std::max(1, c->p.pme_order) * pn);
     o.xcnt = L.take(4 * n);
     o.xcol = L.take(4 * n * (size_t)c->xcap);
+    o.fitems = L.take(16 * std::max<size_t>(1, c->fitems.size()));
+    o.fneed = L.take(4 * R);
+    o.fqueue = L.take(4 * (R + 1));
     for (int k = 0; k < 2; ++k) {
         const size_t fcap = k == 0 ? c->fcap : c->acap, ccap = k == 0 ? c->ccap : 0;
         size_t *q = o.ls[k];
@@ -791,6 +818,22 @@ static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, d
     HIPCHK(c, hipMemsetAsync(ws + o.st, 0, sizeof(DevState), sm));
     HIPCHK(c, hipMemsetAsync(ws + o.cnt, 0, sizeof(RepCounters) * CNT_SPREAD * c->R, sm));
     HIPCHK(c, hipMemsetAsync(ws + o.wave_cnt, 0, 8 * 3 * (size_t)wave_slots(c), sm));
+    HIPCHK(c, up(sm, ws, o.fitems, c->fitems));
+    HIPCHK(c, up(sm, ws, o.fneed, c->fneed));
+    HIPCHK(c, hipMemsetAsync(ws + o.fqueue, 0, 4 * ((size_t)c->R + 1), sm));
+    c->fused.items = at<int4>(ws, o.fitems);
+    c->fused.need = at<int32_t>(ws, o.fneed);
+    c->fused.queue = at<uint32_t>(ws, o.fqueue);
+    c->fused.n_items = (int32_t)c->fitems.size();
+    c->fused.n_reps = c->R;
+    {
+        // at most as many workgroups as can be resident, and no more than the
+        // integrator items (the one-replica jump counters have a slot per wavefront)
+        const int32_t steps = (int32_t)(c->fitems.size()) - [&] { int32_t s = 0; for (int32_t v : c->fneed) s += v; return s; }();
+        c->fused_grid = std::max(1, std::min(fused_resident_groups(c->p.pair_precision == BOUNCE_PAIR_FP64,
+                                                                   c->p.integrator == BOUNCE_BJAOAJB),
+                                             steps));
+    }
     Topo &t = c->tp;
     t.type = at<int32_t>(ws, o.type);
     t.rep_of = at<int32_t>(ws, o.rep_of);
@@ -1118,6 +1161,24 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
     return a;
 }
 
+// one launch per step (F_0 pair force + integrator): only where F_0 carries the
+// short-range pair force and no mesh force
+static bool use_fused(const bounce_ctx *c)
+{
+    return c->p.persistent && !c->out_pair && !(c->pme && c->p.respa_m == 0) && !c->outer;
+}
+
+static void launch_fused_step(bounce_ctx *c, const StepArgs &a, int32_t step_off)
+{
+    PairArgs p = pair_args(c, c->main, -1);
+    p.step_off = step_off;
+    p.far_gate = 0.5 * c->p.skin - 1e-3 > 0.0;
+    p.out = c->d_fpair;
+    p.out_global = 0;
+    p.accumulate = 0;
+    launch_fused(c->stream, a, p, c->fused, c->fused_grid);
+}
+
 // one substep of the fused schedule at the current step index c->step
 // (= device counter + c->pending once the launches before it have run)
 // (e0, e1: optional events recorded around the integrator kernel alone)
@@ -1128,6 +1189,16 @@ static void enqueue_substep(bounce_ctx *c, int close, int open, hipEvent_t e0 = 
         enqueue_build(c, c->pending);
         c->built_step = c->step;
         c->host_rebuilds++;
+    }
+    if (use_fused(c)) {
+        if (e0) (void)hipEventRecord(e0, c->stream);
+        launch_fused_step(c, step_args(c, close, open, c->pending), c->pending);
+        if (e1) (void)hipEventRecord(e1, c->stream);
+        if (open) {
+            c->step++;
+            c->pending++;
+        }
+        return;
     }
     enqueue_force(c, c->pending);
     enqueue_extra(c, c->step, c->pending);
@@ -1170,6 +1241,10 @@ static bounce_status make_graph(bounce_ctx *c)
     }
     for (int k = 0; k < c->p.rebuild_interval; ++k) {
         if (k == 0) enqueue_build(c, 0);
+        if (use_fused(c)) {
+            launch_fused_step(c, step_args(c, 1, 1, k), k);
+            continue;
+        }
         enqueue_force(c, k);
         // the graph starts at a multiple of K, and K is a multiple of respa_m
         StepArgs a = step_args(c, 1, 1, k);
@@ -1570,7 +1645,8 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
 {
     bounce_status s = ready(c);
     if (s) return s;
-    if (!avg_ms || reps < 1 || which < 0 || which > 4) return BOUNCE_E_ARG;
+    if (!avg_ms || reps < 1 || which < 0 || which > 6) return BOUNCE_E_ARG;
+    if (which == 6 && !c->p.persistent) return fail(c, BOUNCE_E_ARG, "the fused launch needs persistent = 1");
     if (which == 4 && !c->pme) return fail(c, BOUNCE_E_ARG, "no PME mesh (pme_grid)");
     if (c->built_step < 0) {
         enqueue_build(c, 0);
@@ -1607,7 +1683,12 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
         else if (which == 4)     // into the RESPA buffer, which every outer kick recomputes first
             launch_pme(c->stream, c->n, c->main, c->pos, c->d_charge, c->tp, pme_args(c, 0, -1), c->pme_atoms,
                        c->d_grid, c->d_theta, c->d_grec, 0, 0, nullptr);
-        else launch_step(c->stream, step_args(c, 0, 0, 0));   // no kicks, jumps or drifts
+        else if (which == 5) {     // a dry step: the pair kernel and the integrator, no kicks, jumps or drifts
+            launch_step_pair(c, 0, c->d_fpair);
+            launch_step(c->stream, step_args(c, 0, 0, 0));
+        } else if (which == 6) {   // the same dry step as one fused launch
+            launch_fused_step(c, step_args(c, 0, 0, 0), 0);
+        } else launch_step(c->stream, step_args(c, 0, 0, 0));   // no kicks, jumps or drifts
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
@@ -1617,6 +1698,105 @@ bounce_status bounce_profile_kernel(bounce_ctx *c, int32_t which, int32_t reps, 
     (void)hipEventDestroy(e1);
     *avg_ms = (double)ms / reps;
     return bounce_sync(c);
+}
+
+// the autotuner's cache key: the device (name, architecture, compute units)
+// and every setting the timed kernels depend on
+static std::string tuning_key(const bounce_ctx *c)
+{
+    int dev = 0;
+    hipDeviceProp_t pr{};
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&pr, dev);
+    char buf[768];
+    std::snprintf(buf, sizeof buf,
+                  "%s/%s/%d cu|n=%d R=%d nt=%d int=%d prec=%d coul=%d per=%d rate=%d split=%d "
+                  "r_on=%.4g r_off=%.4g lj=%.4g/%.4g rc=%.4g skin=%.4g cell=%.4g K=%d",
+                  pr.name, pr.gcnArchName, pr.multiProcessorCount, c->n, c->R, c->nt, c->p.integrator,
+                  c->p.pair_precision, c->p.coulomb, c->p.periodic, c->p.rate_mode, c->p.jump_split,
+                  c->p.r_on, c->p.r_off, c->p.r_on_lj, c->p.r_off_lj, c->p.r_cut, c->p.skin,
+                  c->p.cell_size, c->p.rebuild_interval);
+    std::string k(buf);
+    for (char &ch : k)
+        if (ch == '"' || ch == '\\' || ch == '\n') ch = '_';
+    return k;
+}
+
+// one cache line: {"key": "...", "pair_lanes": L, "persistent": P, ...}
+static bool cache_lookup(const char *path, const std::string &key, int32_t &lanes, int32_t &pers)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string tag = "{\"key\": \"" + key + "\",";
+    char line[2048];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, tag.c_str(), tag.size()) != 0) continue;
+        const char *pl = std::strstr(line, "\"pair_lanes\": "), *pp = std::strstr(line, "\"persistent\": ");
+        int l = 0, p = 0;
+        if (pl && pp && std::sscanf(pl + 14, "%d", &l) == 1 && std::sscanf(pp + 14, "%d", &p) == 1 &&
+            (l == 4 || l == 8 || l == 16 || l == 32) && (p == 0 || p == 1)) {
+            lanes = l;
+            pers = p;
+            found = true;      // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+bounce_status bounce_autotune_cached(bounce_ctx *c, int32_t reps, const char *cache_path, bounce_tuning *out)
+{
+    bounce_status s = ready(c);
+    if (s) return s;
+    if (reps < 1 || !out) return BOUNCE_E_ARG;
+    std::memset(out, 0, sizeof *out);
+    for (double &v : out->pair_ms) v = -1.0;
+    for (double &v : out->step_ms) v = -1.0;
+    const std::string key = tuning_key(c);
+    int32_t lanes = 0, pers = 0;
+    if (cache_path && cache_lookup(cache_path, key, lanes, pers)) {
+        out->from_cache = 1;
+    } else {
+        s = bounce_autotune(c, reps, &lanes, out->pair_ms);
+        if (s) return s;
+        pers = 0;
+        const int32_t saved = c->p.persistent;
+        c->p.persistent = 1;
+        const bool can = use_fused(c);
+        double sep = 0.0, fus = 0.0;
+        if (can) {
+            c->p.persistent = 0;
+            s = bounce_profile_kernel(c, 5, 2, &sep);
+            if (!s) s = bounce_profile_kernel(c, 5, reps, &sep);
+            c->p.persistent = 1;
+            if (!s) s = bounce_profile_kernel(c, 6, 2, &fus);
+            if (!s) s = bounce_profile_kernel(c, 6, reps, &fus);
+            if (!s) {
+                out->step_ms[0] = sep;
+                out->step_ms[1] = fus;
+                pers = fus < sep ? 1 : 0;
+            }
+        }
+        c->p.persistent = saved;
+        if (s) return s;
+        if (cache_path) {
+            FILE *f = std::fopen(cache_path, "a");
+            if (!f) return fail(c, BOUNCE_E_ARG, std::string("cannot write the tuning cache ") + cache_path);
+            std::fprintf(f, "{\"key\": \"%s\", \"pair_lanes\": %d, \"persistent\": %d, "
+                            "\"pair_ms\": [%.6g, %.6g, %.6g, %.6g], \"step_ms\": [%.6g, %.6g]}\n",
+                         key.c_str(), lanes, pers, out->pair_ms[0], out->pair_ms[1], out->pair_ms[2],
+                         out->pair_ms[3], out->step_ms[0], out->step_ms[1]);
+            std::fclose(f);
+        }
+    }
+    c->p.pair_lanes = lanes;
+    c->p.persistent = pers;
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    out->pair_lanes = lanes;
+    out->persistent = pers;
+    return BOUNCE_OK;
 }
 
 bounce_status bounce_autotune(bounce_ctx *c, int32_t reps, int32_t *lanes_out, double *ms_out)

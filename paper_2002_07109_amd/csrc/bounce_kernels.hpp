@@ -89,6 +89,20 @@ struct PmeAtoms {
     double *w;                    // [3 n][N]: weight k of atom s at w[k N + s]
 };
 
+// the items of a fused step launch (one launch per step for all replicas)
+constexpr int PAIR_G = 8;                       // lanes per atom of its pair-force items
+constexpr int PAIR_ATOMS = 256 / PAIR_G;        // atoms per pair-force item
+constexpr int STEP_ATOMS = 64;                  // atoms per integrator item (4 lanes each)
+struct FusedArgs {
+    const int4 *items;            // [n_items]: (replica, first sorted atom, end, kind 0 pair / 1 step),
+                                  //   every pair item ahead of every integrator item
+    const int32_t *need;          // [n_reps] pair items of each replica
+    uint32_t *queue;              // [1 + n_reps]: next item, then finished pair items per
+                                  //   replica (zero between launches)
+    int32_t n_items;
+    int32_t n_reps;
+};
+
 struct JumpArgs {
     StepArgs s;
     int64_t step;
@@ -106,6 +120,8 @@ void launch_atom_energy(hipStream_t sm, int32_t n, const double *pos, const doub
 void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, const double *vals,
                         int32_t width, int32_t stride, int32_t col0, double *out);
 void launch_step(hipStream_t sm, const StepArgs &a);
+void launch_fused(hipStream_t sm, const StepArgs &a, const PairArgs &p, const FusedArgs &f, int32_t grid);
+int32_t fused_resident_groups(int fp64, int bounce);
 // device step counter += count (one thread; orders after the preceding launches)
 void launch_advance(hipStream_t sm, DevState *st, int32_t count);
 // st->far_flag = 0 (after a build of the main list)

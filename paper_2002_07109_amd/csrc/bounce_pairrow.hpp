@@ -179,4 +179,67 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// The pair force of the sorted atoms s = t / G < s_end (G lanes each, lane
+// t % G), MODE_SHORT / MODE_FULL / MODE_LONG, into a.out (sorted or caller
+// order, stored or added).  tab: the n_types x n_types pair constants.
+// FIXED: FP32 arithmetic over the fixed-point mirror.
+template <typename R, int MODE, int G, bool ONE, bool FIXED>
+__device__ __forceinline__ void pair_force_atoms(const PairArgs &a, const TypePair<R> *tab, int32_t t,
+                                                 int32_t s_end)
+{
+    const int32_t s = t / G, lig = t % G;
+    const bool valid = s < s_end;
+    const int nt = a.pg.n_types;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    int32_t gi = 0;
+    if (valid) {
+        const int32_t par = a.mirror_sel >= 0 ? a.mirror_sel : (int32_t)((a.st->step + a.step_off) & 1);
+        const double4 *__restrict__ X = a.ls.x[par];
+        const int2 si = a.ls.sinfo[s];
+        gi = si.x;
+        const int32_t *row = a.ls.flist + (int64_t)s * a.ls.fcap;
+        const int32_t cap = a.ls.fcap;
+        const int2 fc = a.ls.fcnt[s];   // the list build keeps fc.x + fc.y <= cap
+        // a far partner was at least lim + s/2 away at the build; while every
+        // atom has moved less than (s/2)/2 since (the flag clear), none is within lim
+        const bool near_only = a.far_gate && a.st->far_flag == 0u;
+        const int32_t nn = fc.x, cnt = near_only ? fc.x : fc.x + fc.y;
+        if constexpr (FIXED) {
+            const RepInfo &rp = ONE ? a.reps[0] : a.reps[si.y];
+            const float fu[3] = {rp.funit[0], rp.funit[1], rp.funit[2]};
+            const int4 *__restrict__ XF = a.ls.xf[par];
+            const int4 xfi = XF[s];
+            const TypePair<float> *tf = reinterpret_cast<const TypePair<float> *>(tab) + xfi.w * nt;
+            // the separate-mechanism flag is uniform: one branch outside the loop
+            if (MODE != MODE_FULL && a.pg.split)
+                pair_force_row_fixed<MODE, G, true>(XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
+            else
+                pair_force_row_fixed<MODE, G, false>(XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
+        } else {
+            const double4 xi = X[s];
+            const TypePair<R> *ti = tab + mirror_type(xi.w) * nt;
+            const BoxReg box(ONE ? a.reps[0] : load_rep(a.reps, a.single_rep, si.y));
+            if (MODE != MODE_FULL && a.pg.split)
+                pair_force_row<R, MODE, G, true>(X, xi, box, row, nn, cnt, cap, lig, s, ti, a.pg, ax, ay, az);
+            else
+                pair_force_row<R, MODE, G, false>(X, xi, box, row, nn, cnt, cap, lig, s, ti, a.pg, ax, ay, az);
+        }
+    }
+    ax = group_sum<G>(ax);
+    ay = group_sum<G>(ay);
+    az = group_sum<G>(az);
+    if (valid && lig == 0) {
+        const int64_t o = 3 * (int64_t)(a.out_global ? gi : s);
+        if (a.accumulate) {
+            a.out[o + 0] += ax;
+            a.out[o + 1] += ay;
+            a.out[o + 2] += az;
+        } else {
+            a.out[o + 0] = ax;
+            a.out[o + 1] = ay;
+            a.out[o + 2] = az;
+        }
+    }
+}
+
 }  // namespace bnc

@@ -101,6 +101,10 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
     __syncthreads();
 
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
+        pair_force_atoms<R, MODE, G, ONE, FIXED>(a, tab, t, a.n);
+        return;
+    }
     const int32_t s = t / G, lig = t % G;
     const bool valid = s < a.n;
     const int nt = a.pg.n_types;
@@ -132,22 +136,7 @@ __global__ void __launch_bounds__(256) k_pair(PairArgs a)
         const bool near_only = a.far_gate && a.st->far_flag == 0u;
         const int32_t nn = fc.x, cnt = near_only ? fc.x : fc.x + fc.y;
         const int32_t tail = cap - 1 + nn;
-        if constexpr (FIXED) {
-            const RepInfo &rp = ONE ? a.reps[0] : a.reps[si.y];
-            const float fu[3] = {rp.funit[0], rp.funit[1], rp.funit[2]};
-            const int4 *__restrict__ XF = a.ls.xf[par];
-            const TypePair<float> *tf = reinterpret_cast<const TypePair<float> *>(tab) + ti * nt;
-            // the separate-mechanism flag is uniform: one branch outside the loop
-            if (MODE != MODE_FULL && a.pg.split)
-                pair_force_row_fixed<MODE, G, true>(XF, XF[s], fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
-            else
-                pair_force_row_fixed<MODE, G, false>(XF, XF[s], fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
-        } else if (MODE == MODE_SHORT || MODE == MODE_FULL || MODE == MODE_LONG) {
-            if (MODE != MODE_FULL && a.pg.split)
-                pair_force_row<R, MODE, G, true>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
-            else
-                pair_force_row<R, MODE, G, false>(X, xi, box, row, nn, cnt, cap, lig, s, tab + ti * nt, a.pg, ax, ay, az);
-        } else {
+        {
         // energies and parameter-gradient bases: U entries per lane in flight
         constexpr int U = 4;
         for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {

@@ -11,6 +11,7 @@
 // partner from C_i, an accept test U < lambda/lambda*, and a reflection.
 #include "bounce_kernels.hpp"
 #include "bounce_bonded.hpp"
+#include "bounce_pairrow.hpp"
 
 namespace bnc {
 
@@ -357,7 +358,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
     return x;
 }
 
-__device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t)
+__device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const JumpTally &t, int32_t slot)
 {
     if (!__any(active && (t.prop | t.acc | t.bound))) return;     // nothing to add (uniform)
     if (a.single_rep) {
@@ -366,8 +367,7 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
         const unsigned long long p = wave_sum(active ? t.prop : 0), c = wave_sum(active ? t.acc : 0),
                                  b = wave_sum(active ? t.bound : 0);
         if ((threadIdx.x & 63) == 0 && (p | c | b)) {
-            unsigned long long *wc =
-                a.wave_cnt + 3 * ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+            unsigned long long *wc = a.wave_cnt + 3 * (int64_t)slot;
             wc[0] += p;
             wc[1] += c;
             wc[2] += b;
@@ -375,7 +375,7 @@ __device__ void flush_tally(const StepArgs &a, int32_t rep, bool active, const J
         return;
     }
     // this wavefront's copy of the counters
-    const int32_t copy = (int32_t)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (CNT_SPREAD - 1));
+    const int32_t copy = slot & (CNT_SPREAD - 1);
     const int32_t first = __shfl(rep, 0, 64);
     const bool uniform = __all(!active || rep == first);
     if (uniform) {
@@ -420,14 +420,15 @@ __device__ __forceinline__ void outer_kick(const StepArgs &a, int32_t s, int32_t
     for (int c = 0; c < 3; ++c) v[c] = v[c] - H * (a.grec[3 * (int64_t)s + c] * k);
 }
 
-template <typename R, bool BOUNCE, int KC = 1>
-__global__ void __launch_bounds__(256) k_step(StepArgs a)
+// The integrator for the sorted atoms s = t / LPA < s_end (lane t % LPA);
+// slot: this wavefront's slot of the jump counters.
+template <typename R, bool BOUNCE, int KC>
+__device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t s_end, int32_t slot)
 {
     // the jump field's pair constants are read where a proposal needs them
     // (cached global loads): a copy into LDS would put a load and a barrier
     // ahead of every wavefront's work
     const TypePair<R> *__restrict__ ftab = jump_table<R>(a);
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = a.st->step + a.step_off;
     const int32_t par = (int32_t)(n & 1);
     const double4 *__restrict__ X = a.ls.x[par];
@@ -435,7 +436,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     double F[3] = {0.0, 0.0, 0.0};
 
     const int32_t s = t / LPA, sub = t % LPA;
-    const bool active = s < a.n;
+    const bool active = s < s_end;
     JumpTally tally = {0, 0, 0};
     int32_t rep = 0, g = 0, lid = 0;
     double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -601,7 +602,63 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a)
     // was clear (a stale read adds atomics, it never misses one)
     const bool beyond = __ballot(disp2 >= a.far_gate2) != 0ull;
     if (!far_seen && beyond && (threadIdx.x & 63) == 0) atomicOr(&a.st->far_flag, 1u);
-    if (BOUNCE) flush_tally(a, rep, active && sub == 0, tally);
+    if (BOUNCE) flush_tally(a, rep, active && sub == 0, tally, slot);
+}
+
+template <typename R, bool BOUNCE, int KC = 1>
+__global__ void __launch_bounds__(256) k_step(StepArgs a)
+{
+    step_atoms<R, BOUNCE, KC>(a, blockIdx.x * blockDim.x + threadIdx.x, a.n,
+                              blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
+// One launch per step: the F_0 pair force and the integrator of every replica.
+// Workgroups take items from a queue: first every replica's pair-force items
+// (PAIR_ATOMS atoms each), then the integrator items (64 atoms each).  An
+// integrator item of replica r waits until the counter of r's finished pair
+// items reaches r's item count; those items were all taken earlier, by
+// running workgroups that wait on nothing, so the wait ends.  The workgroup
+// that finds the queue empty last (all items are then done) clears the
+// counters for the next launch.
+template <typename R, bool BOUNCE, int KC, bool FIXED>
+__global__ void __launch_bounds__(256) k_fused(StepArgs a, PairArgs p, FusedArgs f)
+{
+    constexpr int MODE = BOUNCE ? MODE_SHORT : MODE_FULL;
+    __shared__ TypePair<R> tab[MAXT * MAXT];
+    __shared__ int32_t s_item;
+    const TypePair<R> *pre = jump_table<R>(a);     // the same precomputed constants
+    for (int k = threadIdx.x; k < p.pg.n_types * p.pg.n_types; k += blockDim.x) tab[k] = pre[k];
+    const int32_t slot = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&f.queue[0], 1u);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();
+        if (it >= f.n_items) {
+            if (threadIdx.x == 0 && it == f.n_items + (int32_t)gridDim.x - 1) {
+                for (int32_t r = 0; r <= f.n_reps; ++r) f.queue[r] = 0u;
+            }
+            return;
+        }
+        const int4 e = f.items[it];     // (replica, first sorted atom, end, kind)
+        if (e.w == 0) {
+            pair_force_atoms<R, MODE, PAIR_G, false, FIXED>(p, tab, e.y * PAIR_G + (int32_t)threadIdx.x, e.z);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                atomicAdd(&f.queue[1 + e.x], 1u);
+            }
+        } else {
+            if (threadIdx.x == 0) {
+                const uint32_t need = (uint32_t)f.need[e.x];
+                while (__hip_atomic_load(&f.queue[1 + e.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need)
+                    __builtin_amdgcn_s_sleep(2);
+            }
+            __syncthreads();
+            __threadfence();
+            step_atoms<R, BOUNCE, KC>(a, e.y * LPA + (int32_t)threadIdx.x, e.z, slot);
+        }
+    }
 }
 
 // the device step counter moves once per batch of launched steps, in a kernel
@@ -641,6 +698,51 @@ void launch_step(hipStream_t sm, const StepArgs &a)
     } else {
         hipLaunchKernelGGL((k_step<float, false>), grid, block, 0, sm, a);
     }
+}
+
+void launch_fused(hipStream_t sm, const StepArgs &a, const PairArgs &p, const FusedArgs &f, int32_t grid)
+{
+    if (a.n <= 0 || f.n_items <= 0) return;
+    const dim3 g(grid), block(256);
+    const bool fx = p.ls.xf[0] != nullptr;
+    if (a.bounce) {
+        const int nw = a.ls.ncls * (a.pg.split ? 2 : 1);
+        const int kc = nw <= 1 ? 1 : (nw <= 2 ? 2 : (nw <= 4 ? 4 : 8));
+        switch (kc * 2 + a.pair_fp64) {
+            case 2: if (fx) hipLaunchKernelGGL((k_fused<float, true, 1, true>), g, block, 0, sm, a, p, f);
+                    else hipLaunchKernelGGL((k_fused<float, true, 1, false>), g, block, 0, sm, a, p, f); break;
+            case 3: hipLaunchKernelGGL((k_fused<double, true, 1, false>), g, block, 0, sm, a, p, f); break;
+            case 4: if (fx) hipLaunchKernelGGL((k_fused<float, true, 2, true>), g, block, 0, sm, a, p, f);
+                    else hipLaunchKernelGGL((k_fused<float, true, 2, false>), g, block, 0, sm, a, p, f); break;
+            case 5: hipLaunchKernelGGL((k_fused<double, true, 2, false>), g, block, 0, sm, a, p, f); break;
+            case 8: if (fx) hipLaunchKernelGGL((k_fused<float, true, 4, true>), g, block, 0, sm, a, p, f);
+                    else hipLaunchKernelGGL((k_fused<float, true, 4, false>), g, block, 0, sm, a, p, f); break;
+            case 9: hipLaunchKernelGGL((k_fused<double, true, 4, false>), g, block, 0, sm, a, p, f); break;
+            case 16: if (fx) hipLaunchKernelGGL((k_fused<float, true, 8, true>), g, block, 0, sm, a, p, f);
+                     else hipLaunchKernelGGL((k_fused<float, true, 8, false>), g, block, 0, sm, a, p, f); break;
+            default: hipLaunchKernelGGL((k_fused<double, true, 8, false>), g, block, 0, sm, a, p, f); break;
+        }
+    } else if (a.pair_fp64) {
+        hipLaunchKernelGGL((k_fused<double, false, 1, false>), g, block, 0, sm, a, p, f);
+    } else if (fx) {
+        hipLaunchKernelGGL((k_fused<float, false, 1, true>), g, block, 0, sm, a, p, f);
+    } else {
+        hipLaunchKernelGGL((k_fused<float, false, 1, false>), g, block, 0, sm, a, p, f);
+    }
+}
+
+// workgroups of one fused launch that can be resident at once (their upper bound)
+int32_t fused_resident_groups(int fp64, int bounce)
+{
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = bounce ? (fp64 ? (const void *)k_fused<double, true, 1, false>
+                                    : (const void *)k_fused<float, true, 1, true>)
+                            : (fp64 ? (const void *)k_fused<double, false, 1, false>
+                                    : (const void *)k_fused<float, false, 1, true>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
+    return std::max(1, cus) * per;
 }
 
 // J half-step alone at the current positions (diagnostics and parity tests)
@@ -691,7 +793,7 @@ __global__ void __launch_bounds__(256) k_jump(JumpArgs ja)
         a.vel[3 * (int64_t)g + 1] = v[1];
         a.vel[3 * (int64_t)g + 2] = v[2];
     }
-    flush_tally(a, rep, active && sub == 0, tally);
+    flush_tally(a, rep, active && sub == 0, tally, blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 void launch_jump(hipStream_t sm, const JumpArgs &a)
