@@ -125,7 +125,8 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
     sim.set_state(pos=state[0], vel=state[1], step=0)
     sim.step(args.warmup)
     sim.sync()
-    lanes, tune = sim.autotune(reps=20)
+    tuned = sim.tune(reps=20)      # lanes per atom and the launch structure
+    lanes, tune = tuned["pair_lanes"], tuned["pair_ms"]
     # the autotuner drops the K-step graph: run to the next list interval and
     # replay one whole interval, so that the graph is captured and instantiated
     # before the timed region, which then starts at a list rebuild
@@ -157,6 +158,8 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
                accepted_per_step=(c1["accepted"] - c0["accepted"]) / args.steps,
                pair_kernel_ms=pair_ms, build_ms=build_ms, step_kernel_ms=step_ms, t_kin=e["tkin"],
                lanes=lanes, tune_ms={k: round(v, 5) for k, v in tune.items()},
+               launch="fused" if tuned["persistent"] else "two launches",
+               dry_step_ms={k: round(v, 5) for k, v in tuned["step_ms"].items()},
                e_pot=e["pair"] + e["bond"] + e["angle"], mesh_ms=mesh_ms,
                pos=sim.pos.cpu().numpy(), list_slots=sim.list_size(B.LIST_FORCE), energy_ms=energy_ms)
     sim.close()
@@ -211,7 +214,8 @@ def run_batch(args, ff):
         sim.set_state(pos=pos, vel=vel, step=0)
         sim.step(50)
         sim.sync()
-        lanes, tune = sim.autotune(reps=10)
+        tuned = sim.tune(reps=10)
+        lanes = tuned["pair_lanes"]
         sim.step(10)
         sim.sync()
         c0 = [sim.counters(r) for r in range(len(systems))]
@@ -239,7 +243,9 @@ def run_batch(args, ff):
                           "accepted_per_step": diff("accepted"), "pair_lanes": lanes,
                           "pair_kernel_us": round(pair_ms * 1e3, 3), "short_pairs": pairs,
                           "pair_kernel_tflops": round(tflops, 4),
-                          "pair_kernel_frac": round(tflops / PEAK_FP32, 5)}
+                          "pair_kernel_frac": round(tflops / PEAK_FP32, 5),
+                          "launch": "fused" if tuned["persistent"] else "two launches",
+                          "dry_step_ms": {k: round(v, 5) for k, v in tuned["step_ms"].items()}}
         log(f"batch {mode_name}: {out[mode_name]}")
     return out
 
@@ -717,6 +723,7 @@ def main():
                    "pair_kernel_us": round(bo["pair_kernel_ms"] * 1e3, 3),
                    "list_build_us": round(bo["build_ms"] * 1e3, 3),
                    "pair_lanes": bo["lanes"], "autotune_ms": bo["tune_ms"],
+                   "launch": bo["launch"], "tuner_dry_step_ms": bo["dry_step_ms"],
                    "rate_bounds": args.rate_mode,
                    "t_kin_K": round(bo["t_kin"], 2), "e_pot": round(bo["e_pot"], 2)},
         "bounce_%s_bounds" % other: {
@@ -736,6 +743,7 @@ def main():
                   "pair_kernel_tflops": round(achieved_ba, 3),
                   "list_build_us": round(ba["build_ms"] * 1e3, 3),
                   "pair_lanes": ba["lanes"], "autotune_ms": ba["tune_ms"],
+                  "launch": ba["launch"], "tuner_dry_step_ms": ba["dry_step_ms"],
                   "t_kin_K": round(ba["t_kin"], 2), "e_pot": round(ba["e_pot"], 2)},
         "speedup_vs_baoab": round(ba["ms_per_step"] / bo["ms_per_step"], 4),
         "bounce_respa_nonbonded": {k: dict(v, speedup_vs_baoab=round(v["ns_per_day"] / ns_day(ba["ms_per_step"]), 4))
