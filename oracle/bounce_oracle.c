@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 counter-based generator, from its published definition      */
@@ -726,8 +727,28 @@ typedef struct {
     double *q_build;
 } run_lists;
 
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+static int build_run_lists_raw(const orc_params *p, const orc_topology *t, const double *q,
+                               run_lists *L);
+
+/* the lists, with the wall time they take added to the counters */
 static int build_run_lists(const orc_params *p, const orc_topology *t, const double *q,
-                           run_lists *L)
+                           run_lists *L, orc_counters *cnt)
+{
+    const double t0 = wall_seconds();
+    const int s = build_run_lists_raw(p, t, q, L);
+    cnt->list_seconds += wall_seconds() - t0;
+    return s;
+}
+
+static int build_run_lists_raw(const orc_params *p, const orc_topology *t, const double *q,
+                               run_lists *L)
 {
     int32_t n = t->n_atoms;
     int s = orc_sort_order(p, n, q, L->order, L->cell);
@@ -1076,7 +1097,7 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
         }                                                                                        \
     } while (0)
 
-    status = build_run_lists(p, t, q, &L);
+    status = build_run_lists(p, t, q, &L, cnt);
     if (status != ORC_OK) goto done;
     cnt->rebuilds++;
     forces(p, t, q, &L, g, grec, cnt, pme, respa, out_pair, erec);
@@ -1094,7 +1115,7 @@ int orc_run(const orc_params *p, const orc_topology *t, double *q, double *v, in
             if (norm2(d) >= 0.25 * p->skin * p->skin) { status = ORC_E_SKIN; goto done; }
         }
         if ((n_step + 1) % p->rebuild_interval == 0) {
-            int s = build_run_lists(p, t, q, &L);
+            int s = build_run_lists(p, t, q, &L, cnt);
             if (s != ORC_OK) { status = s; goto done; }
             cnt->rebuilds++;
         }

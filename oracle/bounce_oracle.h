@@ -111,6 +111,7 @@ typedef struct {
 
 typedef struct {
     int64_t proposals, accepted, bound_violations, rebuilds, pair_evals, steps;
+    double list_seconds;       /* wall time spent building lists (timing only) */
 } orc_counters;
 
 /* one jump proposal; margin = U |v_i| L - v_i.F (accepted iff margin < 0) and

@@ -68,10 +68,11 @@ class Topo(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("proposals", C.c_int64), ("accepted", C.c_int64),
                 ("bound_violations", C.c_int64), ("rebuilds", C.c_int64),
-                ("pair_evals", C.c_int64), ("steps", C.c_int64)]
+                ("pair_evals", C.c_int64), ("steps", C.c_int64), ("list_seconds", C.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        """The event and step counts (the list-build wall time is returned apart)."""
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "list_seconds"}
 
 
 EVENT_DTYPE = np.dtype([("step", np.int64), ("phase", np.int32), ("atom", np.int32),
@@ -351,7 +352,7 @@ def run(p, topo, q, v, step0, nsteps, ev_cap=0):
     st = lib().orc_run(C.byref(p), C.byref(topo.c), _ptr(q), _ptr(v), int(step0), int(nsteps),
                        _ptr(ev) if ev_cap else None, ev_cap, C.byref(nev), C.byref(cnt))
     return dict(q=q, v=v, status=st, status_name=STATUS.get(st, str(st)),
-                counters=cnt.as_dict(), n_events=nev.value,
+                counters=cnt.as_dict(), list_seconds=float(cnt.list_seconds), n_events=nev.value,
                 events=ev[:min(nev.value, ev_cap)] if ev_cap else None)
 
 
