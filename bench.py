@@ -120,7 +120,8 @@ def run_gpu(args, system, ff, integrator, state, rate_mode=0, dt=1.0, rebuild=No
                       periodic=1, dt=dt, gamma=1e-3, temperature=300.0, r_on=args.r_on,
                       r_off=args.r_off, r_cut=9.0, skin=args.skin, ewald_alpha=args.alpha,
                       rebuild_interval=rebuild or args.rebuild, seed=0, cell_size=system.cell_size,
-                      use_graph=0 if args.no_graph else 1, rate_mode=rate_mode, **mesh)
+                      use_graph=0 if args.no_graph else 1, rate_mode=rate_mode,
+                      pair_kernel=args.pair_kernel, **mesh)
     sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
     sim.set_state(pos=state[0], vel=state[1], step=0)
     sim.step(args.warmup)
@@ -596,6 +597,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--cpu-steps-single", type=int, default=2,
                     help="steps of the one-thread oracle legs")
+    ap.add_argument("--pair-kernel", type=int, choices=(0, 4, 8), default=0,
+                    help="F_0 pair force: 0 per-atom rows, 4 or 8 cluster-pair tiles")
     ap.add_argument("--skip-box", action="store_true",
                     help="run only the --batch / --big / --mesh legs (no headline line)")
     ap.add_argument("--cpu-leg", choices=("bounce", "baoab"), default=None,
@@ -696,7 +699,8 @@ def main():
     # the dominant kernel of a step is the F_0 pair kernel
     achieved = short_pairs * FLOPS_SHORT / (bo["pair_kernel_ms"] * 1e-3) / 1e12
     achieved_ba = full_pairs_ba * FLOPS_FULL / (ba["pair_kernel_ms"] * 1e-3) / 1e12
-    traffic = measured_traffic(bo["lanes"])
+    # the committed counter record is the row kernel's
+    traffic = measured_traffic(bo["lanes"]) if not args.pair_kernel else None
     # unpacked FP32 with the transcendentals at a quarter rate
     peak_opmix = (PEAK_FP32 / 2) * FLOPS_SHORT / ((FLOPS_SHORT - TRANSC_PER_PAIR) + 4 * TRANSC_PER_PAIR)
     line = {
@@ -716,7 +720,8 @@ def main():
                                "(alpha %g/A) + LJ, rc 9 A, skin 2 A, BOUNCE r'/r'' = %g/%g A, "
                                "dt 1 fs" % (args.alpha, args.r_on, args.r_off),
                    "n_atoms": system.n_atoms, "rebuild_interval": args.rebuild,
-                   "skin": args.skin, "hip_graph": not args.no_graph},
+                   "skin": args.skin, "hip_graph": not args.no_graph,
+                   "pair_kernel": "rows" if not args.pair_kernel else "clusters of %d" % args.pair_kernel},
         "bounce": {"ns_per_day": round(ns_day(bo["ms_per_step"]), 3),
                    "ms_per_step": round(bo["ms_per_step"], 5),
                    "pair_evals_per_s": (short_pairs + bo["proposals_per_step"]) * steps_s_bo,

@@ -128,7 +128,13 @@ typedef struct {
        an integrator launch per step.  Both give bit-identical results.  Applies
        when the short-range pair force is in F_0 and no mesh force is (else 0). */
     int32_t persistent;
-    int32_t pad_p;
+    /* The F_0 pair force's partner search (FP32 pair arithmetic only): 0 = per-atom
+       rows of the force list (G lanes per atom); 4 or 8 = cluster pairs: clusters
+       of 4 or 8 consecutive sorted atoms, each with a list of the clusters whose
+       bounding boxes (at the build) come within the list radius, evaluated as
+       tiles of one pair per lane.  The same pairs contribute; the sums differ by
+       rounding order only. */
+    int32_t pair_kernel;
 } bounce_params;
 
 typedef struct {

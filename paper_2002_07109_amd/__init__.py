@@ -40,13 +40,15 @@ def make_params(**kw) -> bounce_params:
     moves to the outer step too; jump_split = 1 gives the Coulomb and the
     Lennard-Jones long-range parts separate jump mechanisms (the LJ window
     r_on_lj, r_off_lj defaults to the Coulomb one); persistent = 1 makes each step one
-    persistent launch over all replicas."""
+    persistent launch over all replicas; pair_kernel = 4 or 8 evaluates F_0's pair
+    force over cluster pairs of that many atoms instead of per-atom rows."""
     d = dict(integrator=BJAOAJB, pair_precision=PAIR_FP32, coulomb=COUL_EWALD, periodic=1,
              rebuild_interval=10, max_proposals=100000, log_events=0, use_graph=0, dt=1.0,
              gamma=1e-3, temperature=300.0, r_on=6.0, r_off=7.0, r_cut=9.0, skin=2.0,
              ewald_alpha=0.35, bound_scale=1.0, cell_size=4.4, seed=0, event_capacity=0,
              pair_lanes=0, rate_mode=RATE_ATOM, pme_grid=(0, 0, 0), pme_order=5, respa_m=0,
-             respa_outer=OUTER_RECIP, jump_split=0, r_on_lj=0.0, r_off_lj=0.0, persistent=0)
+             respa_outer=OUTER_RECIP, jump_split=0, r_on_lj=0.0, r_off_lj=0.0, persistent=0,
+             pair_kernel=0)
     d.update(kw)
     p = bounce_params()
     for k, v in d.items():

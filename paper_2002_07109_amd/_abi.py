@@ -35,7 +35,7 @@ class bounce_params(C.Structure):
                 ("pair_lanes", C.c_int32), ("rate_mode", C.c_int32),
                 ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32), ("respa_m", C.c_int32),
                 ("respa_outer", C.c_int32), ("jump_split", C.c_int32), ("r_on_lj", C.c_double),
-                ("r_off_lj", C.c_double), ("persistent", C.c_int32), ("pad_p", C.c_int32)]
+                ("r_off_lj", C.c_double), ("persistent", C.c_int32), ("pair_kernel", C.c_int32)]
 
 
 class bounce_system(C.Structure):

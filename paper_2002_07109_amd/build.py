@@ -22,6 +22,7 @@ SOURCES = {
     "kernels_pair.hip": [],
     "kernels_step.hip": [],
     "kernels_pme.hip": [],
+    "kernels_cluster.hip": [],
     "bounce_api.cpp": [],
 }
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

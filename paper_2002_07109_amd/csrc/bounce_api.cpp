@@ -161,6 +161,11 @@ struct bounce_ctx {
     std::vector<int32_t> fneed;
     FusedArgs fused{};
     int32_t fused_grid = 0;
+    // cluster pairs (pair_kernel = 4 or 8)
+    std::vector<int4> clu;
+    std::vector<int32_t> cl_first;
+    ClusterSet cs{};
+    int32_t cl_cap = 0;
     // schedule
     int64_t step = 0;             // host view: device counter + pending
     int32_t pending = 0;          // steps opened since the device counter last moved
@@ -228,6 +233,8 @@ bounce_status bounce_create(const bounce_params *p, bounce_ctx **out)
     if (p->respa_outer != BOUNCE_OUTER_RECIP && p->respa_outer != BOUNCE_OUTER_NONBONDED) return BOUNCE_E_ARG;
     if (p->respa_outer == BOUNCE_OUTER_NONBONDED && p->respa_m < 1) return BOUNCE_E_ARG;
     if (p->persistent != 0 && p->persistent != 1) return BOUNCE_E_ARG;
+    if (p->pair_kernel != 0 && p->pair_kernel != 4 && p->pair_kernel != 8) return BOUNCE_E_ARG;
+    if (p->pair_kernel != 0 && p->pair_precision != BOUNCE_PAIR_FP32) return BOUNCE_E_ARG;
     if (p->pair_lanes != 0 && p->pair_lanes != 4 && p->pair_lanes != 8 && p->pair_lanes != 16 &&
         p->pair_lanes != 32)
         return BOUNCE_E_ARG;
@@ -517,6 +524,20 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
                 if (kind == 0) c->fneed[r]++;
             }
         }
+    // clusters of pair_kernel consecutive sorted atoms, per replica
+    c->clu.clear();
+    c->cl_first.assign(R + 1, 0);
+    if (c->p.pair_kernel) {
+        const int32_t CL = c->p.pair_kernel;
+        int64_t max_cl = 1;
+        for (int32_t r = 0; r < R; ++r) {
+            c->cl_first[r] = (int32_t)c->clu.size();
+            for (int64_t b = c->rep_off[r]; b < c->rep_off[r + 1]; b += CL)
+                c->clu.push_back(make_int4((int32_t)b, (int32_t)std::min<int64_t>(b + CL, c->rep_off[r + 1]), r, 0));
+            max_cl = std::max<int64_t>(max_cl, (int64_t)c->clu.size() - c->cl_first[r]);
+        }
+        c->cl_first[R] = (int32_t)c->clu.size();
+    }
     // row capacities: 1.5 x the mean count in the list sphere at the densest replica
     auto cap = [&](double r) {
         double m = 1.5 * max_rho * 4.18879020478639 * r * r * r + 64.0;
@@ -530,6 +551,17 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     c->ccap = bounce ? clampcap(cap(c->p.r_cut + c->p.skin)) : 0;
     c->acap = clampcap(cap(c->p.r_cut + 0.01));
     c->xcap = std::max(c->fcap, std::max(c->ccap, c->acap));
+    if (c->p.pair_kernel) {
+        // clusters whose boxes (up to ~6 A across) come within the list radius:
+        // 1.5 x the mean count in the sphere of radius rl + 6 A, plus 64
+        const double rl = (bounce ? r_short(c->p) : c->p.r_cut) + c->p.skin + 6.0;
+        int64_t per = 1;
+        for (int32_t r = 0; r < R; ++r) per = std::max<int64_t>(per, c->cl_first[r + 1] - c->cl_first[r]);
+        const double m = 1.5 * max_rho * 4.18879020478639 * rl * rl * rl / c->p.pair_kernel + 64.0;
+        c->cl_cap = (int32_t)std::min<int64_t>((int64_t)(std::ceil(m / 32.0) * 32.0), ((per + 31) / 32) * 32);
+    } else {
+        c->cl_cap = 0;
+    }
     // exclusions (both directions) and bonded terms per atom
     std::vector<std::vector<int32_t>> ex(n), bt(n);
     for (int32_t k = 0; k < s->n_excl; ++k) {
@@ -625,7 +657,7 @@ struct Offsets {
     size_t type, rep_of, acc_m, inv_mass, ou_c2, excl_ptr, excl_idx, bt_ptr, bt, bond_ij, bond_kr,
         angle_ijk, angle_kt, reps, unit, Lq, tparams, tab_f, tab_d, wave_cnt, rep_off, one_seg, st, cnt, events, fpair, atom,
         seg, xcnt, xcol, cell_rep, rdf, grid, theta, grec, pme_e, pme_fl, pme_f, pme_w, fitems, fneed,
-        fqueue;
+        fqueue, clu, cl_first, cl_ctr, cl_half, cl_cnt, cl_list;
     size_t ls[2][18];
 };
 
@@ -680,6 +712,13 @@ static void plan(const bounce_ctx *c, Layout &L, Offsets &o)
     o.fitems = L.take(16 * std::max<size_t>(1, c->fitems.size()));
     o.fneed = L.take(4 * R);
     o.fqueue = L.take(4 * (R + 1));
+    const size_t ncl = c->clu.size();
+    o.clu = L.take(16 * std::max<size_t>(1, ncl));
+    o.cl_first = L.take(4 * (R + 1));
+    o.cl_ctr = L.take(16 * std::max<size_t>(1, ncl));
+    o.cl_half = L.take(16 * std::max<size_t>(1, ncl));
+    o.cl_cnt = L.take(4 * std::max<size_t>(1, ncl));
+    o.cl_list = L.take(4 * std::max<size_t>(1, ncl * (size_t)c->cl_cap));
     for (int k = 0; k < 2; ++k) {
         const size_t fcap = k == 0 ? c->fcap : c->acap, ccap = k == 0 ? c->ccap : 0;
         size_t *q = o.ls[k];
@@ -821,6 +860,17 @@ static bounce_status bind_impl(bounce_ctx *c, void *workspace, uint64_t bytes, d
     HIPCHK(c, up(sm, ws, o.fitems, c->fitems));
     HIPCHK(c, up(sm, ws, o.fneed, c->fneed));
     HIPCHK(c, hipMemsetAsync(ws + o.fqueue, 0, 4 * ((size_t)c->R + 1), sm));
+    HIPCHK(c, up(sm, ws, o.clu, c->clu));
+    HIPCHK(c, up(sm, ws, o.cl_first, c->cl_first));
+    c->cs.clu = at<int4>(ws, o.clu);
+    c->cs.rep_first = at<int32_t>(ws, o.cl_first);
+    c->cs.ctr = at<int4>(ws, o.cl_ctr);
+    c->cs.half = at<float4>(ws, o.cl_half);
+    c->cs.cnt = at<int32_t>(ws, o.cl_cnt);
+    c->cs.list = at<int32_t>(ws, o.cl_list);
+    c->cs.ncl = (int32_t)c->clu.size();
+    c->cs.cap = c->cl_cap;
+    c->cs.cl = c->p.pair_kernel;
     c->fused.items = at<int4>(ws, o.fitems);
     c->fused.need = at<int32_t>(ws, o.fneed);
     c->fused.queue = at<uint32_t>(ws, o.fqueue);
@@ -1027,6 +1077,11 @@ static void enqueue_build(bounce_ctx *c, int32_t step_off)
     BuildSpec b = main_spec(c);
     b.step_off = step_off;
     launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, b, c->d_st);
+    if (c->p.pair_kernel) {
+        // the cluster boxes may be apart by up to the force list's radius
+        const double rl = (c->p.integrator == BOUNCE_BJAOAJB ? r_short(c->p) : c->p.r_cut) + c->p.skin;
+        launch_cluster_build(c->stream, c->cs, c->main, c->d_reps, c->d_st, -1, step_off, (float)rl);
+    }
     launch_reset_disp(c->stream, c->d_st);
 }
 
@@ -1059,8 +1114,9 @@ static void launch_step_pair(bounce_ctx *c, int32_t step_off, double *out)
     a.out = out;
     a.out_global = 0;
     a.accumulate = 0;
-    launch_pair(c->stream, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
-                c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
+    const int mode = c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL;
+    if (c->p.pair_kernel) launch_pair_cl(c->stream, mode, a, c->cs);
+    else launch_pair(c->stream, mode, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
 }
 
 static void enqueue_force(bounce_ctx *c, int32_t step_off)
@@ -1165,7 +1221,8 @@ static StepArgs step_args(bounce_ctx *c, int close, int open, int32_t step_off)
 // short-range pair force and no mesh force
 static bool use_fused(const bounce_ctx *c)
 {
-    return c->p.persistent && !c->out_pair && !(c->pme && c->p.respa_m == 0) && !c->outer;
+    return c->p.persistent && !c->p.pair_kernel && !c->out_pair && !(c->pme && c->p.respa_m == 0) &&
+           !c->outer;
 }
 
 static void launch_fused_step(bounce_ctx *c, const StepArgs &a, int32_t step_off)
@@ -1354,8 +1411,9 @@ bounce_status bounce_compute_gradient(bounce_ctx *c, int32_t which, double *grad
         a.out = grad;
         a.out_global = 1;
         a.accumulate = 0;
-        launch_pair(sm, c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL,
-                    c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
+        const int mode = c->p.integrator == BOUNCE_BJAOAJB ? MODE_SHORT : MODE_FULL;
+        if (c->p.pair_kernel) launch_pair_cl(sm, mode, a, c->cs);
+        else launch_pair(sm, mode, c->p.pair_precision == BOUNCE_PAIR_FP64, c->p.pair_lanes, a);
         first = 0;
     }
     if (which & (BOUNCE_G_SHORT | BOUNCE_G_LONG | BOUNCE_G_FULL))

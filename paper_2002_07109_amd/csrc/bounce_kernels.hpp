@@ -89,6 +89,19 @@ struct PmeAtoms {
     double *w;                    // [3 n][N]: weight k of atom s at w[k N + s]
 };
 
+// cluster pairs for the tile form of the F_0 pair force (kernels_cluster.hip)
+struct ClusterSet {
+    const int4 *clu;              // [ncl] (first sorted atom, end, replica, 0)
+    const int32_t *rep_first;     // [n_reps + 1] first cluster of each replica
+    int4 *ctr;                    // [ncl] box centre at the build (fixed point; w = replica)
+    float4 *half;                 // [ncl] box half extents (A)
+    int32_t *cnt;                 // [ncl] listed j-clusters
+    int32_t *list;                // [ncl][cap] j-clusters, ascending
+    int32_t ncl, cap;
+    int32_t cl;                   // atoms per cluster: 4 or 8
+    int32_t pad;
+};
+
 // the items of a fused step launch (one launch per step for all replicas)
 constexpr int PAIR_G = 8;                       // lanes per atom of its pair-force items
 constexpr int PAIR_ATOMS = 256 / PAIR_G;        // atoms per pair-force item
@@ -121,6 +134,9 @@ void launch_segment_sum(hipStream_t sm, int32_t n_seg, const int64_t *seg_off, c
                         int32_t width, int32_t stride, int32_t col0, double *out);
 void launch_step(hipStream_t sm, const StepArgs &a);
 void launch_fused(hipStream_t sm, const StepArgs &a, const PairArgs &p, const FusedArgs &f, int32_t grid);
+void launch_cluster_build(hipStream_t sm, const ClusterSet &cs, const ListSet &ls, const RepInfo *reps,
+                          DevState *st, int32_t mirror_sel, int32_t step_off, float rl);
+void launch_pair_cl(hipStream_t sm, int mode, const PairArgs &a, const ClusterSet &cs);
 int32_t fused_resident_groups(int fp64, int bounce);
 // device step counter += count (one thread; orders after the preceding launches)
 void launch_advance(hipStream_t sm, DevState *st, int32_t count);

@@ -48,7 +48,8 @@ def gpu_sim(systems, cfg, fp64=False, log_events=False, event_capacity=0, use_gr
                       pme_grid=cfg.get("pme_grid") or (0, 0, 0), pme_order=cfg.get("pme_order", 5),
                       respa_m=cfg.get("respa_m", 0), respa_outer=cfg.get("respa_outer", 0),
                       jump_split=cfg.get("jump_split", 0), r_on_lj=cfg.get("r_on_lj") or 0.0,
-                      r_off_lj=cfg.get("r_off_lj") or 0.0, persistent=cfg.get("persistent", 0))
+                      r_off_lj=cfg.get("r_off_lj") or 0.0, persistent=cfg.get("persistent", 0),
+                      pair_kernel=cfg.get("pair_kernel", 0))
     return B.Simulation(systems, p, FF["charge"], FF["eps"], FF["sigma"])
 
 
