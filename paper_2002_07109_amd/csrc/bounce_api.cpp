@@ -1078,8 +1078,9 @@ static void enqueue_build(bounce_ctx *c, int32_t step_off)
     b.step_off = step_off;
     launch_build(c->stream, c->n, c->pos, c->d_reps, c->d_cell_rep, c->tp, c->main, b, c->d_st);
     if (c->p.pair_kernel) {
-        // the cluster boxes may be apart by up to the force list's radius
-        const double rl = (c->p.integrator == BOUNCE_BJAOAJB ? r_short(c->p) : c->p.r_cut) + c->p.skin;
+        // the cluster boxes may be apart by up to the force list's radius (plus
+        // 1e-3 A for the FP32 rounding of the box test)
+        const double rl = (c->p.integrator == BOUNCE_BJAOAJB ? r_short(c->p) : c->p.r_cut) + c->p.skin + 1e-3;
         launch_cluster_build(c->stream, c->cs, c->main, c->d_reps, c->d_st, -1, step_off, (float)rl);
     }
     launch_reset_disp(c->stream, c->d_st);
