@@ -59,15 +59,16 @@ def pair_source_hash():
 def measured_traffic(lanes):
     """HBM bytes per launch of the short-range pair kernel, from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary; None unless that summary was taken
-    on the current kernel source with the same lanes per atom."""
+    on the current kernel source and holds these lanes per atom."""
     try:
         text = open(TRAFFIC_FILE).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("source_hash") != pair_source_hash() or rec.get("lanes") != lanes:
+    if rec.get("source_hash") != pair_source_hash():
         return None
-    return rec["hbm_bytes_per_launch"]
+    entry = rec.get("by_lanes", {}).get(str(lanes))
+    return entry["hbm_bytes_per_launch"] if entry else None
 
 
 def copy_calibration(mib):
@@ -196,7 +197,7 @@ def run_batch(args, ff):
     mk = lambda integ, gamma, seed, mode=0: B.make_params(
         integrator=integ, pair_precision=B.PAIR_FP32, coulomb=B.COUL_BARE, periodic=0,
         dt=args.batch_dt, gamma=gamma, temperature=300.0, r_on=7.0, r_off=8.0, r_cut=9.0,
-        skin=2.0, rebuild_interval=10, seed=seed, cell_size=systems[0].cell_size, use_graph=1,
+        skin=2.0, rebuild_interval=args.batch_rebuild, seed=seed, cell_size=systems[0].cell_size, use_graph=1,
         rate_mode=mode)
     # relax the lattice starts (BAOAB with strong friction, untimed)
     sim = B.Simulation(systems, mk(B.BAOAB, 0.05, 99), ff["charge"], ff["eps"], ff["sigma"])
@@ -208,6 +209,7 @@ def run_batch(args, ff):
     out = {"workload": "64 non-periodic flexible-water droplets, %d-%d atoms (%d in all), bare "
                        "Coulomb + LJ, rc 9 A, BOUNCE r'/r'' = 7/8 A, dt %g fs, FP32 pair arithmetic"
                        % (min(sizes), max(sizes), sum(sizes), args.batch_dt),
+           "rebuild_interval": args.batch_rebuild,
            "steps": args.batch_steps}
     for mode_name, mode in (("atom_bounds", 0), ("pair_bounds", 1)):
         sim = B.Simulation(systems, mk(B.BJAOAJB, 1e-3, 0, mode), ff["charge"], ff["eps"],
@@ -229,7 +231,7 @@ def run_batch(args, ff):
         n = sim.n
         # the short-range pair kernel's roofline over all droplets: pairs within
         # r'' counted per droplet (no periodic images, exclusions removed)
-        pair_ms = pair_ms_over_interval(sim, 10, 4)
+        pair_ms = pair_ms_over_interval(sim, args.batch_rebuild, 4)
         q = sim.pos.cpu().numpy()
         pairs = 0
         for r, s in enumerate(systems):
@@ -617,6 +619,9 @@ def main():
                     help="also time 64 uneven droplets in one context")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-dt", type=float, default=0.25)
+    ap.add_argument("--batch-rebuild", type=int, default=40,
+                    help="list rebuild interval K of the batch (steps; 40 x 0.25 fs = the 10 fs "
+                         "list lifetime of the 1 fs box)")
     ap.add_argument("--big", action="store_true",
                     help="also time the 96,000-atom box with the same model")
     ap.add_argument("--big-steps", type=int, default=500)
