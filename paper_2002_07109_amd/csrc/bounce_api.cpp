@@ -559,6 +559,10 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
         for (int32_t r = 0; r < R; ++r) per = std::max<int64_t>(per, c->cl_first[r + 1] - c->cl_first[r]);
         const double m = 1.5 * max_rho * 4.18879020478639 * rl * rl * rl / c->p.pair_kernel + 64.0;
         c->cl_cap = (int32_t)std::min<int64_t>((int64_t)(std::ceil(m / 32.0) * 32.0), ((per + 31) / 32) * 32);
+        // in a droplet a cluster can run from the end of one column of cells to
+        // the start of the next, across the droplet: such boxes meet every
+        // cluster of the replica, so the capacity is the replica's cluster count
+        if (!c->p.periodic) c->cl_cap = (int32_t)(((per + 31) / 32) * 32);
     } else {
         c->cl_cap = 0;
     }

@@ -92,6 +92,23 @@ def test_fused_launch_is_bit_identical_on_one_box(fp64, integrator):
     assert a[2] == b[2] and a[3] == b[3]
 
 
+@pytest.mark.parametrize("variant", ["pair_bounds", "split"])
+def test_fused_launch_is_bit_identical_with_proposal_classes(batch, variant):
+    """The fused launch's integrator with several proposal classes: per-type-pair
+    bounds (two classes) on the droplets, separate Coulomb and Lennard-Jones
+    mechanisms (four classes) on the box."""
+    if variant == "pair_bounds":
+        systems, cfg = batch[:8], dict(DROPLET, rate_mode=1)
+    else:
+        systems, cfg = relaxed_box("b8"), dict(BOX, jump_split=1, r_on_lj=5.0, r_off_lj=6.0)
+    for fp64 in (False, True):
+        a = _run(systems, dict(cfg, persistent=0), fp64, 23)
+        b = _run(systems, dict(cfg, persistent=1), fp64, 23)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), fp64
+        assert a[2] == b[2] and a[3] == b[3]
+        assert sum(c["proposals"] for c in a[2]) > 0
+
+
 def test_tuner_times_then_reads_its_cache(batch, tmp_path):
     cache = tmp_path / "tuning.jsonl"
     sim = gpu_sim(batch, DROPLET, fp64=False, use_graph=True)
