@@ -86,6 +86,15 @@ def test_argument_errors_need_no_gpu():
     p = make_params(periodic=0, respa_m=2, respa_outer=1)        # outer pair force, no mesh
     assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.OK
     L.bounce_destroy(ctx)
+    # launch structure and partner search: persistent 0/1; cluster tiles of 4 or 8
+    # atoms, FP32 pair arithmetic only
+    for kw in (dict(persistent=2), dict(pair_kernel=6), dict(pair_kernel=4, pair_precision=1)):
+        p = make_params(**kw)
+        assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.E_ARG, kw
+    for kw in (dict(persistent=1), dict(pair_kernel=8), dict(pair_kernel=4, persistent=1)):
+        p = make_params(**kw)
+        assert L.bounce_create(C.byref(p), C.byref(ctx)) == _abi.OK, kw
+        L.bounce_destroy(ctx)
 
 
 def test_missing_library_fails_loudly(tmp_path):
