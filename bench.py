@@ -288,7 +288,7 @@ def accuracy_run(args, system, ff, state, integ, dt, m=0, r_on=None, r_off=None)
                       r_off=args.r_off if r_off is None else r_off, r_cut=9.0, skin=args.skin,
                       ewald_alpha=args.alpha,
                       rebuild_interval=args.rebuild if dt == 1.0 else 4 * args.rebuild,
-                      seed=7, cell_size=system.cell_size, use_graph=1, respa_m=m,
+                      seed=args.accuracy_seed, cell_size=system.cell_size, use_graph=1, respa_m=m,
                       respa_outer=B.OUTER_NONBONDED if m else B.OUTER_RECIP)
     sim = B.Simulation(system, p, ff["charge"], ff["eps"], ff["sigma"])
     sim.set_state(pos=state[0], vel=state[1], step=0)
@@ -641,6 +641,8 @@ def main():
     ap.add_argument("--accuracy", type=float, default=0.0, metavar="PS",
                     help="also compare <T_kin>, <E_pot> of BOUNCE and BAOAB at 1 fs with "
                          "BAOAB at 0.25 fs over PS picoseconds each")
+    ap.add_argument("--accuracy-seed", type=int, default=7,
+                    help="Philox seed of the accuracy runs (one replicate per seed)")
     ap.add_argument("--accuracy-splits", default="",
                     type=lambda t: [tuple(float(v) for v in p.split(",")) for p in t.split(";") if p],
                     metavar="R_ON,R_OFF;...",
