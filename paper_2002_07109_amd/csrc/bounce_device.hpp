@@ -132,23 +132,25 @@ struct PairGlobals {
 template <typename R>
 __device__ __forceinline__ void coul_g(R r, R rinv, R alpha, int coulomb, R &g, R &dg);
 
-// FP32: erfc(x) from the Chebyshev-fitted form of Press et al., Numerical
-// Recipes (2nd ed., sec. 6.2, "erfcc"): erfc(x) = t exp(-x^2 + P(t)), t = 1/(1 + x/2),
-// relative error below 1.2e-7 for x >= 0; exp(-x^2) is shared with g'(r).
-__device__ __forceinline__ float erfc_nr(float x, float e)
+// FP32: erfc(x) = exp(-x^2) Q(t), t = 1 / (1 + 0.4 x), with Q the degree-9
+// polynomial fitted to erfc(x) exp(x^2) on 0 <= x <= 8 (relative error 1.9e-8;
+// about 4e-7 in FP32; paper_2002_07109_amd/fit_erfc.py computes the
+// coefficients).  This returns Q; the caller multiplies by exp(-x^2), which it
+// shares with g'(r).  Beyond x = 8 that product is below 1e-27.
+__device__ __forceinline__ float erfcx_fit(float x)
 {
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);
-    float p = 0.17087277f;
-    p = fmaf(p, t, -0.82215223f);
-    p = fmaf(p, t, 1.48851587f);
-    p = fmaf(p, t, -1.13520398f);
-    p = fmaf(p, t, 0.27886807f);
-    p = fmaf(p, t, -0.18628806f);
-    p = fmaf(p, t, 0.09678418f);
-    p = fmaf(p, t, 0.37409196f);
-    p = fmaf(p, t, 1.00002368f);
-    p = fmaf(p, t, -1.26551223f);
-    return t * e * __expf(p);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, x, 1.0f));
+    float q = 0.020177293568849564f;
+    q = fmaf(q, t, -0.028550047427415848f);
+    q = fmaf(q, t, -0.17227867245674133f);
+    q = fmaf(q, t, 0.4207404553890228f);
+    q = fmaf(q, t, -0.18945305049419403f);
+    q = fmaf(q, t, 0.33385446667671204f);
+    q = fmaf(q, t, 0.15468838810920715f);
+    q = fmaf(q, t, 0.23628339171409607f);
+    q = fmaf(q, t, 0.22447969019412994f);
+    q = fmaf(q, t, 5.809841604786925e-05f);
+    return q;
 }
 
 template <>
@@ -158,8 +160,9 @@ __device__ __forceinline__ void coul_g<float>(float r, float rinv, float alpha, 
     if (coulomb) {
         const float ar = alpha * r;
         const float ex = __expf(-ar * ar);
-        g = erfc_nr(ar, ex) * rinv;
-        dg = -(g + (float)TWO_OVER_SQRTPI * alpha * ex) * rinv;
+        const float q = erfcx_fit(ar);          // erfc(ar) = ex q
+        g = ex * q * rinv;
+        dg = -(ex * fmaf(q, rinv, (float)TWO_OVER_SQRTPI * alpha)) * rinv;
     } else {
         g = rinv;
         dg = -rinv * rinv;
@@ -201,7 +204,7 @@ __device__ __forceinline__ R pair_dw(R r2, const TypePair<R> &tp, R alpha, int c
     R rinv2 = rinv * rinv;
     R s2 = tp.sig2 * rinv2;
     R s6 = s2 * s2 * s2;
-    R dlj = tp.eps4 * ((R)6 * s6 - (R)12 * s6 * s6) * rinv;
+    R dlj = tp.eps4 * (s6 * ((R)6 - (R)12 * s6)) * rinv;
     r_out = r;
     rinv_out = rinv;
     return tp.qq * dg + dlj - tp.du_rc;
@@ -220,7 +223,7 @@ __device__ __forceinline__ void pair_dw_parts(R r2, const TypePair<R> &tp, R alp
     R rinv2 = rinv * rinv;
     R s2 = tp.sig2 * rinv2;
     R s6 = s2 * s2 * s2;
-    R dlj = tp.eps4 * ((R)6 * s6 - (R)12 * s6 * s6) * rinv;
+    R dlj = tp.eps4 * (s6 * ((R)6 - (R)12 * s6)) * rinv;
     r_out = r;
     rinv_out = rinv;
     dwc = tp.qq * dg - tp.pad[1];
@@ -234,6 +237,14 @@ __device__ __forceinline__ R switch_chi(R r, R r_on, R inv_w)
     R x = (r - r_on) * inv_w;
     x = x < (R)0 ? (R)0 : (x > (R)1 ? (R)1 : x);
     return x * x * x * ((R)10 + x * ((R)6 * x - (R)15));
+}
+
+// FP32 (the pair kernels' hot loop): the clamp to [0, 1] as one median of three
+template <>
+__device__ __forceinline__ float switch_chi<float>(float r, float r_on, float inv_w)
+{
+    const float x = __builtin_amdgcn_fmed3f(fmaf(r, inv_w, -r_on * inv_w), 0.0f, 1.0f);
+    return x * x * x * fmaf(x, fmaf(6.0f, x, -15.0f), 10.0f);
 }
 
 // The sorted position mirror stores (x, y, z, w) with w = 16 id + type, an

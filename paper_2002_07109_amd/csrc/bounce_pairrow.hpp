@@ -105,13 +105,35 @@ __device__ __forceinline__ void pair_force_row(const double4 *__restrict__ X, co
     }
 }
 
+// 16-byte gathers from the fixed-point mirror through a buffer resource (CDNA
+// V#: base, no stride, size in bytes; word 3 = 0x00020000, the 32-bit data
+// format of the gfx9 family): a 32-bit byte offset per lane instead of a
+// 64-bit address, and an offset past the end reads zeros instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mirror_rsrc(const int4 *XF, int32_t n)
+{
+    const int64_t bytes = 16 * (int64_t)n;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int4 *>(XF), (short)0,
+                                             (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff), 0x00020000);
+}
+
+__device__ __forceinline__ int4 mirror_load(__amdgpu_buffer_rsrc_t r, int32_t i)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, i * 16, 0, 0);
+    return make_int4((int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]);
+}
+
 // The same sum in FP32 pair arithmetic over the fixed-point position mirror:
 // the displacement is the 32-bit difference of two fixed-point positions
 // (minimum image by two's-complement wrap in a periodic box), exact to their
 // rounding, and is converted to A by one FP32 rounding per axis.  Per entry:
-// the index load, one 16-byte gather, integer and FP32 arithmetic only.
-template <int MODE, int G, bool SPLIT>
-__device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF, const int4 &xi,
+// the index load, one 16-byte gather, integer and FP32 arithmetic only.  An
+// empty slot gathers the atom itself (self), whose zero displacement drops out
+// of the r^2 > 0 test.  NEAR: only the row's near part is walked (cnt = nn),
+// so an entry's slot is its index.  ISO (one mirror unit on all three axes):
+// r^2 is formed in mirror units and scaled once, and the unit goes into the
+// pair scalar instead of into each displacement component.
+template <int MODE, int G, bool SPLIT, bool NEAR, bool ISO>
+__device__ __forceinline__ void pair_force_row_fixed(__amdgpu_buffer_rsrc_t XF, const int4 &xi,
                                                      const float fu[3],
                                                      const int32_t *__restrict__ row, int32_t nn,
                                                      int32_t cnt, int32_t cap, int lig, int32_t self,
@@ -123,43 +145,54 @@ __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF
     const float r_on_v = (float)pg.r_on_v, inv_w_v = (float)pg.inv_w_v;
     const float lim = MODE == MODE_SHORT ? (float)pg.r_short : (float)pg.r_cut;
     const float lim2 = lim * lim;
+    const float fu2 = fu[0] * fu[0], lim2u = lim2 / fu2;
     constexpr int U = 4;
     const int32_t tail = cap - 1 + nn;
     int32_t pn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t e = lig + u * G;
-        pn[u] = e < cap ? row[e] : -1;
+        pn[u] = e < cap ? row[e] : self;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t e = lig + u * G;
-        if (e >= cnt) pn[u] = -1;
-        else if (e >= nn) pn[u] = row[tail - e];
+        if (e >= cnt) pn[u] = self;
+        else if (!NEAR && e >= nn) pn[u] = row[tail - e];
     }
     for (int32_t e0 = lig; e0 < cnt; e0 += U * G) {
-        int32_t pj[U];
         int4 xj[U];
         float px = 0.0f, py = 0.0f, pz = 0.0f;
 #pragma unroll
-        for (int u = 0; u < U; ++u) pj[u] = pn[u];
-#pragma unroll
-        for (int u = 0; u < U; ++u) xj[u] = XF[pj[u] >= 0 ? pj[u] : self];
+        for (int u = 0; u < U; ++u) xj[u] = mirror_load(XF, pn[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t e = e0 + (U + u) * G;
-            pn[u] = e < cnt ? row[row_slot(e, nn, tail)] : -1;
+            pn[u] = e < cnt ? row[NEAR ? e : row_slot(e, nn, tail)] : self;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int32_t dxf = (int32_t)((uint32_t)xi.x - (uint32_t)xj[u].x);
             const int32_t dyf = (int32_t)((uint32_t)xi.y - (uint32_t)xj[u].y);
             const int32_t dzf = (int32_t)((uint32_t)xi.z - (uint32_t)xj[u].z);
-            const float rx = (float)dxf * fu[0], ry = (float)dyf * fu[1], rz = (float)dzf * fu[2];
-            const float r2 = pj[u] >= 0 ? rx * rx + ry * ry + rz * rz : lim2;
-            if (!(r2 < lim2)) continue;
+            float rx, ry, rz, r2;
+            if constexpr (ISO) {
+                rx = (float)dxf;
+                ry = (float)dyf;
+                rz = (float)dzf;
+                const float r2u = rx * rx + ry * ry + rz * rz;
+                if (!(r2u < lim2u && r2u > 0.0f)) continue;
+                r2 = r2u * fu2;
+            } else {
+                rx = (float)dxf * fu[0];
+                ry = (float)dyf * fu[1];
+                rz = (float)dzf * fu[2];
+                r2 = rx * rx + ry * ry + rz * rz;
+                if (!(r2 < lim2 && r2 > 0.0f)) continue;
+            }
             const TypePair<float> &tp = tab_i[xj[u].w];
-            const float f = pair_scalar<float, MODE, SPLIT>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
+            float f = pair_scalar<float, MODE, SPLIT>(r2, tp, pg, alpha, r_on, inv_w, r_on_v, inv_w_v);
+            if constexpr (ISO) f *= fu[0];
             px += f * rx;
             py += f * ry;
             pz += f * rz;
@@ -167,6 +200,28 @@ __device__ __forceinline__ void pair_force_row_fixed(const int4 *__restrict__ XF
         ax += (double)px;
         ay += (double)py;
         az += (double)pz;
+    }
+}
+
+// pair_force_row_fixed with the near-part gate and the unit shape as template
+// arguments
+template <int MODE, int G, bool SPLIT>
+__device__ __forceinline__ void pair_row_fixed_by(bool near_only, bool iso, __amdgpu_buffer_rsrc_t XF,
+                                                  const int4 &xi, const float fu[3],
+                                                  const int32_t *__restrict__ row, int32_t nn, int32_t cnt,
+                                                  int32_t cap, int lig, int32_t self,
+                                                  const TypePair<float> *tab_i, const PairGlobals &pg,
+                                                  double &ax, double &ay, double &az)
+{
+    if (near_only) {
+        if (iso)
+            pair_force_row_fixed<MODE, G, SPLIT, true, true>(XF, xi, fu, row, nn, cnt, cap, lig, self, tab_i, pg, ax, ay, az);
+        else
+            pair_force_row_fixed<MODE, G, SPLIT, true, false>(XF, xi, fu, row, nn, cnt, cap, lig, self, tab_i, pg, ax, ay, az);
+    } else if (iso) {
+        pair_force_row_fixed<MODE, G, SPLIT, false, true>(XF, xi, fu, row, nn, cnt, cap, lig, self, tab_i, pg, ax, ay, az);
+    } else {
+        pair_force_row_fixed<MODE, G, SPLIT, false, false>(XF, xi, fu, row, nn, cnt, cap, lig, self, tab_i, pg, ax, ay, az);
     }
 }
 
@@ -207,14 +262,17 @@ __device__ __forceinline__ void pair_force_atoms(const PairArgs &a, const TypePa
         if constexpr (FIXED) {
             const RepInfo &rp = ONE ? a.reps[0] : a.reps[si.y];
             const float fu[3] = {rp.funit[0], rp.funit[1], rp.funit[2]};
-            const int4 *__restrict__ XF = a.ls.xf[par];
-            const int4 xfi = XF[s];
+            const int4 *__restrict__ XFp = a.ls.xf[par];
+            const int4 xfi = XFp[s];
+            const __amdgpu_buffer_rsrc_t XF = mirror_rsrc(XFp, a.n);
             const TypePair<float> *tf = reinterpret_cast<const TypePair<float> *>(tab) + xfi.w * nt;
-            // the separate-mechanism flag is uniform: one branch outside the loop
+            // the separate-mechanism flag, the near-part gate and the unit
+            // shape are uniform (per launch, per replica): branches outside the loop
+            const bool iso = fu[0] == fu[1] && fu[1] == fu[2];
             if (MODE != MODE_FULL && a.pg.split)
-                pair_force_row_fixed<MODE, G, true>(XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
+                pair_row_fixed_by<MODE, G, true>(near_only, iso, XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
             else
-                pair_force_row_fixed<MODE, G, false>(XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
+                pair_row_fixed_by<MODE, G, false>(near_only, iso, XF, xfi, fu, row, nn, cnt, cap, lig, s, tf, a.pg, ax, ay, az);
         } else {
             const double4 xi = X[s];
             const TypePair<R> *ti = tab + mirror_type(xi.w) * nt;

@@ -77,9 +77,10 @@ __device__ __forceinline__ const TypePair<double> *pair_table<double>(const Pair
 
 // G lanes per atom (4, 8, 16 or 32; chosen by the autotuner).  ONE: a single
 // replica, whose box the force modes keep in scalar registers.  FIXED: the
-// force modes over the fixed-point position mirror (FP32 pair arithmetic).
+// force modes over the fixed-point position mirror (FP32 pair arithmetic); with
+// one replica held to 64 VGPRs: eight wavefronts per SIMD hide the gathers.
 template <typename R, int MODE, int G, bool ONE = false, bool FIXED = false>
-__global__ void __launch_bounds__(256) k_pair(PairArgs a)
+__global__ void __launch_bounds__(256, FIXED && ONE ? 8 : 1) k_pair(PairArgs a)
 {
     __shared__ TypePair<R> tab[MAXT * MAXT];
     __shared__ TypePair<double> tabc[MAXT * MAXT];
