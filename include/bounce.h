@@ -187,7 +187,10 @@ bounce_status bounce_update_params(bounce_ctx *ctx, const bounce_params *params)
 
 /* Topology and force field of all replicas (host arrays, copied).  Computes the
    rate bounds L_ab = (1 + 1e-3) max over a 1e-4 A grid of [r', rc] of |chi W'_sf|
-   (Sec. IV.A).  Must precede bounce_workspace_size. */
+   (Sec. IV.A).  Must precede bounce_workspace_size.  Errors: BOUNCE_E_ARG for
+   inconsistent arrays, a box too small for the list radius, a cell grid too
+   large, or more than 134,217,727 atoms with FP32 pair arithmetic (the pair
+   kernels address the position mirror with 32-bit byte offsets). */
 bounce_status bounce_set_system(bounce_ctx *ctx, const bounce_system *sys);
 /* Device workspace bytes the context needs. */
 bounce_status bounce_workspace_size(const bounce_ctx *ctx, uint64_t *bytes);

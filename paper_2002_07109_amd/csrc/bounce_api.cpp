@@ -497,6 +497,10 @@ bounce_status bounce_set_system(bounce_ctx *c, const bounce_system *s)
     // edge / 2^32 (positions modulo 2^32: the 32-bit difference is the minimum
     // image); droplet, unit grid extent / 2^30 from the grid origin
     c->fixed = c->p.pair_precision == BOUNCE_PAIR_FP32;
+    // the FP32 pair kernels gather the mirror through a buffer resource with
+    // 32-bit byte offsets (16 bytes an atom)
+    if (c->fixed && (int64_t)c->n * 16 > (int64_t)0x7fffffff)
+        return fail(c, BOUNCE_E_ARG, "FP32 pair arithmetic supports at most 134,217,727 atoms");
     for (RepInfo &ri : c->reps)
         for (int k = 0; k < 3; ++k) {
             const double u = ri.periodic ? std::ldexp(ri.box[k], -32)
