@@ -211,8 +211,11 @@ def run_batch(args, ff):
                        % (min(sizes), max(sizes), sum(sizes), args.batch_dt),
            "rebuild_interval": args.batch_rebuild,
            "steps": args.batch_steps}
-    for mode_name, mode in (("atom_bounds", 0), ("pair_bounds", 1)):
-        sim = B.Simulation(systems, mk(B.BJAOAJB, 1e-3, 0, mode), ff["charge"], ff["eps"],
+    # BOUNCE with one bound per atom type and per type pair, and BAOAB at the
+    # same time step for comparison
+    for mode_name, integ, mode in (("atom_bounds", B.BJAOAJB, 0), ("pair_bounds", B.BJAOAJB, 1),
+                                   ("baoab", B.BAOAB, 0)):
+        sim = B.Simulation(systems, mk(integ, 1e-3, 0, mode), ff["charge"], ff["eps"],
                            ff["sigma"])
         sim.set_state(pos=pos, vel=vel, step=0)
         sim.step(50)
@@ -229,27 +232,29 @@ def run_batch(args, ff):
         wall = time.perf_counter() - t0
         c1 = [sim.counters(r) for r in range(len(systems))]
         n = sim.n
-        # the short-range pair kernel's roofline over all droplets: pairs within
-        # r'' counted per droplet (no periodic images, exclusions removed)
+        # the pair kernel's roofline over all droplets: pairs within r'' (BOUNCE)
+        # or rc (BAOAB) counted per droplet (no periodic images, exclusions removed)
+        rlim, fl = (8.0, FLOPS_SHORT) if integ == B.BJAOAJB else (9.0, FLOPS_FULL)
         pair_ms = pair_ms_over_interval(sim, args.batch_rebuild, 4)
         q = sim.pos.cpu().numpy()
         pairs = 0
         for r, s in enumerate(systems):
             b, e = sim.offsets[r], sim.offsets[r + 1]
-            pairs += pair_count_open(q[b:e], 8.0, s.excl.shape[0])
+            pairs += pair_count_open(q[b:e], rlim, s.excl.shape[0])
         sim.close()
-        tflops = pairs * FLOPS_SHORT / (pair_ms * 1e-3) / 1e12
+        tflops = pairs * fl / (pair_ms * 1e-3) / 1e12
         ms = 1e3 * wall / args.batch_steps
         diff = lambda k: (sum(c[k] for c in c1) - sum(c[k] for c in c0)) / args.batch_steps
         out[mode_name] = {"ms_per_step": round(ms, 5), "atom_steps_per_s": n * 1e3 / ms,
                           "proposals_per_step": diff("proposals"),
                           "accepted_per_step": diff("accepted"), "pair_lanes": lanes,
-                          "pair_kernel_us": round(pair_ms * 1e3, 3), "short_pairs": pairs,
+                          "pair_kernel_us": round(pair_ms * 1e3, 3), "pairs_in_range": pairs,
                           "pair_kernel_tflops": round(tflops, 4),
                           "pair_kernel_frac": round(tflops / PEAK_FP32, 5),
                           "launch": "fused" if tuned["persistent"] else "two launches",
                           "dry_step_ms": {k: round(v, 5) for k, v in tuned["step_ms"].items()}}
         log(f"batch {mode_name}: {out[mode_name]}")
+    out["speedup_vs_baoab"] = round(out["baoab"]["ms_per_step"] / out["atom_bounds"]["ms_per_step"], 4)
     return out
 
 
