@@ -236,6 +236,7 @@ __device__ __forceinline__ double cell_gap(int32_t ci, int32_t cj, int32_t n, do
 
 constexpr int LB = 4;          // wavefronts per cell
 constexpr int LCAP = 512;      // candidate atoms staged in LDS per batch
+static_assert(LCAP % 64 == 0, "a wavefront's 64 lanes test whole chunks of the staged batch");
 constexpr int LMAXI = 64;      // atoms per cell handled
 constexpr int LDIM = 12;       // candidate cells per dimension
 constexpr int LCELLS = 352;    // candidate cells kept per cell
@@ -268,7 +269,9 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
     __shared__ double4 ipos[LMAXI];
     __shared__ int32_t iex[LMAXI][LEXCL];
     __shared__ int32_t s_ncells;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // (the wavefront index as a scalar: the row pointers of the atom a wavefront
+    // handles are then scalar too, as the buffer resources of its stores need)
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t nbusy = ls.busy[0];
     for (int32_t idx = blockIdx.x; idx < nbusy; idx += gridDim.x) {
     const int32_t ci = ls.busy[1 + idx];              // uniform per workgroup
@@ -441,39 +444,44 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
             for (int b = 0; b < KC; ++b) nc[b] = rowc[k * KC + b];
             int32_t *frow = ls.flist + (int64_t)i * ls.fcap;
             int32_t *crow = ls.clist + (int64_t)i * ls.ncls * ls.ccap;
+            // the row stores go through buffer resources of this atom's rows
+            // (uniform across the wavefront; word 3 = 0x00020000, the 32-bit
+            // data format of the gfx9 family): 32-bit offsets, and an entry past
+            // a row's capacity is dropped by the hardware's range check (the
+            // counts still take it, and the build reports the overflow)
+            const __amdgpu_buffer_rsrc_t rsf = __builtin_amdgcn_make_buffer_rsrc(frow, (short)0, 4 * ls.fcap, 0x00020000);
+            const __amdgpu_buffer_rsrc_t rsc = __builtin_amdgcn_make_buffer_rsrc(crow, (short)0, 4 * ls.ncls * ls.ccap, 0x00020000);
             for (int32_t f0 = 0; f0 < nb; f0 += 64) {
+                // every lane reads a staged entry (f < LCAP: f0 < nb <= LCAP and
+                // f0 is a multiple of 64, as LCAP is), and a lane past the batch
+                // takes r2 = +inf, which no test below accepts: the predicates are
+                // computed without branches
                 const int32_t f = f0 + lane;
-                bool hf = false, hg = false, hc = false;
-                int32_t j = -1;
-                if (f < nb) {
-                    j = cj[f];
-                    double dx = xi.x - cx[f], dy = xi.y - cy[f], dz = xi.z - cz[f];
-                    box.apply(dx, dy, dz);
-                    const double r2 = norm2_exact(dx, dy, dz);
-                    if (r2 < rmax2) {
-                        bool ex = false;
-                        if (r2 <= exr2) {      // the atom itself or possibly excluded
-                            const int32_t gj = ls.perm[j];
-                            ex = j == i;
+                const int32_t j = cj[f];
+                double dx = xi.x - cx[f], dy = xi.y - cy[f], dz = xi.z - cz[f];
+                box.apply(dx, dy, dz);
+                const double r2 = f < nb ? norm2_exact(dx, dy, dz) : __builtin_huge_val();
+                bool ex = false;
+                if (r2 <= exr2) {      // the atom itself or possibly excluded (never past the batch)
+                    const int32_t gj = ls.perm[j];
+                    ex = j == i;
 #pragma unroll
-                            for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == gj;
-                        }
-                        if (!ex) {
-                            const bool in_f = bs.want_force && r2 < bs.rf2;
-                            hf = in_f && r2 < bs.rfn2;
-                            hg = in_f && !(r2 < bs.rfn2);
-                            hc = bs.want_cand && r2 < bs.rcmax2 && !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
-                        }
-                    }
+                    for (int t = 0; t < LEXCL; ++t) ex |= ex_id[t] == gj;
                 }
+                const bool in = r2 < rmax2 && !ex;
+                const bool in_f = in && bs.want_force && r2 < bs.rf2;
+                const bool hf = in_f && r2 < bs.rfn2;
+                const bool hg = in_f && !(r2 < bs.rfn2);
+                const bool hc = in && bs.want_cand && r2 < bs.rcmax2 && !(bs.rcmin2 > 0.0 && r2 < bs.rcmin2);
                 const uint64_t mf = __ballot(hf), mg = __ballot(hg);
                 if (hf) {      // near: from the front of the row
                     const int32_t q = nf + __popcll(mf & below);
-                    if (q < ls.fcap) frow[q] = j;
+                    __builtin_amdgcn_raw_buffer_store_b32(j, rsf, 4 * q, 0, 0);
                 }
-                if (hg) {      // far: from the back
+                if (hg) {      // far: from the back (past the capacity: a negative
+                               // index, i.e. an offset beyond the range, dropped)
                     const int32_t q = ng + __popcll(mg & below);
-                    if (q < ls.fcap) frow[ls.fcap - 1 - q] = j;
+                    __builtin_amdgcn_raw_buffer_store_b32(j, rsf, 4 * (ls.fcap - 1 - q), 0, 0);
                 }
                 // candidates by class (the partner's type when the rate
                 // bounds are per type pair, else one class), each in candidate order
@@ -485,7 +493,10 @@ __global__ void __launch_bounds__(64 * LB) k_lists(int32_t n_cells, const RepInf
                     const uint64_t mb = __ballot(hb);
                     if (hb) {
                         const int32_t q = nc[b] + __popcll(mb & below);
-                        if (q < ls.ccap) crow[b * ls.ccap + q] = j;
+                        // one class: the range check drops what is past the row;
+                        // several: a class must not spill into the next one
+                        if (KC == 1 || q < ls.ccap)
+                            __builtin_amdgcn_raw_buffer_store_b32(j, rsc, 4 * (b * ls.ccap + q), 0, 0);
                     }
                     nc[b] += __popcll(mb);
                 }

@@ -84,3 +84,23 @@ def test_an_atom_at_rest(orc):
     assert np.abs(sim.pos.cpu().numpy() - o["q"]).max() <= 1e-6
     assert np.abs(sim.vel.cpu().numpy() - o["v"]).max() <= 1e-6
     assert sim.counters()["proposals"] == o["counters"]["proposals"]
+
+
+@pytest.mark.parametrize("integrator", [0, 1], ids=["bounce", "baoab"])
+def test_list_overflow_is_reported(integrator):
+    """A droplet of 1,500 waters squeezed to eight times water's density: its
+    rows outgrow the capacities the build sizes from water's density (below the
+    droplet's size, which caps them).  The stores past a row's end are dropped
+    by the range check of the row's buffer resource, the counts still take
+    them, and the build reports the overflow."""
+    import paper_2002_07109_amd as B
+    from paper_2002_07109_amd._abi import E_CAPACITY
+    s = water_droplet(n_waters=1500, seed=5)
+    c = s.pos.mean(0)
+    pos = c + 0.5 * (s.pos - c)
+    origin, dims = droplet_grid(pos, s.cell_size)
+    s = dataclasses.replace(s, pos=pos, grid_origin=origin, grid_dims=dims)
+    sim = gpu_sim(s, dict(DROPLET, integrator=integrator))
+    with pytest.raises(B.BounceError) as e:
+        sim.profile_kernel(1, 1)
+    assert e.value.status == E_CAPACITY
