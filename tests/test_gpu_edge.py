@@ -86,13 +86,16 @@ def test_an_atom_at_rest(orc):
     assert sim.counters()["proposals"] == o["counters"]["proposals"]
 
 
-@pytest.mark.parametrize("integrator", [0, 1], ids=["bounce", "baoab"])
-def test_list_overflow_is_reported(integrator):
+@pytest.mark.parametrize("integrator,rate_mode", [(0, 0), (1, 0), (0, 1)],
+                         ids=["bounce", "baoab", "bounce_type_pair_bounds"])
+def test_list_overflow_is_reported(integrator, rate_mode):
     """A droplet of 1,500 waters squeezed to eight times water's density: its
     rows outgrow the capacities the build sizes from water's density (below the
     droplet's size, which caps them).  The stores past a row's end are dropped
-    by the range check of the row's buffer resource, the counts still take
-    them, and the build reports the overflow."""
+    by the range check of the row's buffer resource (with per-type-pair bounds,
+    a class's stores past its own capacity are skipped, so that one class does
+    not spill into the next), the counts still take them, and the build
+    reports the overflow; the context then still runs a normal droplet."""
     import paper_2002_07109_amd as B
     from paper_2002_07109_amd._abi import E_CAPACITY
     s = water_droplet(n_waters=1500, seed=5)
@@ -100,7 +103,14 @@ def test_list_overflow_is_reported(integrator):
     pos = c + 0.5 * (s.pos - c)
     origin, dims = droplet_grid(pos, s.cell_size)
     s = dataclasses.replace(s, pos=pos, grid_origin=origin, grid_dims=dims)
-    sim = gpu_sim(s, dict(DROPLET, integrator=integrator))
+    sim = gpu_sim(s, dict(DROPLET, integrator=integrator, rate_mode=rate_mode))
     with pytest.raises(B.BounceError) as e:
         sim.profile_kernel(1, 1)
     assert e.value.status == E_CAPACITY
+    sim.close()
+    # the next context on the device is unaffected
+    ok = gpu_sim(water_droplet(n_waters=100, seed=6), dict(DROPLET, integrator=integrator, rate_mode=rate_mode))
+    ok.step(20)
+    ok.sync()
+    assert np.isfinite(ok.pos.cpu().numpy()).all()
+    ok.close()
