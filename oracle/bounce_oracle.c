@@ -652,32 +652,12 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
         term *= mu / (double)M;
         cdf += term;
     }
-    const uint64_t w_first[4] = {w[0], w[1], w[2], w[3]};
     for (int64_t k = 1; k <= M; ++k) {
-        /* the two words of proposal k: proposal 1 takes words 2 and 3 of the
-           block that gave the count's uniform; proposal 2 of J(m, JB) takes
-           words 0 and 1, that of J(m, JA) words 2 and 3, of the block
-           (m + 1, P2, i, 0) and (m, P2, i, 0) respectively (so that one block
-           serves the two J half-steps between two kicks); proposal k >= 3
-           takes words 0 and 1 of block (step, phase, i, k) */
-        uint64_t wp, wu;
-        if (k == 1) {
-            wp = w_first[2];
-            wu = w_first[3];
-        } else if (k == 2) {
-            const int jb = phase == ORC_PH_JB;
-            draw(p, jb ? step + 1 : step, ORC_PH_P2, i, 0, w);
-            wp = jb ? w[0] : w[2];
-            wu = jb ? w[1] : w[3];
-        } else {
-            draw(p, step, phase, i, (uint64_t)k, w);
-            wp = w[0];
-            wu = w[1];
-        }
+        draw(p, step, phase, i, (uint64_t)k, w);
         /* (mechanism, partner) with probability weight / W: X uniform on
            [0, W), then the class whose weight range holds X and the member
            within it */
-        uint64_t X = orc_umulh(wp, W), lo = 0;
+        uint64_t X = orc_umulh(w[0], W), lo = 0;
         int cls = 0;
         while (X >= lo + (uint64_t)ncl[cls % ncls] * Lqa[cls]) {
             lo += (uint64_t)ncl[cls % ncls] * Lqa[cls];
@@ -686,7 +666,7 @@ static int jump_atom(const orc_params *p, const orc_topology *t, const jump_cons
         const int mech = cls / ncls;
         int32_t j = cls_start[cls % ncls][(X - lo) / Lqa[cls]];
         const double L = (double)Lqa[cls] * unit;   /* this proposal's bound */
-        double u = orc_u01(wu);
+        double u = orc_u01(w[1]);
         double d[3], F[3];
         min_image(p, q + 3 * i, q + 3 * j, d);
         double r = sqrt(norm2(d));

@@ -33,9 +33,8 @@ extern "C" {
 
 enum { ORC_BOUNCE = 0, ORC_BAOAB = 1 };
 enum { ORC_COUL_BARE = 0, ORC_COUL_EWALD = 1 };
-/* random-stream phases (counter word 1 = phase << 32 | atom); P2 holds the
-   second proposals of the closing J of step n - 1 and the opening J of step n */
-enum { ORC_PH_JA = 0, ORC_PH_O = 1, ORC_PH_JB = 2, ORC_PH_P2 = 3 };
+/* random-stream phases (counter word 1 = phase << 32 | atom) */
+enum { ORC_PH_JA = 0, ORC_PH_O = 1, ORC_PH_JB = 2 };
 /* gradient components */
 enum { ORC_G_BONDED = 1, ORC_G_SHORT = 2, ORC_G_LONG = 4, ORC_G_FULL = 8, ORC_G_RECIP = 16 };
 /* rate bounds of the jump mechanisms (Sec. III.D thinning; Sec. V: the bound may

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liborc.so")
 MAXT = 8
 BOUNCE, BAOAB = 0, 1
 COUL_BARE, COUL_EWALD = 0, 1
-PH_JA, PH_O, PH_JB, PH_P2 = 0, 1, 2, 3
+PH_JA, PH_O, PH_JB = 0, 1, 2
 RATE_ATOM, RATE_PAIR = 0, 1
 WEIGHT_BITS = 20
 G_BONDED, G_SHORT, G_LONG, G_FULL, G_RECIP = 1, 2, 4, 8, 16
