@@ -64,3 +64,45 @@ def test_index_draw_is_uniform(orc):
         counts[orc.umulh(w, n)] += 1
     chi2 = ((counts - 1000.0) ** 2 / 1000.0).sum()
     assert stats.chi2.sf(chi2, n - 1) > 1e-4
+
+
+def test_proposal_words_follow_the_layout(orc):
+    """The partner of every logged proposal k comes from word 0 of the Philox
+    block (step, phase, i, k), computed here by numpy's independent Philox
+    (word 0 of block k = 0 is the count's uniform); the member index is
+    umulh64(word, |C_i|).  Five candidates per atom and a mean of two
+    proposals, so that k = 1, 2 and >= 3 all occur, in both half-steps."""
+    KB = 0.0019872041
+    n_groups, nc = 300, 5
+    n = (nc + 1) * n_groups
+    p = orc.make_params(None, charge=[-0.834], eps=[0.0], sigma=[0.0], periodic=False,
+                        coulomb=0, r_on=5.0, r_off=6.0, r_cut=9.0, bound_scale=40.0, dt=1.0,
+                        seed=11, replica=3)
+    dirs = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0]], float)
+    q = np.zeros((n, 3))
+    v = np.zeros((n, 3))
+    row_ptr = np.zeros(n + 1, np.int64)
+    col = []
+    _, L_a = orc.rate_bounds(p)
+    beta = 1.0 / (KB * 300.0)
+    speed = 2.0 / (nc * beta * L_a[0] * 40.0 * 0.5)     # a mean of two proposals
+    for g in range(n_groups):
+        c = (nc + 1) * g
+        q[c] = [200.0 * g, 0.0, 0.0]
+        for m in range(nc):
+            q[c + 1 + m] = q[c] + (6.5 + 0.4 * m) * dirs[m]
+        v[c] = speed * np.array([0.6, -0.64, 0.48])
+        col.extend(range(c + 1, c + 1 + nc))
+    for a in range(n):
+        row_ptr[a + 1] = row_ptr[a] + (nc if a % (nc + 1) == 0 else 0)
+    col = np.array(col, np.int32)
+    topo = orc.Topology(np.zeros(n, np.int32), np.full(n, 15.999))
+    for step, phase in ((4, orc.PH_JA), (4, orc.PH_JB)):
+        out = orc.jump_halfstep(p, topo, q, v, row_ptr, col, step=step, phase=phase, ev_cap=10**5)
+        ev = out["events"]
+        assert (ev["k"] == 1).any() and (ev["k"] == 2).any() and (ev["k"] >= 3).any()
+        for e in ev:
+            i, k = int(e["atom"]), int(e["k"])
+            w = _numpy_block([step, (phase << 32) | i, k, 0], [11, 3])[0]
+            J = (int(w) * nc) >> 64
+            assert int(e["partner"]) == int(col[row_ptr[i] + J]), (step, phase, i, k)
