@@ -77,6 +77,21 @@ struct Event {
 // ---------------------------------------------------------------------------
 struct U4 { uint64_t x, y, z, w; };
 
+// the full 128-bit product a b as (hi, lo) from four 32 x 32 -> 64 products
+// with 64-bit accumulation (each maps to one v_mad_u64_u32); none of the
+// partial sums can overflow 64 bits
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t t = (uint64_t)a0 * b0;
+    const uint64_t u = (uint64_t)a1 * b0 + (t >> 32);
+    const uint64_t v = (uint64_t)a0 * b1 + (uint32_t)u;
+    const uint64_t w = (uint64_t)a1 * b1 + (u >> 32);
+    hi = w + (v >> 32);
+    lo = (v << 32) | (uint32_t)t;
+}
+
 __device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                             uint64_t k0, uint64_t k1)
 {
@@ -85,8 +100,9 @@ __device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) { k0 += W0; k1 += W1; }
-        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128(M0, c0, hi0, lo0);
+        mul128(M1, c2, hi1, lo1);
         uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
     }
