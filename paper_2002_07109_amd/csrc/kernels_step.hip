@@ -189,6 +189,13 @@ __device__ __forceinline__ int32_t poisson_count(const StepArgs &a, uint64_t W, 
     // rounding of this bound and of any faithfully rounded exp), is below the
     // first CDF term, so the inversion stops at M = 0 without evaluating exp
     if (U <= (1.0 - mu) - 0x1p-50) return 0;
+    // e^-mu <= 1 - mu + mu^2/2 and e^-mu (1 + mu) >= 1 - mu^2/2 (mu >= 0): a
+    // uniform above the first bound and below the second, with 2^-45 to spare
+    // on each side (far more than the rounding of these bounds, of exp and of
+    // the CDF's first two terms), lies between the first two CDF terms, so the
+    // inversion stops at M = 1, again without evaluating exp
+    const double h = 0.5 * mu * mu;
+    if (a.max_proposals >= 1 && U > ((1.0 - mu) + h) + 0x1p-45 && U <= (1.0 - h) - 0x1p-45) return 1;
     int32_t M = 0;
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
