@@ -193,9 +193,15 @@ __device__ __forceinline__ int32_t poisson_count(const StepArgs &a, uint64_t W, 
     // uniform above the first bound and below the second, with 2^-45 to spare
     // on each side (far more than the rounding of these bounds, of exp and of
     // the CDF's first two terms), lies between the first two CDF terms, so the
-    // inversion stops at M = 1, again without evaluating exp
-    const double h = 0.5 * mu * mu;
+    // inversion stops at M = 1, again without evaluating exp; likewise M = 2
+    // between e^-mu (1 + mu) <= 1 - mu^2/2 + mu^3/3 and
+    // e^-mu (1 + mu + mu^2/2) >= 1 - mu^3/6 (each difference has a derivative
+    // of one sign for mu >= 0)
+    const double h = 0.5 * mu * mu, c = mu * h;      // mu^2/2, mu^3/2
     if (a.max_proposals >= 1 && U > ((1.0 - mu) + h) + 0x1p-45 && U <= (1.0 - h) - 0x1p-45) return 1;
+    if (a.max_proposals >= 2 && U > ((1.0 - h) + c * (2.0 / 3.0)) + 0x1p-45 &&
+        U <= (1.0 - c * (1.0 / 3.0)) - 0x1p-45)
+        return 2;
     int32_t M = 0;
     double term = exp(-mu), cdf = term;
     while (U > cdf) {
