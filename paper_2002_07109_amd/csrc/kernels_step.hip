@@ -500,6 +500,18 @@ __device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t
         }
     }
     const double U_jb = u01(group_get_u64<LPA>(w.x, 1)), U_ja = u01(group_get_u64<LPA>(w.x, 2));
+    // Box-Muller on the O block (while the entry loads are in flight): lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
+    const uint64_t ow0 = group_get_u64<LPA>(w.x, 0), ow1 = group_get_u64<LPA>(w.y, 0);
+    const uint64_t ow2 = group_get_u64<LPA>(w.z, 0), ow3 = group_get_u64<LPA>(w.w, 0);
+    double gauss;
+    {
+        const double ua = u01(sub >= 2 ? ow2 : ow0), ub = u01(sub >= 2 ? ow3 : ow1);
+        const double rad = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincos(2.0 * M_PI * ub, &sn, &cs);
+        gauss = rad * (sub == 1 ? sn : cs);
+    }
+    const double G0 = group_get<LPA>(gauss, 0), G1 = group_get<LPA>(gauss, 1), G2 = group_get<LPA>(gauss, 2);
     int32_t M_jb = 0, M_est = 0;
     Proposal pp;     // lanes 3, 1: proposals 1, 2 of J(n-1, JB); lanes 2, 0: 1, 2 of J(n, JA)
     pp.F[0] = pp.F[1] = pp.F[2] = 0.0;
@@ -551,18 +563,6 @@ __device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t
     F[0] += fb[0];
     F[1] += fb[1];
     F[2] += fb[2];
-    // Box-Muller on the O block: lane 0 cos, lane 1 sin of (w0, w1); lane 2 cos of (w2, w3)
-    const uint64_t ow0 = group_get_u64<LPA>(w.x, 0), ow1 = group_get_u64<LPA>(w.y, 0);
-    const uint64_t ow2 = group_get_u64<LPA>(w.z, 0), ow3 = group_get_u64<LPA>(w.w, 0);
-    double gauss;
-    {
-        const double ua = u01(sub >= 2 ? ow2 : ow0), ub = u01(sub >= 2 ? ow3 : ow1);
-        const double rad = sqrt(-2.0 * log(ua));
-        double sn, cs;
-        sincos(2.0 * M_PI * ub, &sn, &cs);
-        gauss = rad * (sub == 1 ? sn : cs);
-    }
-    const double G0 = group_get<LPA>(gauss, 0), G1 = group_get<LPA>(gauss, 1), G2 = group_get<LPA>(gauss, 2);
 
     // the atom's chain, on every lane of the group
     if (a.do_close) {
