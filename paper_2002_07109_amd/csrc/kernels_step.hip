@@ -519,6 +519,7 @@ __device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t
     pp.lb = 1.0;
     pp.p = 0;
     pp.mech = 0;
+    bool need = false;
     if (BOUNCE) {
         // both counts at the entry velocity in one evaluation: lanes 0, 1 the
         // count of (n-1, JB), lanes 2, 3 the estimated count of (n, JA)
@@ -533,16 +534,15 @@ __device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t
         if (capped && sub == 1) atomicOr(&a.st->status, ST_POISSON);
         // the first two proposals of each half-step, one per lane; lane 3's
         // block was drawn at entry, the others take one call together
-        const bool need = sub == JB_L1 ? M_jb >= 1
-                        : sub == JB_L2 ? M_jb >= 2
-                        : sub == JA_L1 ? M_est >= 1 : M_est >= 2;
+        need = sub == JB_L1 ? M_jb >= 1
+             : sub == JB_L2 ? M_jb >= 2
+             : sub == JA_L1 ? M_est >= 1 : M_est >= 2;
         U4 pw = w;
         if (need && sub != JB_L1)
             pw = draw(ri, sub == JB_L2 ? n - 1 : n, sub == JB_L2 ? 2 : 0, lid, sub == JA_L1 ? 1 : 2);
-        if (need) {
-            block_proposal<KC>(pw, PT, pp);
-            field_proposal<R>(a, ftab, X, ri, ti, q, pp);
-        }
+        // the partner from the candidate row; its position is read after the
+        // bonded terms, which run while the row entry is in flight
+        if (need) block_proposal<KC>(pw, PT, pp);
     }
     if (active && e0.x >= 0) {
         // bonded terms shared by the lanes: k = sub, sub + LPA, ...
@@ -554,6 +554,7 @@ __device__ __forceinline__ void step_atoms(const StepArgs &a, int32_t t, int32_t
             bonded_slot_grad(s, e, X, ri, a.tp, fb);
         }
     }
+    if (BOUNCE && need) field_proposal<R>(a, ftab, X, ri, ti, q, pp);
 #pragma unroll
     for (int m = 1; m < LPA; m <<= 1) {
         fb[0] += __shfl_xor(fb[0], m, LPA);
